@@ -1,0 +1,462 @@
+"""PBM applied to the dual VTS problem (Section 3.2), written out step by step.
+
+Variables xi = (u, alpha, nu_lo, nu_hi); multipliers (rho, mu_lo, mu_hi);
+penalties (p, q_lo, q_hi).  All displacement-sized vectors live in the
+all-DOF layout with zeros at fixed DOFs; the linear algebra of the reduced
+system runs on the free DOFs plus the scalar alpha (size n+1).
+
+Readings of the paper used here (each also listed in the design doc):
+  * the constant term of res_3 in eq. (3.10) is taken as -rho_lo (the sign
+    that differentiating eq. (3.9) gives; it is printed as +rho_lo);
+  * the mu_lo update of Algorithm 1 uses phi'(-nu_lo/q_lo), as eq. (3.4)
+    and the definition of h_lo prescribe;
+  * the 2x2 per-element inverse of the (nu_lo, nu_hi) block and the Schur
+    complement are evaluated in the closed forms derived below, which are
+    algebraically identical to eq. (3.12) and its inverse formula but avoid
+    the cancellation rho''^2 - rho''^2 when the penalties are small.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import fe
+from .penalty import phi, dphi, d2phi
+
+
+# ----------------------------------------------------------------------------
+# options and state
+# ----------------------------------------------------------------------------
+@dataclass
+class Options:
+    """Parameters of Algorithms 1 and 2.  beta, gamma, p_min, eps_nwt0 and the
+    MINRES rule are the values stated after Algorithm 1 and in Section 6.2.
+    eps_pbm, eps_nwt_min and eps_nwt_final are tighter than the paper's
+    (1e-5..1e-6, 1e-3, 10 eps_pbm) so that the result meets a KKT residual of
+    1e-6; `paper_options()` returns the paper's values."""
+    beta: float = 0.3
+    gamma: float = 0.3
+    p_min: float = 1e-8
+    eps_pbm: float = 1e-8
+    eps_nwt0: float = 1.0
+    eps_nwt_min: float = 1e-5
+    eps_nwt_final: Optional[float] = 5e-7     # None -> 10 * eps_pbm
+    eps_stat: Optional[float] = 5e-7          # None -> gap test only
+    accept_stall: float = 1e-6                # final-Newton stall accepted below this res
+    eps_mr0: Optional[float] = None           # None -> 1e-4 sqrt(n)
+    eps_mr_min: float = 1e-9
+    armijo_c1: float = 1e-4
+    armijo_min: float = 2.0 ** -30
+    max_outer: int = 100
+    max_newton: int = 100
+    max_minres: int = 500
+    final_res4: bool = True                   # final Newton also tests res_4
+
+
+def paper_options(eps_pbm: float = 1e-5) -> "Options":
+    """The parameter values of the paper's experiments (Section 7)."""
+    return Options(eps_pbm=eps_pbm, eps_nwt_min=1e-3, eps_nwt_final=None,
+                   final_res4=False, eps_stat=None, accept_stall=0.0)
+
+
+@dataclass
+class State:
+    u: np.ndarray
+    alpha: float
+    nu_lo: np.ndarray
+    nu_hi: np.ndarray
+    rho: np.ndarray
+    mu_lo: np.ndarray
+    mu_hi: np.ndarray
+    p: np.ndarray
+    q_lo: np.ndarray
+    q_hi: np.ndarray
+
+    def copy(self):
+        return State(self.u.copy(), float(self.alpha), self.nu_lo.copy(),
+                     self.nu_hi.copy(), self.rho.copy(), self.mu_lo.copy(),
+                     self.mu_hi.copy(), self.p.copy(), self.q_lo.copy(),
+                     self.q_hi.copy())
+
+
+def initial_state(n_dof: int, m: int, V: float) -> State:
+    """Initial point stated after Algorithm 1: u = 0, alpha = 1,
+    nu_lo = nu_hi = e, rho_i = V/m, mu_lo = mu_hi = e, p = q = e."""
+    one = np.ones(m)
+    return State(np.zeros(n_dof), 1.0, one.copy(), one.copy(),
+                 np.full(m, V / m), one.copy(), one.copy(), one.copy(),
+                 one.copy(), one.copy())
+
+
+class VTS:
+    """Problem data: grid, K_e, load, volume, bounds (problem (1.1))."""
+
+    def __init__(self, problem):
+        self.pr = problem
+        self.grid = fe.Grid(problem.nx, problem.ny, problem.nz, problem.fixed)
+        self.Ke = fe.element_stiffness(problem.E, problem.nu, problem.h)
+        self.f = self.grid.mask(problem.f)
+        self.V = float(problem.V)
+        m = self.grid.m
+        self.rho_lo = np.broadcast_to(np.asarray(problem.rho_lo, float), (m,)).copy()
+        self.rho_hi = np.broadcast_to(np.asarray(problem.rho_hi, float), (m,)).copy()
+        self.free = self.grid.free
+        self.n = self.free.size
+
+
+# ----------------------------------------------------------------------------
+# evaluation of the augmented Lagrangian, its derivatives, eq. (3.9)-(3.11)
+# ----------------------------------------------------------------------------
+@dataclass
+class Eval:
+    e: np.ndarray
+    be: np.ndarray          # m x 24, b_i = K_i u on element i's DOFs
+    s: np.ndarray
+    t_lo: np.ndarray
+    t_hi: np.ndarray
+    rho1: np.ndarray        # rho'
+    rho2: np.ndarray        # rho''
+    mu_lo1: np.ndarray
+    mu_lo2: np.ndarray
+    mu_hi1: np.ndarray
+    mu_hi2: np.ndarray
+    g1: np.ndarray          # all-DOF, masked
+    g2: float
+    g3: np.ndarray
+    g4: np.ndarray
+
+
+def evaluate(P: VTS, st: State) -> Eval:
+    """Section 3.2: s_i, the weights rho', rho'', mu', mu'' and the gradient
+    (res_1, ..., res_4) of eq. (3.10) with the constant of res_3 = -rho_lo."""
+    g = P.grid
+    e = fe.element_energies(g, P.Ke, st.u)
+    be = fe.element_forces(g, P.Ke, st.u)
+    s = (e - st.alpha + st.nu_lo - st.nu_hi) / st.p
+    t_lo = -st.nu_lo / st.q_lo
+    t_hi = -st.nu_hi / st.q_hi
+    rho1 = st.rho * dphi(s)
+    rho2 = st.rho / st.p * d2phi(s)
+    mu_lo1 = st.mu_lo * dphi(t_lo)
+    mu_lo2 = st.mu_lo / st.q_lo * d2phi(t_lo)
+    mu_hi1 = st.mu_hi * dphi(t_hi)
+    mu_hi2 = st.mu_hi / st.q_hi * d2phi(t_hi)
+    g1 = fe.apply_K(g, P.Ke, rho1, st.u) - P.f
+    g2 = P.V - rho1.sum()
+    g3 = -P.rho_lo + rho1 - mu_lo1
+    g4 = P.rho_hi - rho1 - mu_hi1
+    return Eval(e, be, s, t_lo, t_hi, rho1, rho2, mu_lo1, mu_lo2, mu_hi1,
+                mu_hi2, g1, g2, g3, g4)
+
+
+def lagrangian(P: VTS, st: State) -> float:
+    """Augmented Lagrangian, eq. (3.9)."""
+    e = fe.element_energies(P.grid, P.Ke, st.u)
+    s = (e - st.alpha + st.nu_lo - st.nu_hi) / st.p
+    return (st.alpha * P.V - P.f @ st.u - P.rho_lo @ st.nu_lo + P.rho_hi @ st.nu_hi
+            + np.sum(st.rho * st.p * phi(s))
+            + np.sum(st.mu_lo * st.q_lo * phi(-st.nu_lo / st.q_lo))
+            + np.sum(st.mu_hi * st.q_hi * phi(-st.nu_hi / st.q_hi)))
+
+
+def lagrangian_change(P: VTS, st: State, new: State) -> float:
+    """L(new) - L(st), eq. (3.9), summed term by term so that the difference
+    is not lost to cancellation between two large totals."""
+    e0 = fe.element_energies(P.grid, P.Ke, st.u)
+    e1 = fe.element_energies(P.grid, P.Ke, new.u)
+    s0 = (e0 - st.alpha + st.nu_lo - st.nu_hi) / st.p
+    s1 = (e1 - new.alpha + new.nu_lo - new.nu_hi) / st.p
+    lin = ((new.alpha - st.alpha) * P.V - P.f @ (new.u - st.u)
+           - P.rho_lo @ (new.nu_lo - st.nu_lo) + P.rho_hi @ (new.nu_hi - st.nu_hi))
+    pen = np.sum(st.rho * st.p * (phi(s1) - phi(s0)))
+    pen += np.sum(st.mu_lo * st.q_lo * (phi(-new.nu_lo / st.q_lo) - phi(-st.nu_lo / st.q_lo)))
+    pen += np.sum(st.mu_hi * st.q_hi * (phi(-new.nu_hi / st.q_hi) - phi(-st.nu_hi / st.q_hi)))
+    return float(lin + pen)
+
+
+def res_pbm(P: VTS, ev: Eval) -> float:
+    """Feasibility measure of eq. (3.15): ||res1||/||f|| + |res2|/V +
+    ||res3||/(||rho_lo|| + ||rho_hi||)."""
+    return (np.linalg.norm(ev.g1) / np.linalg.norm(P.f) + abs(ev.g2) / P.V
+            + np.linalg.norm(ev.g3) / (np.linalg.norm(P.rho_lo) + np.linalg.norm(P.rho_hi)))
+
+
+def res4_term(P: VTS, ev: Eval) -> float:
+    return np.linalg.norm(ev.g4) / (np.linalg.norm(P.rho_lo) + np.linalg.norm(P.rho_hi))
+
+
+# ----------------------------------------------------------------------------
+# the reduced Newton system, eqs. (3.11)-(3.14)
+# ----------------------------------------------------------------------------
+def nu_block(ev: Eval):
+    """Per element, the 2x2 block [[H33_ii, H34_ii], [H34_ii, H44_ii]] =
+    [[r''+ml'', -r''], [-r'', r''+mh'']] has determinant
+    det = r''(ml''+mh'') + ml'' mh'' (the r''^2 terms cancel exactly) and
+    inverse (1/det) [[r''+mh'', r''], [r'', r''+ml'']]."""
+    r2, l2, h2 = ev.rho2, ev.mu_lo2, ev.mu_hi2
+    det = r2 * (l2 + h2) + l2 * h2
+    return det
+
+
+def schur_weights(ev: Eval):
+    """Closed form of eq. (3.12).  Element i couples (u, alpha) to its two nu
+    unknowns through c_i [1, -1] with c_i = rho''_i [b_i; -1].  Subtracting
+    c_i [1,-1] A_i^{-1} [1,-1]^T c_i^T = rho''^2 (ml''+mh'')/det c c^T from
+    the rho''_i [b;-1][b;-1]^T part of H leaves weight
+        w_i = rho'' ml'' mh'' / det  ( = 1/(1/rho'' + 1/ml'' + 1/mh'') ),
+    and the right-hand side term H_{y nu} A^{-1} (res3, res4) becomes
+        z_i [b_i; -1],  z_i = rho''(mh'' res3_i - ml'' res4_i)/det."""
+    det = nu_block(ev)
+    w = ev.rho2 * ev.mu_lo2 * ev.mu_hi2 / det
+    z = ev.rho2 * (ev.mu_hi2 * ev.g3 - ev.mu_lo2 * ev.g4) / det
+    return w, z, det
+
+
+def schur_matrix(P: VTS, ev: Eval) -> sp.csr_matrix:
+    """S of eq. (3.12) on (free u, alpha):
+        S = [[K(rho') + B diag(w) B^T, -B w], [-(B w)^T, sum w]]."""
+    g = P.grid
+    w, _, _ = schur_weights(ev)
+    K1 = fe.assemble_K_free(g, P.Ke, ev.rho1)
+    B = fe.element_force_matrix(g, ev.be)
+    Suu = (K1 + B @ sp.diags(w) @ B.T).tocsr()
+    c = -(B @ w)
+    S = sp.bmat([[Suu, sp.csr_matrix(c[:, None])],
+                 [sp.csr_matrix(c[None, :]), sp.csr_matrix([[w.sum()]])]], format="csr")
+    return S
+
+
+def reduced_rhs(P: VTS, ev: Eval) -> np.ndarray:
+    """rhs of eq. (3.13): [-res1 + B z; -res2 - sum z] (free DOFs, alpha)."""
+    _, z, _ = schur_weights(ev)
+    Bz = fe.scatter(P.grid, z[:, None] * ev.be)
+    ru = (-ev.g1 + Bz)[P.free]
+    return np.concatenate([ru, [-ev.g2 - z.sum()]])
+
+
+def schur_apply(P: VTS, ev: Eval, x_free: np.ndarray, beta: float):
+    """y = S [x; beta] without assembling S (used by parity tests)."""
+    g = P.grid
+    w, _, _ = schur_weights(ev)
+    x = np.zeros(g.n_dof)
+    x[P.free] = x_free
+    t = np.einsum("ei,ei->e", ev.be, x[g.dofs]) - beta
+    yu = fe.apply_K(g, P.Ke, ev.rho1, x) + fe.scatter(g, (w * t)[:, None] * ev.be)
+    return yu[P.free], float(-(w * t).sum())
+
+
+def delta_nu(ev: Eval, tau: np.ndarray):
+    """Eq. (3.14): with tau_i = b_i^T du - dalpha,
+        (dnl, dnh) = -A_i^{-1} (res3 + r'' tau, res4 - r'' tau),
+    multiplied out (the r''^2 tau terms cancel exactly)."""
+    r2, l2, h2 = ev.rho2, ev.mu_lo2, ev.mu_hi2
+    det = nu_block(ev)
+    dnl = -((r2 + h2) * ev.g3 + r2 * ev.g4 + r2 * h2 * tau) / det
+    dnh = -(r2 * ev.g3 + (r2 + l2) * ev.g4 - r2 * l2 * tau) / det
+    return dnl, dnh
+
+
+def full_hessian(P: VTS, ev: Eval) -> np.ndarray:
+    """Dense Hessian of eq. (3.11) on (free u, alpha, nu_lo, nu_hi); for tiny
+    grids only (pins the reduction)."""
+    g = P.grid
+    n, m = P.n, g.m
+    B = fe.element_force_matrix(g, ev.be).toarray()          # n x m
+    r1, r2 = ev.rho1, ev.rho2
+    K1 = fe.assemble_K_free(g, P.Ke, r1).toarray()
+    N = n + 1 + 2 * m
+    H = np.zeros((N, N))
+    H[:n, :n] = (B * r2) @ B.T + K1                            # H11
+    H[:n, n] = -(B @ r2)                                       # H12
+    H[:n, n + 1:n + 1 + m] = B * r2                            # H13
+    H[:n, n + 1 + m:] = -(B * r2)                              # H14
+    H[n, n] = r2.sum()                                         # H22
+    H[n, n + 1:n + 1 + m] = -r2                                # H23
+    H[n, n + 1 + m:] = r2                                      # H24
+    idx_l = np.arange(n + 1, n + 1 + m)
+    idx_h = np.arange(n + 1 + m, N)
+    H[idx_l, idx_l] = r2 + ev.mu_lo2                           # H33
+    H[idx_l, idx_h] = -r2                                      # H34
+    H[idx_h, idx_h] = r2 + ev.mu_hi2                           # H44
+    iu = np.triu_indices(N, 1)
+    H[(iu[1], iu[0])] = H[iu]
+    return H
+
+
+def full_gradient(P: VTS, ev: Eval) -> np.ndarray:
+    return np.concatenate([ev.g1[P.free], [ev.g2], ev.g3, ev.g4])
+
+
+def schur_literal(P: VTS, ev: Eval) -> np.ndarray:
+    """S of eq. (3.12) computed literally as H_yy - H_ynu H_nunu^{-1} H_nuy
+    with a dense inverse (tiny grids, well-scaled data only)."""
+    H = full_hessian(P, ev)
+    k = P.n + 1
+    return H[:k, :k] - H[:k, k:] @ np.linalg.solve(H[k:, k:], H[k:, :k])
+
+
+# ----------------------------------------------------------------------------
+# gap and dual objective, eq. (2.6) and the objective of (2.1)
+# ----------------------------------------------------------------------------
+def duality_gap(P: VTS, st: State, e: Optional[np.ndarray] = None) -> float:
+    """delta(u, alpha) of eq. (2.6)."""
+    if e is None:
+        e = fe.element_energies(P.grid, P.Ke, st.u)
+    a = st.alpha - e
+    return float(-0.5 * P.f @ st.u + st.alpha * P.V
+                 - np.sum(np.minimum(P.rho_lo * a, P.rho_hi * a)))
+
+
+def dual_objective(P: VTS, st: State) -> float:
+    """d(u, alpha, nu_lo, nu_hi): objective of problem (2.1)."""
+    return float(st.alpha * P.V - P.f @ st.u - P.rho_lo @ st.nu_lo + P.rho_hi @ st.nu_hi)
+
+
+def update_multipliers(st: State, ev: Eval, beta: float, rho_only=False):
+    """Algorithm 1, multiplier step: rho+ = rho phi'(s), mu_lo+ = mu_lo
+    phi'(-nu_lo/q_lo), mu_hi+ = mu_hi phi'(-nu_hi/q_hi), each clipped into
+    [beta x, x/beta]."""
+    def clip(x, xp):
+        return np.minimum(np.maximum(xp, beta * x), x / beta)
+    rho = clip(st.rho, st.rho * dphi(ev.s))
+    if rho_only:
+        return rho, st.mu_lo, st.mu_hi
+    mu_lo = clip(st.mu_lo, st.mu_lo * dphi(ev.t_lo))
+    mu_hi = clip(st.mu_hi, st.mu_hi * dphi(ev.t_hi))
+    return rho, mu_lo, mu_hi
+
+
+def stationarity(P: VTS, rho: np.ndarray, e: np.ndarray, alpha: float) -> float:
+    """Estimate of the KKT stationarity/box terms for a candidate density:
+    max_i |rho_i - Proj_[lo,hi](rho_i + (e_i - alpha)/alpha)| / hi_i, with e
+    from the current u (an addition to Algorithm 1's gap test, used so that
+    the final density meets a KKT residual target)."""
+    proj = np.clip(rho + (e - alpha) / alpha, P.rho_lo, P.rho_hi)
+    return float(np.max(np.abs(rho - proj) / P.rho_hi))
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 2 (PBM NEWTON) and Algorithm 1 (PBM)
+# ----------------------------------------------------------------------------
+@dataclass
+class Log:
+    newton: list = field(default_factory=list)
+    outer: list = field(default_factory=list)
+
+
+class Solver:
+    """Oracle PBM solver.  `linsolve(S, rhs, eps)` may be replaced (tests use
+    a direct solve); the default is MINRES preconditioned by one V-cycle."""
+
+    def __init__(self, problem, opts: Optional[Options] = None, linsolve=None):
+        from . import mg, minres
+        self.P = VTS(problem)
+        self.opts = opts or Options()
+        self.levels_count = problem.levels
+        self.mg = mg
+        self.minres = minres
+        self._linsolve = linsolve
+        n = self.P.n
+        self.eps_mr = (self.opts.eps_mr0 if self.opts.eps_mr0 is not None
+                       else 1e-4 * math.sqrt(n))
+        self.res_prev = None
+        self.log = Log()
+        self.status = "ok"
+
+    # one linear solve of eq. (3.13)
+    def linsolve(self, ev, S, rhs):
+        if self._linsolve is not None:
+            return self._linsolve(S, rhs, self.eps_mr), 0
+        h = self.mg.Hierarchy(self.P.grid, S, self.levels_count)
+        x, its, _ = self.minres.minres(lambda v: S @ v, rhs, h.vcycle,
+                                       self.eps_mr, self.opts.max_minres)
+        return x, its
+
+    def newton(self, st: State, eps_nwt: float, final=False):
+        """Algorithm 2.  The MINRES tolerance rule of Section 6.2 compares
+        res_PBM of consecutive steps of this call."""
+        P, o = self.P, self.opts
+        ev = evaluate(P, st)
+        self.res_prev = None
+        for it in range(o.max_newton):
+            S = schur_matrix(P, ev)
+            rhs = reduced_rhs(P, ev)
+            tries = 0
+            while True:
+                dy, mr_its = self.linsolve(ev, S, rhs)
+                du = np.zeros(P.grid.n_dof)
+                du[P.free] = dy[:-1]
+                da = float(dy[-1])
+                tau = np.einsum("ei,ei->e", ev.be, du[P.grid.dofs]) - da
+                dnl, dnh = delta_nu(ev, tau)
+                slope = float(ev.g1 @ du + ev.g2 * da + ev.g3 @ dnl + ev.g4 @ dnh)
+                if slope < 0 or tries >= 1 or self._linsolve is not None:
+                    break
+                # a non-descent direction: tighten the MINRES tolerance once
+                self.eps_mr = max(0.1 * self.eps_mr, o.eps_mr_min)
+                tries += 1
+            if slope >= 0:
+                self.status = "nondescent"
+                return st, ev
+            kappa = 1.0
+            while True:
+                new = st.copy()
+                new.u = st.u + kappa * du
+                new.alpha = st.alpha + kappa * da
+                new.nu_lo = st.nu_lo + kappa * dnl
+                new.nu_hi = st.nu_hi + kappa * dnh
+                if lagrangian_change(P, st, new) <= o.armijo_c1 * kappa * slope:
+                    break
+                kappa *= 0.5
+                if kappa < o.armijo_min:
+                    self.status = "linesearch"
+                    return st, ev
+            st = new
+            ev = evaluate(P, st)
+            res = res_pbm(P, ev)
+            r4 = res4_term(P, ev)
+            self.log.newton.append(dict(res=res, res4=r4, kappa=kappa,
+                                        minres=mr_its, eps_mr=self.eps_mr))
+            if self.res_prev is not None and res > 0.9 * self.res_prev:
+                self.eps_mr = max(0.1 * self.eps_mr, o.eps_mr_min)
+            self.res_prev = res
+            crit = res + r4 if (final and o.final_res4) else res
+            if crit < eps_nwt:
+                break
+        return st, ev
+
+    def solve(self, st: Optional[State] = None):
+        P, o = self.P, self.opts
+        if st is None:
+            st = initial_state(P.grid.n_dof, P.grid.m, P.V)
+        eps_nwt = o.eps_nwt0
+        for k in range(o.max_outer):
+            st, ev = self.newton(st, eps_nwt)
+            delta = duality_gap(P, st, ev.e)
+            d = dual_objective(P, st)
+            ratio = abs(delta / d)
+            self.log.outer.append(dict(gap=delta, dual=d, ratio=ratio, eps_nwt=eps_nwt,
+                                       sum_rho=float(st.rho.sum())))
+            rho_n, mul_n, muh_n = update_multipliers(st, ev, o.beta)
+            stat = stationarity(P, rho_n, ev.e, st.alpha) if o.eps_stat else 0.0
+            self.log.outer[-1]["stat"] = stat
+            if self.status != "ok" or (ratio < o.eps_pbm and stat < (o.eps_stat or 1.0)):
+                break
+            st.rho, st.mu_lo, st.mu_hi = rho_n, mul_n, muh_n
+            st.p = np.maximum(o.gamma * st.p, o.p_min)
+            st.q_lo = np.maximum(o.gamma * st.q_lo, o.p_min)
+            st.q_hi = np.maximum(o.gamma * st.q_hi, o.p_min)
+            eps_nwt = max(min(100.0 * ratio, eps_nwt), o.eps_nwt_min)
+        eps_final = o.eps_nwt_final if o.eps_nwt_final is not None else 10.0 * o.eps_pbm
+        if self.status == "ok":
+            st, ev = self.newton(st, eps_final, final=True)
+            if self.status != "ok" and self.log.newton and \
+                    self.log.newton[-1]["res"] < o.accept_stall:
+                self.status = "ok"          # near-optimal stall accepted
+        st.rho, _, _ = update_multipliers(st, ev, o.beta, rho_only=True)
+        self.state = st
+        return st

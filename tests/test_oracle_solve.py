@@ -1,0 +1,96 @@
+"""End-to-end pins of the oracle PBM solver (Algorithms 1 and 2) against
+results fixed by the mathematics: brute force, a case with a closed-form
+optimum, weak duality (Theorem 2) and invariances of problem (1.1)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import pbm, kkt, fe
+
+
+def _solve(pr, **kw):
+    s = pbm.Solver(pr, pbm.Options(**kw))
+    st = s.solve()
+    assert s.status == "ok"
+    return s, st
+
+
+def _check(s, st):
+    P = s.P
+    return kkt.kkt_residual(P.grid, P.Ke, P.f, P.V, P.rho_lo, P.rho_hi, st.rho, st.u, st.alpha)
+
+
+def test_two_element_brute_force():
+    # m = 2: c(r, V - r) is convex in r; golden section to 1e-12
+    pr = W.cantilever_edge(2, 1, 1, 1, vol_frac=0.6)
+    s, st = _solve(pr)
+    P = s.P
+    lo = max(P.rho_lo[0], P.V - P.rho_hi[1])
+    hi = min(P.rho_hi[0], P.V - P.rho_lo[1])
+    c = lambda r: kkt.compliance(P.grid, P.Ke, np.array([r, P.V - r]), P.f)
+    g = (math.sqrt(5) - 1) / 2
+    a, b = lo, hi
+    for _ in range(200):
+        x1, x2 = b - g * (b - a), a + g * (b - a)
+        if c(x1) < c(x2):
+            b = x2
+        else:
+            a = x1
+    cstar = c(0.5 * (a + b))
+    assert abs(kkt.compliance(P.grid, P.Ke, st.rho, P.f) - cstar) < 1e-7 * cstar
+    assert abs(st.rho[0] - 0.5 * (a + b)) < 1e-5
+
+
+def test_uniform_strain_bar_has_uniform_optimum():
+    pr = W.bar_rollers(4, 2, 2, 2, vol_frac=0.5)
+    s, st = _solve(pr)
+    P = s.P
+    assert np.max(np.abs(st.rho - P.V / P.grid.m)) < 1e-6
+    c_uni = kkt.compliance(P.grid, P.Ke, np.full(P.grid.m, P.V / P.grid.m), P.f)
+    assert abs(0.5 * P.f @ st.u - c_uni) < 1e-7 * c_uni
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return _solve(W.config(0))
+
+
+def test_config0_kkt_and_duality_certificate(c1):
+    s, st = c1
+    r = _check(s, st)
+    assert r["kkt"] <= 1e-6, r
+    P = s.P
+    lb, ub, rel = kkt.certificate(P.grid, P.Ke, P.f, P.V, P.rho_lo, P.rho_hi, st.rho, st.u)
+    assert rel <= 1e-7
+    c = kkt.compliance(P.grid, P.Ke, st.rho, P.f)
+    # rho itself is feasible only to the KKT tolerance: its compliance sits
+    # within that tolerance of the bracket
+    assert lb * (1 - 1e-6) <= c <= ub * (1 + 1e-6)
+    # Section 7.1: the PBM volume is met from above within one permille
+    assert 0 <= st.rho.sum() - P.V <= 1e-3 * P.V
+
+
+def test_config0_mirror_symmetry(c1):
+    s, st = c1
+    g = s.P.grid
+    r = st.rho.reshape(g.nz, g.ny, g.nx)
+    assert np.max(np.abs(r - r[:, ::-1, :])) < 1e-5
+
+
+def test_load_scaling_invariance(c1):
+    s, st = c1
+    pr = W.config(0)
+    pr.f = 2.0 * pr.f
+    s2, st2 = _solve(pr)
+    c1v = kkt.compliance(s.P.grid, s.P.Ke, st.rho, s.P.f)
+    c2v = kkt.compliance(s2.P.grid, s2.P.Ke, st2.rho, s2.P.f)
+    assert abs(c2v - 4 * c1v) < 1e-6 * c2v
+    assert np.max(np.abs(st.rho - st2.rho)) < 1e-4
+
+
+def test_bridge_small_kkt():
+    pr = W.bridge_top(8, 4, 4, 2, vol_frac=0.15)
+    s, st = _solve(pr)
+    assert _check(s, st)["kkt"] <= 1e-6
