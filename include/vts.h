@@ -1,0 +1,239 @@
+/*
+ * vts.h -- C ABI of libvts: the PBM method with multigrid-preconditioned
+ * MINRES for the 3D variable thickness sheet (VTS) problem on one MI355X
+ * (gfx950) GPU.
+ *
+ * Method: A. Brune, M. Kocvara, "On barrier and modified barrier multigrid
+ * methods for 3d topology optimization" (arXiv 1904.06556).
+ *   problem (1.1)        min 1/2 f^T u  s.t.  K(rho) u = f, sum rho = V,
+ *                        rho_lo <= rho <= rho_hi,  K(rho) = sum_i rho_i K_i
+ *   problem (2.1)        its dual, to which PBM is applied
+ *   eq. (3.9)            augmented Lagrangian; eq. (3.10) its gradient
+ *   eq. (3.12)-(3.14)    Schur complement S, reduced Newton system, Delta nu
+ *   Algorithm 1 / 2      PBM outer loop / PBM Newton method
+ *   Section 6            V-cycle multigrid preconditioned MINRES
+ *
+ * Conventions (apply to every entry point):
+ *   - Grid: nx x ny x nz unit cubes of side h (finest level); nodes
+ *     (nx+1)(ny+1)(nz+1) numbered i + (nx+1)(j + (ny+1)k), x fastest;
+ *     displacement DOF c of node p is 3p + c ("all-DOF layout", length
+ *     n_dof = 3 * nodes).  Elements numbered i + nx(j + ny k).
+ *   - Fixed (Dirichlet) DOFs are held at zero; every vector this library
+ *     writes is zero there and every vector it reads is masked on read.
+ *   - "S-vector": length n_dof + 1, the all-DOF displacement part followed
+ *     by the scalar alpha (the extra unknown of eq. (3.13)).
+ *   - Pointers named *_dev are device pointers on the device that was
+ *     current at vts_create; *_host are host pointers.  The caller owns
+ *     every buffer it passes; no pointer is retained after a call returns.
+ *   - All device work is issued on the stream given to vts_create, in
+ *     stream order.  Calls that return host statistics synchronize it.
+ *   - No call throws; failures return a vts_status and vts_last_error()
+ *     gives a message.  A context is not thread-safe.
+ */
+#ifndef VTS_H
+#define VTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vts_ctx vts_ctx;
+
+typedef enum {
+    VTS_OK = 0,
+    VTS_EINVAL = 1,       /* invalid argument or problem data (e.g. not strictly feasible) */
+    VTS_ENOMEM = 2,       /* device allocation failed */
+    VTS_EDEVICE = 3,      /* a HIP runtime call failed */
+    VTS_ESTATE = 4,       /* call out of order (e.g. apply_S before newton_setup) */
+    VTS_ENOTCONV = 5,     /* iteration limit reached */
+    VTS_ENONDESCENT = 6,  /* Newton direction not a descent direction / line search stalled */
+    VTS_ENONSPD = 7       /* preconditioner or coarse matrix not positive definite */
+} vts_status;
+
+typedef enum {
+    VTS_FP64 = 0,         /* everything in FP64 */
+    VTS_MIXED = 1         /* multigrid preconditioner in FP32, everything else FP64 */
+} vts_precision;
+
+/* Problem (1.1) on a structured grid.  Section 7: the design domain is a
+ * coarse box refined levels-1 times, so nx, ny, nz must be divisible by
+ * 2^(levels-1).  All pointers are host pointers, copied by vts_create.
+ * rho_lo/rho_hi may be NULL, in which case the scalars are used for every
+ * element.  Requirements (the assumptions after (1.1)): rho_hi > rho_lo,
+ * sum rho_lo < V < sum rho_hi, at least one fixed DOF, and fixed DOFs
+ * nested across levels (a fixed fine DOF interpolates from fixed coarse
+ * DOFs only; holds for clamped faces and fixed corner nodes).  Violations
+ * give VTS_EINVAL. */
+typedef struct {
+    int32_t nx, ny, nz, levels;
+    double E, nu, h;
+    const uint8_t* fixed_host;    /* n_dof entries, 1 = fixed */
+    const double* f_host;         /* n_dof entries, load vector */
+    double V;
+    const double* rho_lo_host;    /* m entries or NULL */
+    const double* rho_hi_host;    /* m entries or NULL */
+    double rho_lo_s, rho_hi_s;
+    int32_t precision;            /* vts_precision */
+} vts_problem;
+
+/* Parameters of Algorithms 1 and 2 and of the MINRES rule of Section 6.2.
+ * vts_default_options() fills the values used by this library (the paper's
+ * beta = gamma = 0.3, p_min = 1e-8, eps_NWT = 1, eps_MR rule; tighter
+ * eps_PBM = 1e-8, eps_NWT_min = 1e-5, final eps_NWT = 5e-7 and a
+ * stationarity test so that results meet a KKT residual of 1e-6). */
+typedef struct {
+    double beta, gamma, p_min;
+    double eps_pbm, eps_nwt0, eps_nwt_min, eps_nwt_final;
+    double eps_stat;              /* <= 0: outer loop stops on the gap test alone */
+    double accept_stall;          /* final-Newton stall accepted if res_PBM below this */
+    double eps_mr0;               /* <= 0: 1e-4 sqrt(n) (Section 6.2) */
+    double eps_mr_min;            /* floor of the MINRES tolerance (1e-9) */
+    double armijo_c1, armijo_min; /* Armijo constant and smallest step */
+    int32_t max_outer, max_newton, max_minres;
+    int32_t final_res4;           /* final Newton also requires the res_4 term */
+} vts_options;
+
+typedef struct {
+    int32_t iterations;
+    double rel_residual;          /* phi_bar / beta_1 of preconditioned MINRES */
+} vts_linstats;
+
+typedef struct {
+    double res_pbm;               /* eq. (3.15) at the new point */
+    double res4;                  /* ||res_4|| / (||rho_lo|| + ||rho_hi||) */
+    double kappa;                 /* accepted Armijo step */
+    double slope;                 /* grad L^T Delta xi */
+    double eps_mr;                /* MINRES tolerance used */
+    int32_t minres_its;
+} vts_newtonstats;
+
+typedef struct {
+    double gap, dual, ratio;      /* delta (2.6), dual objective of (2.1), |delta/d| */
+    double stat;                  /* stationarity estimate of the candidate rho */
+    double eps_nwt, sum_rho;
+    int32_t newton_its, minres_its;
+    int32_t converged;            /* 1 when Algorithm 1's stopping test holds */
+} vts_pbmstats;
+
+typedef struct {
+    double compliance;            /* 1/2 f^T u at the returned state */
+    double alpha, sum_rho;
+    double res_pbm;
+    int32_t outer, newton, minres;
+    int32_t status;               /* vts_status of the run */
+} vts_result;
+
+/* Which internal vector vts_get_vector copies (device to device). */
+typedef enum {
+    VTS_VEC_U = 0,        /* displacement u, n_dof */
+    VTS_VEC_RHO = 1,      /* element multipliers rho (densities), m */
+    VTS_VEC_ENERGY = 2,   /* e_i = 1/2 u^T K_i u at the current state, m */
+    VTS_VEC_RHS = 3,      /* reduced right-hand side of eq. (3.13), S-vector */
+    VTS_VEC_DY = 4,       /* last Newton direction (Delta u, Delta alpha), S-vector */
+    VTS_VEC_G1 = 5,       /* res_1 = K(rho')u - f, n_dof */
+    VTS_VEC_DNU_LO = 6,   /* last Delta nu_lo, m */
+    VTS_VEC_DNU_HI = 7,   /* last Delta nu_hi, m */
+    VTS_VEC_RHO1 = 8,     /* rho' = rho phi'(s), m */
+    VTS_VEC_W = 9         /* Schur weight w = (1/rho'' + 1/mu_lo'' + 1/mu_hi'')^-1, m */
+} vts_vector;
+
+/* Fills *opt with this library's defaults. */
+void vts_default_options(vts_options* opt);
+
+/* Creates a context holding all device state of one problem: the problem
+ * data, the PBM state initialized as stated after Algorithm 1 (u = 0,
+ * alpha = 1, nu = e, rho = V/m, mu = e, p = q = e), and the multigrid
+ * hierarchy storage.  stream: a hipStream_t (NULL = default stream).
+ * opt may be NULL (defaults).  On failure *out is NULL. */
+vts_status vts_create(const vts_problem* pr, const vts_options* opt, void* stream,
+                      vts_ctx** out);
+void vts_destroy(vts_ctx* ctx);
+
+/* Device bytes vts_create would allocate for this problem (for admission). */
+size_t vts_footprint_bytes(const vts_problem* pr, const vts_options* opt);
+
+/* Sizes of this context: n_dof, m, number of free DOFs n, levels. */
+vts_status vts_sizes(const vts_ctx* ctx, int64_t* n_dof, int64_t* m, int64_t* n_free,
+                     int32_t* levels);
+
+/* Sets the element multipliers rho (= densities), m FP64 values on device. */
+vts_status vts_set_rho(vts_ctx* ctx, const double* rho_dev);
+
+/* y = K(rho) x with the current rho, problem (1.1): K(rho) = sum rho_i K_i,
+ * K_i the Q1 element stiffness of Section 6.2 scattered to element i's DOFs.
+ * x_dev, y_dev: n_dof FP64 (all-DOF layout); fixed DOFs masked on read and
+ * written as 0.  x and y must not overlap. */
+vts_status vts_apply_K(vts_ctx* ctx, const double* x_dev, double* y_dev);
+
+/* The same operator in FP32 (the precision of the mixed-mode multigrid):
+ * x_dev, y_dev n_dof floats; rho taken from the FP64 rho rounded to FP32. */
+vts_status vts_apply_K_f32(vts_ctx* ctx, const float* x_dev, float* y_dev);
+
+/* e_i = 1/2 u_e^T K_e u_e for all elements (the constraint of (2.1)).
+ * u_dev: n_dof FP64; e_dev: m FP64. */
+vts_status vts_element_energy(vts_ctx* ctx, const double* u_dev, double* e_dev);
+
+/* Algorithm 2, step "compute matrix S and the right-hand side" at the
+ * current state: element energies, the weights rho', rho'', mu', mu'' of
+ * Section 3.2, the gradient (3.10) (res_3 with constant -rho_lo), the
+ * reduced right-hand side of (3.13) and the multigrid hierarchy of S
+ * (Galerkin coarse operators, Section 6.1). */
+vts_status vts_newton_setup(vts_ctx* ctx);
+
+/* y = S [x; beta] with S of eq. (3.12) at the state of the last
+ * vts_newton_setup:  y_u = K(rho')x + sum_i w_i b_i (b_i^T x - beta),
+ * y_alpha = -sum_i w_i (b_i^T x - beta), b_i = K_i u.  x_dev, y_dev:
+ * S-vectors (FP64).  VTS_ESTATE before the first vts_newton_setup. */
+vts_status vts_apply_S(vts_ctx* ctx, const double* x_dev, double* y_dev);
+
+/* z = M^{-1} r: one V-cycle (Section 6.1) on the hierarchy of the last
+ * vts_newton_setup, in FP64 or FP32 per the problem's precision.
+ * r_dev, z_dev: S-vectors (FP64); may not overlap. */
+vts_status vts_precondition(vts_ctx* ctx, const double* r_dev, double* z_dev);
+
+/* Solves S dy = rhs (3.13) by MINRES preconditioned with one V-cycle,
+ * stopping when phi_bar <= eps_mr * beta_1 (eq. (6.2) in the
+ * preconditioner norm) or after max_minres iterations.  The direction is
+ * kept in the context (VTS_VEC_DY).  stats may be NULL. */
+vts_status vts_solve_newton(vts_ctx* ctx, double eps_mr, vts_linstats* stats);
+
+/* One iteration of Algorithm 2: setup (if not current), MINRES solve with
+ * the context's eps_MR, Delta nu (3.14), Armijo backtracking on (3.9),
+ * update of (u, alpha, nu), res_PBM (3.15) and the eps_MR rule of
+ * Section 6.2.  Returns VTS_ENONDESCENT if no descent step was found. */
+vts_status vts_newton_step(vts_ctx* ctx, vts_newtonstats* stats);
+
+/* Runs Algorithm 2 to tolerance eps_nwt. */
+vts_status vts_newton(vts_ctx* ctx, double eps_nwt, int32_t final_call,
+                      vts_newtonstats* last);
+
+/* One pass of the body of Algorithm 1: Newton to the current eps_NWT, the
+ * gap (2.6) and dual objective, the stopping test; if not converged the
+ * multiplier update with the beta safeguard, the penalty update and the
+ * eps_NWT update. */
+vts_status vts_pbm_iterate(vts_ctx* ctx, vts_pbmstats* stats);
+
+/* Algorithm 1 to convergence, followed by the final Newton call and the
+ * last update of rho. */
+vts_status vts_pbm_solve(vts_ctx* ctx, vts_result* result);
+
+/* Copies an internal vector (see vts_vector) to dst_dev (device). */
+vts_status vts_get_vector(const vts_ctx* ctx, int32_t which, double* dst_dev);
+
+/* Checkpoint of the PBM state to host memory, layout (FP64):
+ *   u[n_dof], alpha, nu_lo[m], nu_hi[m], rho[m], mu_lo[m], mu_hi[m],
+ *   p[m], q_lo[m], q_hi[m], eps_nwt, eps_mr
+ * *bytes: in = capacity of host_buf (or 0 to query), out = size needed. */
+vts_status vts_get_state(const vts_ctx* ctx, void* host_buf, size_t* bytes);
+vts_status vts_set_state(vts_ctx* ctx, const void* host_buf, size_t bytes);
+
+/* Message of the last failure on this context (static storage of ctx). */
+const char* vts_last_error(const vts_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VTS_H */

@@ -454,8 +454,8 @@ class Solver:
         eps_final = o.eps_nwt_final if o.eps_nwt_final is not None else 10.0 * o.eps_pbm
         if self.status == "ok":
             st, ev = self.newton(st, eps_final, final=True)
-            if self.status != "ok" and self.log.newton and \
-                    self.log.newton[-1]["res"] < o.accept_stall:
+            if self.status != "ok" and self.res_prev is not None and \
+                    self.res_prev < o.accept_stall:
                 self.status = "ok"          # near-optimal stall accepted
         st.rho, _, _ = update_multipliers(st, ev, o.beta, rho_only=True)
         self.state = st

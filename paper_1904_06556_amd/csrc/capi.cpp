@@ -1,0 +1,908 @@
+// C ABI of libvts: problem validation, device allocation, and the host-side
+// control flow of Algorithm 1 (PBM), Algorithm 2 (PBM NEWTON) and MINRES.
+// Every per-element and per-DOF step runs in the kernels of kernels.hip and
+// mg.hip; the host only reads the scalars that decide the next branch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "vts_internal.hpp"
+
+using namespace vts;
+
+struct vts_ctx : public Ctx {};
+
+namespace {
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            c.err = std::string(#expr) + ": " + hipGetErrorString(e_);                 \
+            return VTS_EDEVICE;                                                        \
+        }                                                                              \
+    } while (0)
+
+struct Dims {
+    int nx, ny, nz;
+};
+
+int64_t nodes_of(const Dims& d) { return (int64_t)(d.nx + 1) * (d.ny + 1) * (d.nz + 1); }
+
+// sizes of every device allocation of a problem (bytes), in allocation order
+struct Plan {
+    std::vector<size_t> bytes;
+    size_t total() const {
+        size_t s = 0;
+        for (size_t b : bytes) s += (b + 255) / 256 * 256;
+        return s;
+    }
+};
+
+vts_status validate(const vts_problem* pr, std::string& err) {
+    if (!pr) { err = "null problem"; return VTS_EINVAL; }
+    if (pr->nx < 1 || pr->ny < 1 || pr->nz < 1 || pr->levels < 1 || pr->levels > 12) {
+        err = "grid dimensions and levels must be positive";
+        return VTS_EINVAL;
+    }
+    const int s = 1 << (pr->levels - 1);
+    if (pr->nx % s || pr->ny % s || pr->nz % s) {
+        err = "nx, ny, nz must be divisible by 2^(levels-1)";
+        return VTS_EINVAL;
+    }
+    if (!pr->fixed_host || !pr->f_host) { err = "fixed and f are required"; return VTS_EINVAL; }
+    if (!(pr->E > 0) || !(pr->nu > -1.0 && pr->nu < 0.5) || !(pr->h > 0)) {
+        err = "material constants out of range";
+        return VTS_EINVAL;
+    }
+    if (pr->precision != VTS_FP64 && pr->precision != VTS_MIXED) {
+        err = "unknown precision";
+        return VTS_EINVAL;
+    }
+    return VTS_OK;
+}
+
+template <typename T>
+void fill_level_geom(Level<T>& L, const Dims& d) {
+    L.nx = d.nx; L.ny = d.ny; L.nz = d.nz;
+    L.NX = d.nx + 1; L.NY = d.ny + 1; L.NZ = d.nz + 1;
+    L.nn = nodes_of(d);
+    L.m = (int64_t)d.nx * d.ny * d.nz;
+    L.coff[0] = 0;
+    for (int col = 0; col < 8; ++col) {
+        const int px = col & 1, py = (col >> 1) & 1, pz = col >> 2;
+        L.cnx[col] = (L.NX - px + 1) / 2;
+        L.cny[col] = (L.NY - py + 1) / 2;
+        L.cnz[col] = (L.NZ - pz + 1) / 2;
+        L.coff[col + 1] = L.coff[col] + (int64_t)L.cnx[col] * L.cny[col] * L.cnz[col];
+    }
+}
+
+// coarse mask by injection: coarse DOF fixed iff the coincident fine DOF is
+std::vector<uint8_t> coarsen_mask(const std::vector<uint8_t>& fm, const Dims& f) {
+    const Dims c{f.nx / 2, f.ny / 2, f.nz / 2};
+    std::vector<uint8_t> cm(3 * nodes_of(c));
+    const int64_t FX = f.nx + 1, FY = f.ny + 1, CX = c.nx + 1, CY = c.ny + 1;
+    for (int K = 0; K <= c.nz; ++K)
+        for (int J = 0; J <= c.ny; ++J)
+            for (int I = 0; I <= c.nx; ++I) {
+                const int64_t N = I + CX * (J + CY * K);
+                const int64_t n = 2 * I + FX * (2 * J + FY * 2 * K);
+                for (int q = 0; q < 3; ++q) cm[3 * N + q] = fm[3 * n + q];
+            }
+    return cm;
+}
+
+// every fixed fine DOF must interpolate from fixed coarse DOFs only
+bool nested(const std::vector<uint8_t>& fm, const Dims& f, const std::vector<uint8_t>& cm) {
+    const int64_t FX = f.nx + 1, FY = f.ny + 1, CX = f.nx / 2 + 1, CY = f.ny / 2 + 1;
+    for (int k = 0; k <= f.nz; ++k)
+        for (int j = 0; j <= f.ny; ++j)
+            for (int i = 0; i <= f.nx; ++i) {
+                const int64_t n = i + FX * (j + FY * k);
+                for (int q = 0; q < 3; ++q) {
+                    if (!fm[3 * n + q]) continue;
+                    const int is[2] = {i >> 1, (i + 1) >> 1}, js[2] = {j >> 1, (j + 1) >> 1},
+                              ks[2] = {k >> 1, (k + 1) >> 1};
+                    for (int a = 0; a < 2; ++a)
+                        for (int b = 0; b < 2; ++b)
+                            for (int cc = 0; cc < 2; ++cc) {
+                                const int64_t N = is[a] + CX * (js[b] + CY * ks[cc]);
+                                if (!cm[3 * N + q]) return false;
+                            }
+                }
+            }
+    return true;
+}
+
+Plan make_plan(const vts_problem* pr) {
+    Plan p;
+    const Dims d{pr->nx, pr->ny, pr->nz};
+    const int64_t nn = nodes_of(d), ndof = 3 * nn, m = (int64_t)d.nx * d.ny * d.nz;
+    auto add = [&](size_t b) { p.bytes.push_back(b); };
+    add(576 * 8); add(576 * 4); add(8 * 576 * 8); add(512 * 8);     // Ke, Kef, Mc, Qc
+    add(ndof); add(ndof * 8);                                        // fixed, f
+    add(m * 8); add(m * 8);                                          // bounds
+    add(ndof * 8);                                                   // u
+    for (int q = 0; q < 8; ++q) add(m * 8);                          // nlo..qhi
+    add(m * 4);                                                      // rhof
+    add(m * 8); add(24 * m * 8);                                     // e, be
+    for (int q = 0; q < 8; ++q) add(m * 8);                          // r1 r2 l2 h2 g3 g4 w zc
+    add(24 * m * 8);                                                 // gch
+    add(ndof * 8); add((ndof + 1) * 8); add((ndof + 1) * 8);         // g1 rhs dy
+    for (int q = 0; q < 5; ++q) add(m * 8);                          // dnl dnh c1 c2 wt
+    for (int q = 0; q < 8; ++q) add((ndof + 1) * 8);                 // MINRES
+    add(kRedSlots * kRedBlocks * 8); add(kRedSlots * 8);             // partials, red
+    const size_t ts = pr->precision == VTS_MIXED ? 4 : 8;
+    Dims dl = d;
+    for (int k = pr->levels - 1; k >= 0; --k) {
+        const int64_t lnn = nodes_of(dl), lm = (int64_t)dl.nx * dl.ny * dl.nz;
+        add(3 * lnn);                                                // fixed
+        add(kStencilVals * lnn * ts); add(9 * lnn * ts); add(3 * lnn * ts);
+        if (k < pr->levels - 1) {
+            add(576 * lm * ts);                                      // E
+            if (k > 0) add(576 * lm * ts);                           // TQ (levels with a parent)
+        }
+        for (int q = 0; q < 3; ++q) add((3 * lnn + 1) * ts);         // r z res
+        dl = Dims{dl.nx / 2, dl.ny / 2, dl.nz / 2};
+    }
+    return p;
+}
+
+template <typename T>
+vts_status alloc_t(Ctx& c, T** ptr, int64_t count) {
+    void* q = nullptr;
+    const size_t b = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    if (hipMalloc(&q, b) != hipSuccess) {
+        c.err = "hipMalloc failed (" + std::to_string(b) + " bytes)";
+        return VTS_ENOMEM;
+    }
+    c.allocs.push_back(q);
+    *ptr = (T*)q;
+    return VTS_OK;
+}
+
+#define ALLOC(ptr, count)                                  \
+    do {                                                   \
+        vts_status s_ = alloc_t(c, &(ptr), (count));       \
+        if (s_ != VTS_OK) return s_;                       \
+    } while (0)
+
+template <typename T>
+vts_status build_hierarchy(Ctx& c, Hierarchy<T>& H, const std::vector<uint8_t>& fine_mask) {
+    const int L = c.L;
+    H.lev.resize(L);
+    std::vector<std::vector<uint8_t>> masks(L);
+    std::vector<Dims> dims(L);
+    masks[L - 1] = fine_mask;
+    dims[L - 1] = Dims{c.nx, c.ny, c.nz};
+    for (int k = L - 2; k >= 0; --k) {
+        dims[k] = Dims{dims[k + 1].nx / 2, dims[k + 1].ny / 2, dims[k + 1].nz / 2};
+        masks[k] = coarsen_mask(masks[k + 1], dims[k + 1]);
+        if (!nested(masks[k + 1], dims[k + 1], masks[k])) {
+            c.err = "fixed DOFs are not nested across multigrid levels";
+            return VTS_EINVAL;
+        }
+    }
+    for (int k = 0; k < L; ++k) {
+        Level<T>& Lk = H.lev[k];
+        std::memset(&Lk, 0, sizeof(Lk));
+        fill_level_geom(Lk, dims[k]);
+        ALLOC(Lk.fixed, 3 * Lk.nn);
+        HIPCHK(hipMemcpy(Lk.fixed, masks[k].data(), 3 * Lk.nn, hipMemcpyHostToDevice));
+        ALLOC(Lk.st, (int64_t)kStencilVals * Lk.nn);
+        ALLOC(Lk.dinv, 9 * Lk.nn);
+        ALLOC(Lk.acol, 3 * Lk.nn);
+        if (k < L - 1) {
+            ALLOC(Lk.E, 576 * Lk.m);
+            if (k > 0) ALLOC(Lk.TQ, 576 * Lk.m);
+        }
+        ALLOC(Lk.r, 3 * Lk.nn + 1);
+        ALLOC(Lk.z, 3 * Lk.nn + 1);
+        ALLOC(Lk.res, 3 * Lk.nn + 1);
+    }
+    // the scratch TQ of level k is written from level k's E (k >= 1); level L-1 has none
+    std::vector<int> cmap(3 * H.lev[0].nn, -1);
+    int nc = 0;
+    for (size_t q = 0; q < cmap.size(); ++q)
+        if (!masks[0][q]) cmap[q] = nc++;
+    nc += 1;  // alpha
+    if (nc > kMaxCoarse) {
+        c.err = "coarsest level too large for the dense solver (" + std::to_string(nc) + ")";
+        return VTS_EINVAL;
+    }
+    if (nc < 2) {
+        c.err = "coarsest level has no free DOF";
+        return VTS_EINVAL;
+    }
+    H.nc = nc;
+    ALLOC(H.A, (int64_t)nc * nc);
+    ALLOC(H.cmap, (int64_t)cmap.size());
+    HIPCHK(hipMemcpy(H.cmap, cmap.data(), cmap.size() * sizeof(int), hipMemcpyHostToDevice));
+    ALLOC(H.flag, 1);
+    return VTS_OK;
+}
+
+vts_status sync_red(Ctx& c) {
+    HIPCHK(hipMemcpyAsync(c.red_host, c.red, kRedSlots * sizeof(double), hipMemcpyDeviceToHost, c.s));
+    HIPCHK(hipStreamSynchronize(c.s));
+    return VTS_OK;
+}
+
+// evaluation at the current state: energies, coefficients, gradient, rhs
+vts_status evaluate(Ctx& c) {
+    launch_eval(c);
+    launch_grad(c);
+    vts_status st = sync_red(c);
+    if (st != VTS_OK) return st;
+    const double* r = c.red_host;
+    c.sum_r1 = r[SL_SUM_R1];
+    c.sum_z = r[SL_SUM_Z];
+    c.sum_w = r[SL_SUM_W];
+    c.n_g3 = std::sqrt(r[SL_G3SQ]);
+    c.n_g4 = std::sqrt(r[SL_G4SQ]);
+    c.n_g1 = std::sqrt(r[SL_G1SQ]);
+    c.g2 = c.V - c.sum_r1;
+    launch_set(c, c.rhs + c.ndof, -c.g2 - c.sum_z);
+    if (!std::isfinite(c.n_g1) || !std::isfinite(c.sum_w) || !std::isfinite(c.n_g3)) {
+        c.err = "non-finite value in the gradient";
+        return VTS_EINVAL;
+    }
+    c.eval_valid = true;
+    c.setup_valid = false;
+    return VTS_OK;
+}
+
+double res_pbm(const Ctx& c) {
+    return c.n_g1 / c.norm_f + std::fabs(c.g2) / c.V + c.n_g3 / c.norm_bounds;
+}
+double res4_term(const Ctx& c) { return c.n_g4 / c.norm_bounds; }
+
+vts_status build_mg(Ctx& c) {
+    int flag = 0;
+    if (c.h64) {
+        mg_build(c, *c.h64);
+        flag = mg_check_factor(c, *c.h64);
+    } else {
+        mg_build(c, *c.h32);
+        flag = mg_check_factor(c, *c.h32);
+    }
+    HIPCHK(hipGetLastError());
+    if (flag) {
+        c.err = "coarsest multigrid matrix is not positive definite";
+        return VTS_ENONSPD;
+    }
+    c.setup_valid = true;
+    return VTS_OK;
+}
+
+vts_status setup(Ctx& c) {
+    if (!c.eval_valid) {
+        vts_status st = evaluate(c);
+        if (st != VTS_OK) return st;
+    }
+    if (!c.setup_valid) return build_mg(c);
+    return VTS_OK;
+}
+
+void precond(Ctx& c, const double* r, double* z) {
+    if (c.h64)
+        mg_vcycle(c, *c.h64, r, z);
+    else
+        mg_vcycle(c, *c.h32, r, z);
+}
+
+// Preconditioned MINRES (Paige-Saunders), x0 = 0: Lanczos in the M-inner
+// product with M^{-1} one V-cycle, Givens QR of the tridiagonal, stop when the
+// M^{-1}-norm estimate phi_bar of the residual is <= eps * beta_1.
+vts_status minres(Ctx& c, double eps, vts_linstats* out) {
+    const int64_t n = c.ndof + 1;
+    double *x = c.mv[0], *r1 = c.mv[1], *r2 = c.mv[2], *y = c.mv[3], *v = c.mv[4];
+    double* wb[3] = {c.mv[5], c.mv[6], c.mv[7]};   // w, w1(k-2), w2(k-1) rotate
+    launch_fill(c, x, 0.0, n);
+    HIPCHK(hipMemcpyAsync(r1, c.rhs, n * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+    precond(c, r1, y);
+    launch_dot(c, r1, y, n, SL_DOT);
+    vts_status st = sync_red(c);
+    if (st != VTS_OK) return st;
+    const double b1sq = c.red_host[SL_DOT];
+    if (!(b1sq >= 0) || !std::isfinite(b1sq)) {
+        c.err = "MINRES: preconditioner not positive definite";
+        return VTS_ENONSPD;
+    }
+    int it = 0;
+    double rel = 0.0;
+    if (b1sq > 0) {
+        const double beta1 = std::sqrt(b1sq);
+        double beta = beta1, beta_old = 0.0;
+        HIPCHK(hipMemcpyAsync(r2, r1, n * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+        launch_fill(c, wb[0], 0.0, n);
+        launch_fill(c, wb[1], 0.0, n);
+        launch_fill(c, wb[2], 0.0, n);
+        int iw = 0, iw1 = 1, iw2 = 2;                 // buffers holding w_k-1 ... as in the recurrence
+        double cs = -1.0, sn = 0.0, dbar = 0.0, eps_l = 0.0, phibar = beta1;
+        for (it = 1; it <= c.opt.max_minres; ++it) {
+            launch_scale(c, v, y, 1.0 / beta, n);
+            launch_apply_S(c, v, y);
+            if (it >= 2) launch_axpy(c, y, -beta / beta_old, r1, n);
+            launch_dot(c, v, y, n, SL_DOT);
+            if ((st = sync_red(c)) != VTS_OK) return st;
+            const double alpha = c.red_host[SL_DOT];
+            launch_axpy(c, y, -alpha / beta, r2, n);
+            std::swap(r1, r2);
+            std::swap(r2, y);
+            precond(c, r2, y);
+            launch_dot(c, r2, y, n, SL_DOT);
+            if ((st = sync_red(c)) != VTS_OK) return st;
+            const double bsq = c.red_host[SL_DOT];
+            if (!(bsq >= 0) || !std::isfinite(bsq)) {
+                c.err = "MINRES: preconditioner not positive definite";
+                return VTS_ENONSPD;
+            }
+            beta_old = beta;
+            beta = std::sqrt(bsq);
+            const double eps_old = eps_l;
+            const double delta = cs * dbar + sn * alpha;
+            const double gbar = sn * dbar - cs * alpha;
+            eps_l = sn * beta;
+            dbar = -cs * beta;
+            double gamma = std::hypot(gbar, beta);
+            gamma = std::max(gamma, 2.220446049250313e-16);
+            cs = gbar / gamma;
+            sn = beta / gamma;
+            const double phi = cs * phibar;
+            phibar = sn * phibar;
+            // w1 <- w2, w2 <- w, w <- (v - eps_old w1 - delta w2)/gamma
+            const int old_w1 = iw1;
+            iw1 = iw2;
+            iw2 = iw;
+            iw = old_w1;
+            launch_minres_w(c, wb[iw], v, wb[iw1], wb[iw2], eps_old, delta, 1.0 / gamma, x, phi, n);
+            rel = phibar / beta1;
+            if (phibar <= eps * beta1) break;
+        }
+        if (it > c.opt.max_minres) it = c.opt.max_minres;
+    }
+    HIPCHK(hipMemcpyAsync(c.dy, x, n * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+    // keep the rotated buffers consistent for the next call
+    c.mv[1] = r1; c.mv[2] = r2; c.mv[3] = y;
+    HIPCHK(hipGetLastError());
+    c.minres_total += it;
+    if (out) {
+        out->iterations = it;
+        out->rel_residual = rel;
+    }
+    return VTS_OK;
+}
+
+vts_status newton_step(Ctx& c, vts_newtonstats* out, bool final_call) {
+    vts_status st = setup(c);
+    if (st != VTS_OK) return st;
+    vts_linstats ls{0, 0.0};
+    double slope = 0.0, dalpha = 0.0;
+    for (int tries = 0;; ++tries) {
+        if ((st = minres(c, c.eps_mr, &ls)) != VTS_OK) return st;
+        launch_dnu(c);
+        launch_dot(c, c.g1, c.dy, c.ndof, SL_DOT);
+        launch_copy1(c, c.dy + c.ndof, c.red + SL_AUX);
+        if ((st = sync_red(c)) != VTS_OK) return st;
+        dalpha = c.red_host[SL_AUX];
+        slope = c.red_host[SL_DOT] + c.g2 * dalpha + c.red_host[SL_SLOPE_NU];
+        if (slope < 0 || tries >= 1) break;
+        // a non-descent direction: tighten the MINRES tolerance once
+        c.eps_mr = std::max(0.1 * c.eps_mr, c.opt.eps_mr_min);
+    }
+    if (!(slope < 0)) {
+        c.err = "Newton direction is not a descent direction";
+        return VTS_ENONDESCENT;
+    }
+    // f^T du for the linear part of the Lagrangian change
+    launch_dot(c, c.f, c.dy, c.ndof, SL_DOT);
+    if ((st = sync_red(c)) != VTS_OK) return st;
+    const double fdu = c.red_host[SL_DOT];
+    double kappa = 1.0;
+    for (;;) {
+        launch_linesearch(c, kappa, dalpha);
+        if ((st = sync_red(c)) != VTS_OK) return st;
+        const double dL = kappa * dalpha * c.V - kappa * fdu + c.red_host[SL_LS];
+        if (dL <= c.opt.armijo_c1 * kappa * slope) break;
+        kappa *= 0.5;
+        if (kappa < c.opt.armijo_min) {
+            c.err = "Armijo line search stalled";
+            return VTS_ENONDESCENT;
+        }
+    }
+    launch_update(c, kappa);
+    c.alpha += kappa * dalpha;
+    c.eval_valid = false;
+    if ((st = evaluate(c)) != VTS_OK) return st;
+    const double res = res_pbm(c), r4 = res4_term(c);
+    if (c.res_prev >= 0 && res > 0.9 * c.res_prev)
+        c.eps_mr = std::max(0.1 * c.eps_mr, c.opt.eps_mr_min);
+    c.res_prev = res;
+    c.newton_total += 1;
+    if (out) {
+        out->res_pbm = res;
+        out->res4 = r4;
+        out->kappa = kappa;
+        out->slope = slope;
+        out->eps_mr = c.eps_mr;
+        out->minres_its = ls.iterations;
+    }
+    (void)final_call;
+    return VTS_OK;
+}
+
+vts_status newton(Ctx& c, double eps_nwt, bool final_call, vts_newtonstats* last, int* its) {
+    c.res_prev = -1.0;
+    vts_newtonstats ns{};
+    int k = 0;
+    vts_status st = VTS_OK;
+    for (k = 0; k < c.opt.max_newton; ++k) {
+        st = newton_step(c, &ns, final_call);
+        if (st != VTS_OK) break;
+        const double crit = (final_call && c.opt.final_res4) ? ns.res_pbm + ns.res4 : ns.res_pbm;
+        if (crit < eps_nwt) break;
+    }
+    if (last) *last = ns;
+    if (its) *its = k + (st == VTS_OK ? 1 : 0);
+    if (st == VTS_OK && k >= c.opt.max_newton) {
+        c.err = "Newton iteration limit";
+        return VTS_ENOTCONV;
+    }
+    return st;
+}
+
+vts_status pbm_iterate(Ctx& c, vts_pbmstats* out) {
+    const int mr0 = c.minres_total;
+    int nits = 0;
+    vts_newtonstats ns{};
+    vts_status st = newton(c, c.eps_nwt, false, &ns, &nits);
+    if (st != VTS_OK) return st;
+    launch_outer_eval(c);
+    launch_dot(c, c.f, c.u, c.ndof, SL_DOT);
+    if ((st = sync_red(c)) != VTS_OK) return st;
+    const double* r = c.red_host;
+    const double fu = r[SL_DOT];
+    const double gap = -0.5 * fu + c.alpha * c.V - r[SL_GAP];
+    const double dual = c.alpha * c.V - fu - r[SL_NLO] + r[SL_NHI];
+    const double ratio = std::fabs(gap / dual);
+    const double stat = r[SL_STAT];
+    c.outer += 1;
+    const bool stop = ratio < c.opt.eps_pbm && (c.opt.eps_stat <= 0 || stat < c.opt.eps_stat);
+    if (out) {
+        out->gap = gap;
+        out->dual = dual;
+        out->ratio = ratio;
+        out->stat = c.opt.eps_stat > 0 ? stat : 0.0;
+        out->eps_nwt = c.eps_nwt;
+        out->sum_rho = r[SL_SUM_RHO];
+        out->newton_its = nits;
+        out->minres_its = c.minres_total - mr0;
+        out->converged = stop ? 1 : 0;
+    }
+    if (stop) {
+        c.converged = true;
+        return VTS_OK;
+    }
+    launch_mult_update(c, 0);
+    launch_penalty_update(c);
+    c.eps_nwt = std::max(std::min(100.0 * ratio, c.eps_nwt), c.opt.eps_nwt_min);
+    c.eval_valid = false;
+    c.setup_valid = false;
+    HIPCHK(hipGetLastError());
+    return VTS_OK;
+}
+
+vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, void* stream) {
+    c.nx = pr->nx; c.ny = pr->ny; c.nz = pr->nz; c.L = pr->levels;
+    c.nn = nodes_of(Dims{c.nx, c.ny, c.nz});
+    c.ndof = 3 * c.nn;
+    c.m = (int64_t)c.nx * c.ny * c.nz;
+    c.E = pr->E; c.nu = pr->nu; c.h = pr->h; c.V = pr->V;
+    c.prec = pr->precision;
+    if (opt) c.opt = *opt; else vts_default_options(&c.opt);
+    c.s = (hipStream_t)stream;
+
+    // host-side checks of the data (assumptions after problem (1.1))
+    std::vector<uint8_t> mask(pr->fixed_host, pr->fixed_host + c.ndof);
+    std::vector<double> f(pr->f_host, pr->f_host + c.ndof);
+    int64_t nfixed = 0;
+    double nf2 = 0.0;
+    for (int64_t q = 0; q < c.ndof; ++q) {
+        mask[q] = mask[q] ? 1 : 0;
+        nfixed += mask[q];
+        if (mask[q]) f[q] = 0.0;
+        if (!std::isfinite(f[q])) { c.err = "load vector is not finite"; return VTS_EINVAL; }
+        nf2 += f[q] * f[q];
+    }
+    if (nfixed == 0) { c.err = "no fixed DOF: K(rho) is singular"; return VTS_EINVAL; }
+    if (nf2 == 0.0) { c.err = "zero load"; return VTS_EINVAL; }
+    c.nfree = c.ndof - nfixed;
+    c.norm_f = std::sqrt(nf2);
+    std::vector<double> lo(c.m), hi(c.m);
+    double slo = 0, shi = 0, nlo2 = 0, nhi2 = 0;
+    for (int64_t e = 0; e < c.m; ++e) {
+        lo[e] = pr->rho_lo_host ? pr->rho_lo_host[e] : pr->rho_lo_s;
+        hi[e] = pr->rho_hi_host ? pr->rho_hi_host[e] : pr->rho_hi_s;
+        if (!(hi[e] > lo[e]) || lo[e] < 0) { c.err = "need 0 <= rho_lo < rho_hi"; return VTS_EINVAL; }
+        slo += lo[e]; shi += hi[e]; nlo2 += lo[e] * lo[e]; nhi2 += hi[e] * hi[e];
+    }
+    if (!(slo < c.V && c.V < shi)) { c.err = "volume not strictly feasible"; return VTS_EINVAL; }
+    c.norm_bounds = std::sqrt(nlo2) + std::sqrt(nhi2);
+    {
+        // nested fixed DOFs and the size of the dense coarsest system
+        std::vector<uint8_t> mk = mask;
+        Dims dk{c.nx, c.ny, c.nz};
+        for (int k = c.L - 1; k > 0; --k) {
+            std::vector<uint8_t> mc = coarsen_mask(mk, dk);
+            if (!nested(mk, dk, mc)) {
+                c.err = "fixed DOFs are not nested across multigrid levels";
+                return VTS_EINVAL;
+            }
+            mk.swap(mc);
+            dk = Dims{dk.nx / 2, dk.ny / 2, dk.nz / 2};
+        }
+        int64_t nc = 1;
+        for (uint8_t v : mk) nc += v ? 0 : 1;
+        if (nc > kMaxCoarse) {
+            c.err = "coarsest level too large for the dense solver (" + std::to_string(nc) + ")";
+            return VTS_EINVAL;
+        }
+    }
+    HIPCHK(hipGetDevice(&c.device));
+
+    // constants
+    double Ke[576], Q[512], Mc[8 * 576];
+    float Kef[576];
+    element_stiffness(c.E, c.nu, c.h, Ke);
+    child_interp(Q);
+    galerkin_child_matrices(Ke, Q, Mc);
+    for (int q = 0; q < 576; ++q) Kef[q] = (float)Ke[q];
+    ALLOC(c.Ke, 576); ALLOC(c.Kef, 576); ALLOC(c.Mc, 8 * 576); ALLOC(c.Qc, 512);
+    HIPCHK(hipMemcpy(c.Ke, Ke, sizeof(Ke), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c.Kef, Kef, sizeof(Kef), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c.Mc, Mc, sizeof(Mc), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c.Qc, Q, sizeof(Q), hipMemcpyHostToDevice));
+
+    ALLOC(c.fixed, c.ndof); ALLOC(c.f, c.ndof); ALLOC(c.rlo, c.m); ALLOC(c.rhi, c.m);
+    HIPCHK(hipMemcpy(c.fixed, mask.data(), c.ndof, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c.f, f.data(), c.ndof * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c.rlo, lo.data(), c.m * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c.rhi, hi.data(), c.m * 8, hipMemcpyHostToDevice));
+    ALLOC(c.u, c.ndof);
+    ALLOC(c.nlo, c.m); ALLOC(c.nhi, c.m); ALLOC(c.rho, c.m); ALLOC(c.mlo, c.m);
+    ALLOC(c.mhi, c.m); ALLOC(c.p, c.m); ALLOC(c.qlo, c.m); ALLOC(c.qhi, c.m);
+    ALLOC(c.rhof, c.m);
+    ALLOC(c.e, c.m); ALLOC(c.be, 24 * c.m);
+    ALLOC(c.r1, c.m); ALLOC(c.r2, c.m); ALLOC(c.l2, c.m); ALLOC(c.h2, c.m);
+    ALLOC(c.g3, c.m); ALLOC(c.g4, c.m); ALLOC(c.w, c.m); ALLOC(c.zc, c.m);
+    ALLOC(c.gch, 24 * c.m);
+    ALLOC(c.g1, c.ndof); ALLOC(c.rhs, c.ndof + 1); ALLOC(c.dy, c.ndof + 1);
+    ALLOC(c.dnl, c.m); ALLOC(c.dnh, c.m); ALLOC(c.c1, c.m); ALLOC(c.c2, c.m); ALLOC(c.wt, c.m);
+    for (int q = 0; q < 8; ++q) ALLOC(c.mv[q], c.ndof + 1);
+    ALLOC(c.partials, kRedSlots * kRedBlocks);
+    ALLOC(c.red, kRedSlots);
+    {
+        void* hp = nullptr;
+        HIPCHK(hipHostMalloc(&hp, kRedSlots * sizeof(double), hipHostMallocDefault));
+        c.red_host = (double*)hp;
+        std::memset(c.red_host, 0, kRedSlots * sizeof(double));
+    }
+    vts_status st;
+    if (c.prec == VTS_FP64) {
+        c.h64 = new Hierarchy<double>();
+        st = build_hierarchy(c, *c.h64, mask);
+    } else {
+        c.h32 = new Hierarchy<float>();
+        st = build_hierarchy(c, *c.h32, mask);
+    }
+    if (st != VTS_OK) return st;
+
+    launch_init_state(c);
+    launch_round_rho(c);
+    c.alpha = 1.0;
+    c.eps_nwt = c.opt.eps_nwt0;
+    c.eps_mr = c.opt.eps_mr0 > 0 ? c.opt.eps_mr0 : 1e-4 * std::sqrt((double)c.nfree);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c.s));
+    return VTS_OK;
+}
+
+void ctx_free(Ctx& c) {
+    if (c.s) hipStreamSynchronize(c.s);
+    else hipDeviceSynchronize();
+    for (void* p : c.allocs) hipFree(p);
+    c.allocs.clear();
+    if (c.red_host) hipHostFree(c.red_host);
+    c.red_host = nullptr;
+    delete c.h64;
+    delete c.h32;
+    c.h64 = nullptr;
+    c.h32 = nullptr;
+}
+
+thread_local std::string g_create_err;
+
+}  // namespace
+
+extern "C" {
+
+void vts_default_options(vts_options* o) {
+    if (!o) return;
+    o->beta = 0.3;
+    o->gamma = 0.3;
+    o->p_min = 1e-8;
+    o->eps_pbm = 1e-8;
+    o->eps_nwt0 = 1.0;
+    o->eps_nwt_min = 1e-5;
+    o->eps_nwt_final = 5e-7;
+    o->eps_stat = 5e-7;
+    o->accept_stall = 1e-6;
+    o->eps_mr0 = 0.0;
+    o->eps_mr_min = 1e-9;
+    o->armijo_c1 = 1e-4;
+    o->armijo_min = 9.313225746154785e-10;   // 2^-30
+    o->max_outer = 100;
+    o->max_newton = 100;
+    o->max_minres = 500;
+    o->final_res4 = 1;
+}
+
+vts_status vts_create(const vts_problem* pr, const vts_options* opt, void* stream, vts_ctx** out) {
+    if (!out) return VTS_EINVAL;
+    *out = nullptr;
+    std::string err;
+    vts_status st = validate(pr, err);
+    if (st != VTS_OK) {
+        g_create_err = err;
+        return st;
+    }
+    vts_ctx* c = new (std::nothrow) vts_ctx();
+    if (!c) return VTS_ENOMEM;
+    st = ctx_create(*c, pr, opt, stream);
+    if (st != VTS_OK) {
+        g_create_err = c->err;
+        ctx_free(*c);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return VTS_OK;
+}
+
+void vts_destroy(vts_ctx* c) {
+    if (!c) return;
+    ctx_free(*c);
+    delete c;
+}
+
+size_t vts_footprint_bytes(const vts_problem* pr, const vts_options* opt) {
+    (void)opt;
+    std::string err;
+    if (validate(pr, err) != VTS_OK) return 0;
+    return make_plan(pr).total();
+}
+
+vts_status vts_sizes(const vts_ctx* c, int64_t* n_dof, int64_t* m, int64_t* n_free,
+                     int32_t* levels) {
+    if (!c) return VTS_EINVAL;
+    if (n_dof) *n_dof = c->ndof;
+    if (m) *m = c->m;
+    if (n_free) *n_free = c->nfree;
+    if (levels) *levels = c->L;
+    return VTS_OK;
+}
+
+vts_status vts_set_rho(vts_ctx* cp, const double* rho_dev) {
+    if (!cp || !rho_dev) return VTS_EINVAL;
+    Ctx& c = *cp;
+    HIPCHK(hipMemcpyAsync(c.rho, rho_dev, c.m * 8, hipMemcpyDeviceToDevice, c.s));
+    launch_round_rho(c);
+    c.eval_valid = false;
+    c.setup_valid = false;
+    HIPCHK(hipGetLastError());
+    return VTS_OK;
+}
+
+vts_status vts_apply_K(vts_ctx* cp, const double* x, double* y) {
+    if (!cp || !x || !y || x == y) return VTS_EINVAL;
+    Ctx& c = *cp;
+    launch_apply_K_f64(c, c.rho, x, y);
+    HIPCHK(hipGetLastError());
+    return VTS_OK;
+}
+
+vts_status vts_apply_K_f32(vts_ctx* cp, const float* x, float* y) {
+    if (!cp || !x || !y || x == y) return VTS_EINVAL;
+    Ctx& c = *cp;
+    launch_apply_K_f32(c, c.rhof, x, y);
+    HIPCHK(hipGetLastError());
+    return VTS_OK;
+}
+
+vts_status vts_element_energy(vts_ctx* cp, const double* u, double* e) {
+    if (!cp || !u || !e) return VTS_EINVAL;
+    Ctx& c = *cp;
+    launch_energy(c, u, e);
+    HIPCHK(hipGetLastError());
+    return VTS_OK;
+}
+
+vts_status vts_newton_setup(vts_ctx* cp) {
+    if (!cp) return VTS_EINVAL;
+    Ctx& c = *cp;
+    c.eval_valid = false;
+    return setup(c);
+}
+
+vts_status vts_apply_S(vts_ctx* cp, const double* x, double* y) {
+    if (!cp || !x || !y || x == y) return VTS_EINVAL;
+    Ctx& c = *cp;
+    if (!c.eval_valid) { c.err = "apply_S before newton_setup"; return VTS_ESTATE; }
+    launch_apply_S(c, x, y);
+    HIPCHK(hipGetLastError());
+    return VTS_OK;
+}
+
+vts_status vts_precondition(vts_ctx* cp, const double* r, double* z) {
+    if (!cp || !r || !z || r == z) return VTS_EINVAL;
+    Ctx& c = *cp;
+    if (!c.setup_valid) { c.err = "precondition before newton_setup"; return VTS_ESTATE; }
+    precond(c, r, z);
+    HIPCHK(hipGetLastError());
+    return VTS_OK;
+}
+
+vts_status vts_solve_newton(vts_ctx* cp, double eps_mr, vts_linstats* stats) {
+    if (!cp) return VTS_EINVAL;
+    Ctx& c = *cp;
+    if (!c.setup_valid) { c.err = "solve before newton_setup"; return VTS_ESTATE; }
+    return minres(c, eps_mr, stats);
+}
+
+vts_status vts_newton_step(vts_ctx* cp, vts_newtonstats* stats) {
+    if (!cp) return VTS_EINVAL;
+    return newton_step(*cp, stats, false);
+}
+
+vts_status vts_newton(vts_ctx* cp, double eps_nwt, int32_t final_call, vts_newtonstats* last) {
+    if (!cp) return VTS_EINVAL;
+    return newton(*cp, eps_nwt, final_call != 0, last, nullptr);
+}
+
+vts_status vts_pbm_iterate(vts_ctx* cp, vts_pbmstats* stats) {
+    if (!cp) return VTS_EINVAL;
+    Ctx& c = *cp;
+    if (c.converged) { c.err = "already converged"; return VTS_ESTATE; }
+    return pbm_iterate(c, stats);
+}
+
+vts_status vts_pbm_solve(vts_ctx* cp, vts_result* res) {
+    if (!cp) return VTS_EINVAL;
+    Ctx& c = *cp;
+    vts_status st = VTS_OK;
+    while (!c.converged && c.outer < c.opt.max_outer) {
+        st = pbm_iterate(c, nullptr);
+        if (st != VTS_OK) break;
+    }
+    if (st == VTS_OK && !c.converged) st = VTS_ENOTCONV;
+    vts_newtonstats ns{};
+    if (st == VTS_OK) {
+        st = newton(c, c.opt.eps_nwt_final, true, &ns, nullptr);
+        if (st != VTS_OK && c.res_prev >= 0 && c.res_prev < c.opt.accept_stall) st = VTS_OK;
+        // the last accepted state was evaluated; make sure of it before the rho update
+        if (!c.eval_valid) {
+            vts_status s2 = evaluate(c);
+            if (s2 != VTS_OK && st == VTS_OK) st = s2;
+        }
+        launch_mult_update(c, 1);
+        launch_round_rho(c);
+        c.eval_valid = false;
+        c.setup_valid = false;
+    }
+    if (res) {
+        launch_dot(c, c.f, c.u, c.ndof, SL_DOT);
+        launch_outer_eval(c);
+        vts_status s3 = sync_red(c);
+        if (s3 != VTS_OK && st == VTS_OK) st = s3;
+        res->compliance = 0.5 * c.red_host[SL_DOT];
+        res->alpha = c.alpha;
+        res->sum_rho = c.red_host[SL_SUM_RHO];
+        res->res_pbm = c.res_prev;
+        res->outer = c.outer;
+        res->newton = c.newton_total;
+        res->minres = c.minres_total;
+        res->status = st;
+    }
+    c.status = st;
+    return st;
+}
+
+vts_status vts_get_vector(const vts_ctx* cp, int32_t which, double* dst) {
+    if (!cp || !dst) return VTS_EINVAL;
+    Ctx& c = const_cast<vts_ctx&>(*cp);
+    const double* src = nullptr;
+    int64_t n = 0;
+    switch (which) {
+        case VTS_VEC_U: src = c.u; n = c.ndof; break;
+        case VTS_VEC_RHO: src = c.rho; n = c.m; break;
+        case VTS_VEC_ENERGY: src = c.e; n = c.m; break;
+        case VTS_VEC_RHS: src = c.rhs; n = c.ndof + 1; break;
+        case VTS_VEC_DY: src = c.dy; n = c.ndof + 1; break;
+        case VTS_VEC_G1: src = c.g1; n = c.ndof; break;
+        case VTS_VEC_DNU_LO: src = c.dnl; n = c.m; break;
+        case VTS_VEC_DNU_HI: src = c.dnh; n = c.m; break;
+        case VTS_VEC_RHO1: src = c.r1; n = c.m; break;
+        case VTS_VEC_W: src = c.w; n = c.m; break;
+        default: c.err = "unknown vector"; return VTS_EINVAL;
+    }
+    if ((which == VTS_VEC_ENERGY || which == VTS_VEC_RHS || which == VTS_VEC_G1 ||
+         which == VTS_VEC_RHO1 || which == VTS_VEC_W) && !c.eval_valid) {
+        c.err = "state not evaluated (call vts_newton_setup)";
+        return VTS_ESTATE;
+    }
+    HIPCHK(hipMemcpyAsync(dst, src, n * 8, hipMemcpyDeviceToDevice, c.s));
+    return VTS_OK;
+}
+
+vts_status vts_get_state(const vts_ctx* cp, void* buf, size_t* bytes) {
+    if (!cp || !bytes) return VTS_EINVAL;
+    Ctx& c = const_cast<vts_ctx&>(*cp);
+    const size_t need = (size_t)(c.ndof + 1 + 8 * c.m + 2) * 8;
+    if (!buf || *bytes < need) {
+        *bytes = need;
+        return buf ? VTS_EINVAL : VTS_OK;
+    }
+    double* b = (double*)buf;
+    HIPCHK(hipMemcpyAsync(b, c.u, c.ndof * 8, hipMemcpyDeviceToHost, c.s));
+    b += c.ndof;
+    *b++ = c.alpha;
+    double* arr[8] = {c.nlo, c.nhi, c.rho, c.mlo, c.mhi, c.p, c.qlo, c.qhi};
+    for (int q = 0; q < 8; ++q) {
+        HIPCHK(hipMemcpyAsync(b, arr[q], c.m * 8, hipMemcpyDeviceToHost, c.s));
+        b += c.m;
+    }
+    *b++ = c.eps_nwt;
+    *b++ = c.eps_mr;
+    HIPCHK(hipStreamSynchronize(c.s));
+    *bytes = need;
+    return VTS_OK;
+}
+
+vts_status vts_set_state(vts_ctx* cp, const void* buf, size_t bytes) {
+    if (!cp || !buf) return VTS_EINVAL;
+    Ctx& c = *cp;
+    const size_t need = (size_t)(c.ndof + 1 + 8 * c.m + 2) * 8;
+    if (bytes != need) { c.err = "state size mismatch"; return VTS_EINVAL; }
+    const double* b = (const double*)buf;
+    HIPCHK(hipMemcpyAsync(c.u, b, c.ndof * 8, hipMemcpyHostToDevice, c.s));
+    b += c.ndof;
+    c.alpha = *b++;
+    double* arr[8] = {c.nlo, c.nhi, c.rho, c.mlo, c.mhi, c.p, c.qlo, c.qhi};
+    for (int q = 0; q < 8; ++q) {
+        HIPCHK(hipMemcpyAsync(arr[q], b, c.m * 8, hipMemcpyHostToDevice, c.s));
+        b += c.m;
+    }
+    c.eps_nwt = *b++;
+    c.eps_mr = *b++;
+    HIPCHK(hipStreamSynchronize(c.s));
+    launch_round_rho(c);
+    c.eval_valid = false;
+    c.setup_valid = false;
+    c.converged = false;
+    return VTS_OK;
+}
+
+const char* vts_last_error(const vts_ctx* c) {
+    if (!c) return g_create_err.c_str();
+    return c->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,707 @@
+// HIP kernels of libvts for CDNA4 (gfx950), wave64.
+//
+// Layouts (see include/vts.h): all-DOF displacement vectors, node-major xyz;
+// per-element arrays in element order; per-element 24-vectors stored
+// component-major ([j][e]) so that a wave reads them coalesced.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+
+#include "vts_internal.hpp"
+
+namespace vts {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t gid() {
+    return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+}
+
+__device__ __forceinline__ int64_t node_id(int i, int j, int k, int NX, int NY) {
+    return (int64_t)i + (int64_t)NX * ((int64_t)j + (int64_t)NY * k);
+}
+
+// Penalty-barrier function of Ben-Tal and Zibulevsky with tau_hat = -1/2
+// (Section 3.1): quadratic for t >= -1/2, logarithmic branch below.
+__device__ __forceinline__ double pen_phi(double t) {
+    return t >= -0.5 ? t + 0.5 * t * t : -0.25 * log(-2.0 * t) - 0.375;
+}
+__device__ __forceinline__ double pen_dphi(double t) {
+    return t >= -0.5 ? 1.0 + t : -0.25 / t;
+}
+__device__ __forceinline__ double pen_d2phi(double t) {
+    return t >= -0.5 ? 1.0 : 0.25 / (t * t);
+}
+
+// block-wide sum of NQ values per thread; thread 0 writes partials[q*kRedBlocks + block]
+template <int NQ>
+__device__ __forceinline__ void block_sum_store(double (&v)[NQ], double* partials, int slot0,
+                                                uint32_t maxmask = 0) {
+    __shared__ double sh[NQ][kThreads / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double x = v[q];
+        const bool mx = (maxmask >> q) & 1u;
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_down(x, off, 64);
+            x = mx ? fmax(x, o) : x + o;
+        }
+        if (lane == 0) sh[q][wv] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const bool mx = (maxmask >> q) & 1u;
+            double x = sh[q][0];
+            for (int k = 1; k < kThreads / 64; ++k) x = mx ? fmax(x, sh[q][k]) : x + sh[q][k];
+            partials[(slot0 + q) * kRedBlocks + blockIdx.x] = x;
+        }
+    }
+}
+
+static inline int red_grid(int64_t n) {
+    int64_t b = (n + kThreads - 1) / kThreads;
+    if (b < 1) b = 1;
+    return (int)(b < kRedBlocks ? b : kRedBlocks);
+}
+static inline int grid1d(int64_t n) {
+    int64_t b = (n + kThreads - 1) / kThreads;
+    return (int)(b < 1 ? 1 : b);
+}
+
+// Sum (or max) of partials[slot*kRedBlocks + b] over b < nb, fixed order.
+__global__ void k_finalize(const double* __restrict__ partials, int nb, int slot0,
+                           uint32_t maxmask, double* __restrict__ out) {
+    const int q = slot0 + blockIdx.x;
+    const bool mx = (maxmask >> blockIdx.x) & 1u;
+    double x = mx ? -DBL_MAX : 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const double v = partials[q * kRedBlocks + b];
+        x = mx ? fmax(x, v) : x + v;
+    }
+    __shared__ double sh[kThreads];
+    sh[threadIdx.x] = x;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = mx ? fmax(sh[threadIdx.x], sh[threadIdx.x + s])
+                                                  : sh[threadIdx.x] + sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[q] = sh[0];
+}
+
+// ---------------------------------------------------------------------------
+// K(rho) x : one thread per node gathers the contributions of its <= 8
+// elements (problem (1.1), K(rho) = sum rho_i K_i); deterministic, no atomics.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_apply_K(int nx, int ny, int nz, const T* __restrict__ Ke, const T* __restrict__ rho,
+          const T* __restrict__ x, const uint8_t* __restrict__ fixed, T* __restrict__ y) {
+    const int NX = nx + 1, NY = ny + 1;
+    const int64_t nn = (int64_t)NX * NY * (nz + 1);
+    const int64_t n = gid();
+    if (n >= nn) return;
+    const int i = (int)(n % NX);
+    const int64_t t = n / NX;
+    const int j = (int)(t % NY), k = (int)(t / NY);
+    T a0 = 0, a1 = 0, a2 = 0;
+    for (int ez = -1; ez <= 0; ++ez) {
+        const int kk = k + ez;
+        if (kk < 0 || kk >= nz) continue;
+        for (int ey = -1; ey <= 0; ++ey) {
+            const int jj = j + ey;
+            if (jj < 0 || jj >= ny) continue;
+            for (int ex = -1; ex <= 0; ++ex) {
+                const int ii = i + ex;
+                if (ii < 0 || ii >= nx) continue;
+                const int64_t e = ii + (int64_t)nx * (jj + (int64_t)ny * kk);
+                const int la = -ex - 2 * ey - 4 * ez;
+                const T* K0 = Ke + (3 * la) * 24;
+                T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const int64_t nb = node_id(ii + (b & 1), jj + ((b >> 1) & 1), kk + (b >> 2), NX, NY);
+                    const T x0 = fixed[3 * nb] ? T(0) : x[3 * nb];
+                    const T x1 = fixed[3 * nb + 1] ? T(0) : x[3 * nb + 1];
+                    const T x2 = fixed[3 * nb + 2] ? T(0) : x[3 * nb + 2];
+                    s0 += K0[3 * b] * x0 + K0[3 * b + 1] * x1 + K0[3 * b + 2] * x2;
+                    s1 += K0[24 + 3 * b] * x0 + K0[24 + 3 * b + 1] * x1 + K0[24 + 3 * b + 2] * x2;
+                    s2 += K0[48 + 3 * b] * x0 + K0[48 + 3 * b + 1] * x1 + K0[48 + 3 * b + 2] * x2;
+                }
+                const T r = rho[e];
+                a0 += r * s0;
+                a1 += r * s1;
+                a2 += r * s2;
+            }
+        }
+    }
+    y[3 * n] = fixed[3 * n] ? T(0) : a0;
+    y[3 * n + 1] = fixed[3 * n + 1] ? T(0) : a1;
+    y[3 * n + 2] = fixed[3 * n + 2] ? T(0) : a2;
+}
+
+void launch_apply_K_f64(Ctx& c, const double* rho, const double* x, double* y) {
+    hipLaunchKernelGGL(k_apply_K<double>, dim3(grid1d(c.nn)), dim3(kThreads), 0, c.s,
+                       c.nx, c.ny, c.nz, c.Ke, rho, x, c.fixed, y);
+}
+void launch_apply_K_f32(Ctx& c, const float* rho, const float* x, float* y) {
+    hipLaunchKernelGGL(k_apply_K<float>, dim3(grid1d(c.nn)), dim3(kThreads), 0, c.s,
+                       c.nx, c.ny, c.nz, c.Kef, rho, x, c.fixed, y);
+}
+
+// gather the 24 (masked) DOF values of element (i,j,k)
+__device__ __forceinline__ void gather_elem(const double* __restrict__ x,
+                                            const uint8_t* __restrict__ fixed, int i, int j,
+                                            int k, int NX, int NY, double (&xe)[24]) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int64_t nb = node_id(i + (b & 1), j + ((b >> 1) & 1), k + (b >> 2), NX, NY);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xe[3 * b + c] = fixed[3 * nb + c] ? 0.0 : x[3 * nb + c];
+    }
+}
+
+__device__ __forceinline__ void elem_ijk(int64_t e, int nx, int ny, int& i, int& j, int& k) {
+    i = (int)(e % nx);
+    const int64_t t = e / nx;
+    j = (int)(t % ny);
+    k = (int)(t / ny);
+}
+
+// e_i = 1/2 u_e^T K_e u_e
+__global__ void __launch_bounds__(kThreads)
+k_energy(int nx, int ny, int nz, const double* __restrict__ Ke, const double* __restrict__ u,
+         const uint8_t* __restrict__ fixed, double* __restrict__ eout) {
+    const int64_t m = (int64_t)nx * ny * nz;
+    const int64_t e = gid();
+    if (e >= m) return;
+    int i, j, k;
+    elem_ijk(e, nx, ny, i, j, k);
+    double ue[24];
+    gather_elem(u, fixed, i, j, k, nx + 1, ny + 1, ue);
+    double en = 0.0;
+    for (int r = 0; r < 24; ++r) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < 24; ++q) s += Ke[r * 24 + q] * ue[q];
+        en += ue[r] * s;
+    }
+    eout[e] = 0.5 * en;
+}
+
+void launch_energy(Ctx& c, const double* u, double* e) {
+    hipLaunchKernelGGL(k_energy, dim3(grid1d(c.m)), dim3(kThreads), 0, c.s, c.nx, c.ny, c.nz,
+                       c.Ke, u, c.fixed, e);
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation at the current state (Section 3.2): energies, forces b_e = K_e u_e,
+// s_i, rho', rho'', mu', mu'', res_3, res_4, Schur weight w and rhs weight z.
+// Partial sums: sum rho', sum z, sum w, ||res3||^2, ||res4||^2.
+// ---------------------------------------------------------------------------
+struct EvalArgs {
+    int nx, ny, nz;
+    double alpha;
+    const double *Ke, *u, *nlo, *nhi, *rho, *mlo, *mhi, *p, *qlo, *qhi, *rlo, *rhi;
+    const uint8_t* fixed;
+    double *e, *be, *r1, *r2, *l2, *h2, *g3, *g4, *w, *zc, *partials;
+};
+
+__global__ void __launch_bounds__(kThreads) k_eval(EvalArgs a) {
+    const int64_t m = (int64_t)a.nx * a.ny * a.nz;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int64_t e = gid(); e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        elem_ijk(e, a.nx, a.ny, i, j, k);
+        double ue[24];
+        gather_elem(a.u, a.fixed, i, j, k, a.nx + 1, a.ny + 1, ue);
+        double en = 0.0;
+        for (int r = 0; r < 24; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < 24; ++q) s += a.Ke[r * 24 + q] * ue[q];
+            a.be[r * m + e] = s;
+            en += ue[r] * s;
+        }
+        en *= 0.5;
+        a.e[e] = en;
+        const double pe = a.p[e], ql = a.qlo[e], qh = a.qhi[e];
+        const double s = (en - a.alpha + a.nlo[e] - a.nhi[e]) / pe;
+        const double tl = -a.nlo[e] / ql, th = -a.nhi[e] / qh;
+        const double rh = a.rho[e], ml = a.mlo[e], mh = a.mhi[e];
+        const double r1 = rh * pen_dphi(s), r2 = rh / pe * pen_d2phi(s);
+        const double ml1 = ml * pen_dphi(tl), ml2 = ml / ql * pen_d2phi(tl);
+        const double mh1 = mh * pen_dphi(th), mh2 = mh / qh * pen_d2phi(th);
+        const double g3 = -a.rlo[e] + r1 - ml1;
+        const double g4 = a.rhi[e] - r1 - mh1;
+        // 2x2 block of (nu_lo, nu_hi): det with the rho''^2 terms cancelled
+        const double det = r2 * (ml2 + mh2) + ml2 * mh2;
+        const double w = r2 * ml2 * mh2 / det;
+        const double z = r2 * (mh2 * g3 - ml2 * g4) / det;
+        a.r1[e] = r1;
+        a.r2[e] = r2;
+        a.l2[e] = ml2;
+        a.h2[e] = mh2;
+        a.g3[e] = g3;
+        a.g4[e] = g4;
+        a.w[e] = w;
+        a.zc[e] = z;
+        acc[0] += r1;
+        acc[1] += z;
+        acc[2] += w;
+        acc[3] += g3 * g3;
+        acc[4] += g4 * g4;
+    }
+    block_sum_store<5>(acc, a.partials, SL_SUM_R1);
+}
+
+void launch_eval(Ctx& c) {
+    EvalArgs a{c.nx, c.ny, c.nz, c.alpha, c.Ke, c.u, c.nlo, c.nhi, c.rho, c.mlo, c.mhi, c.p,
+               c.qlo, c.qhi, c.rlo, c.rhi, c.fixed, c.e, c.be, c.r1, c.r2, c.l2, c.h2,
+               c.g3, c.g4, c.w, c.zc, c.partials};
+    const int g = red_grid(c.m);
+    hipLaunchKernelGGL(k_eval, dim3(g), dim3(kThreads), 0, c.s, a);
+    hipLaunchKernelGGL(k_finalize, dim3(5), dim3(kThreads), 0, c.s, c.partials, g, (int)SL_SUM_R1,
+                       0u, c.red);
+}
+
+// res_1 = K(rho')u - f = sum_e rho'_e b_e - f and the reduced right-hand side
+// rhs_u = -res_1 + sum_e z_e b_e = f - sum_e (rho'_e - z_e) b_e (masked).
+__global__ void __launch_bounds__(kThreads)
+k_grad(int nx, int ny, int nz, const double* __restrict__ be, const double* __restrict__ r1,
+       const double* __restrict__ zc, const double* __restrict__ f,
+       const uint8_t* __restrict__ fixed, double* __restrict__ g1, double* __restrict__ rhs,
+       double* partials) {
+    const int NX = nx + 1, NY = ny + 1;
+    const int64_t nn = (int64_t)NX * NY * (nz + 1);
+    const int64_t m = (int64_t)nx * ny * nz;
+    double acc[1] = {0.0};
+    for (int64_t n = gid(); n < nn; n += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(n % NX);
+        const int64_t t = n / NX;
+        const int j = (int)(t % NY), k = (int)(t / NY);
+        double a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+        for (int ez = -1; ez <= 0; ++ez) {
+            const int kk = k + ez;
+            if (kk < 0 || kk >= nz) continue;
+            for (int ey = -1; ey <= 0; ++ey) {
+                const int jj = j + ey;
+                if (jj < 0 || jj >= ny) continue;
+                for (int ex = -1; ex <= 0; ++ex) {
+                    const int ii = i + ex;
+                    if (ii < 0 || ii >= nx) continue;
+                    const int64_t e = ii + (int64_t)nx * (jj + (int64_t)ny * kk);
+                    const int la = -ex - 2 * ey - 4 * ez;
+                    const double w1 = r1[e], w2 = r1[e] - zc[e];
+                    for (int c = 0; c < 3; ++c) {
+                        const double bv = be[(3 * la + c) * m + e];
+                        a[c] += w1 * bv;
+                        b[c] += w2 * bv;
+                    }
+                }
+            }
+        }
+        for (int c = 0; c < 3; ++c) {
+            const bool fx = fixed[3 * n + c];
+            const double gv = fx ? 0.0 : a[c] - f[3 * n + c];
+            g1[3 * n + c] = gv;
+            rhs[3 * n + c] = fx ? 0.0 : f[3 * n + c] - b[c];
+            acc[0] += gv * gv;
+        }
+    }
+    block_sum_store<1>(acc, partials, SL_G1SQ);
+}
+
+void launch_grad(Ctx& c) {
+    const int g = red_grid(c.nn);
+    hipLaunchKernelGGL(k_grad, dim3(g), dim3(kThreads), 0, c.s, c.nx, c.ny, c.nz, c.be, c.r1,
+                       c.zc, c.f, c.fixed, c.g1, c.rhs, c.partials);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c.s, c.partials, g, (int)SL_G1SQ,
+                       0u, c.red);
+}
+
+// ---------------------------------------------------------------------------
+// S [x; beta] of eq. (3.12), matrix-free in FP64:
+//   pass 1 (elements): wt_e = w_e (b_e^T x_e - beta), partial sum of wt
+//   pass 2 (nodes):    y_n = sum_e rho'_e (K_e x_e)_n + wt_e (b_e)_n
+//   y_alpha = -sum_e wt_e
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads)
+k_S_pass1(int nx, int ny, int nz, const double* __restrict__ be, const double* __restrict__ w,
+          const double* __restrict__ x, int64_t ndof, const uint8_t* __restrict__ fixed,
+          double* __restrict__ wt, double* partials) {
+    const int64_t m = (int64_t)nx * ny * nz;
+    const double beta = x[ndof];
+    double acc[1] = {0.0};
+    for (int64_t e = gid(); e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        elem_ijk(e, nx, ny, i, j, k);
+        double xe[24];
+        gather_elem(x, fixed, i, j, k, nx + 1, ny + 1, xe);
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < 24; ++q) t += be[q * m + e] * xe[q];
+        const double v = w[e] * (t - beta);
+        wt[e] = v;
+        acc[0] += v;
+    }
+    block_sum_store<1>(acc, partials, SL_WT);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_S_pass2(int nx, int ny, int nz, const double* __restrict__ Ke, const double* __restrict__ r1,
+          const double* __restrict__ be, const double* __restrict__ wt,
+          const double* __restrict__ x, const uint8_t* __restrict__ fixed,
+          double* __restrict__ y) {
+    const int NX = nx + 1, NY = ny + 1;
+    const int64_t nn = (int64_t)NX * NY * (nz + 1);
+    const int64_t m = (int64_t)nx * ny * nz;
+    const int64_t n = gid();
+    if (n >= nn) return;
+    const int i = (int)(n % NX);
+    const int64_t t = n / NX;
+    const int j = (int)(t % NY), k = (int)(t / NY);
+    double a0 = 0, a1 = 0, a2 = 0;
+    for (int ez = -1; ez <= 0; ++ez) {
+        const int kk = k + ez;
+        if (kk < 0 || kk >= nz) continue;
+        for (int ey = -1; ey <= 0; ++ey) {
+            const int jj = j + ey;
+            if (jj < 0 || jj >= ny) continue;
+            for (int ex = -1; ex <= 0; ++ex) {
+                const int ii = i + ex;
+                if (ii < 0 || ii >= nx) continue;
+                const int64_t e = ii + (int64_t)nx * (jj + (int64_t)ny * kk);
+                const int la = -ex - 2 * ey - 4 * ez;
+                const double* K0 = Ke + (3 * la) * 24;
+                double s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const int64_t nb = node_id(ii + (b & 1), jj + ((b >> 1) & 1), kk + (b >> 2), NX, NY);
+                    const double x0 = fixed[3 * nb] ? 0.0 : x[3 * nb];
+                    const double x1 = fixed[3 * nb + 1] ? 0.0 : x[3 * nb + 1];
+                    const double x2 = fixed[3 * nb + 2] ? 0.0 : x[3 * nb + 2];
+                    s0 += K0[3 * b] * x0 + K0[3 * b + 1] * x1 + K0[3 * b + 2] * x2;
+                    s1 += K0[24 + 3 * b] * x0 + K0[24 + 3 * b + 1] * x1 + K0[24 + 3 * b + 2] * x2;
+                    s2 += K0[48 + 3 * b] * x0 + K0[48 + 3 * b + 1] * x1 + K0[48 + 3 * b + 2] * x2;
+                }
+                const double r = r1[e], q = wt[e];
+                a0 += r * s0 + q * be[(3 * la) * m + e];
+                a1 += r * s1 + q * be[(3 * la + 1) * m + e];
+                a2 += r * s2 + q * be[(3 * la + 2) * m + e];
+            }
+        }
+    }
+    y[3 * n] = fixed[3 * n] ? 0.0 : a0;
+    y[3 * n + 1] = fixed[3 * n + 1] ? 0.0 : a1;
+    y[3 * n + 2] = fixed[3 * n + 2] ? 0.0 : a2;
+}
+
+__global__ void k_store_neg(const double* __restrict__ red, int slot, double* __restrict__ dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = -red[slot];
+}
+
+void launch_apply_S(Ctx& c, const double* x, double* y) {
+    const int g = red_grid(c.m);
+    hipLaunchKernelGGL(k_S_pass1, dim3(g), dim3(kThreads), 0, c.s, c.nx, c.ny, c.nz, c.be, c.w,
+                       x, c.ndof, c.fixed, c.wt, c.partials);
+    hipLaunchKernelGGL(k_S_pass2, dim3(grid1d(c.nn)), dim3(kThreads), 0, c.s, c.nx, c.ny, c.nz,
+                       c.Ke, c.r1, c.be, c.wt, x, c.fixed, y);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c.s, c.partials, g, (int)SL_WT, 0u,
+                       c.red);
+    hipLaunchKernelGGL(k_store_neg, dim3(1), dim3(64), 0, c.s, c.red, (int)SL_WT, y + c.ndof);
+}
+
+// ---------------------------------------------------------------------------
+// Newton completion: Delta nu of eq. (3.14) (multiplied out), and the line
+// search coefficients c1 = b_e^T du_e, c2 = 1/2 du_e^T K_e du_e so that
+// e_i(u + k du) = e_i + k c1 + k^2 c2 exactly.
+// ---------------------------------------------------------------------------
+struct DnuArgs {
+    int nx, ny, nz;
+    int64_t ndof;
+    const double *Ke, *be, *dy, *r2, *l2, *h2, *g3, *g4;
+    const uint8_t* fixed;
+    double *c1, *c2, *dnl, *dnh, *partials;
+};
+
+__global__ void __launch_bounds__(kThreads) k_dnu(DnuArgs a) {
+    const int64_t m = (int64_t)a.nx * a.ny * a.nz;
+    const double da = a.dy[a.ndof];
+    double acc[1] = {0.0};
+    for (int64_t e = gid(); e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        elem_ijk(e, a.nx, a.ny, i, j, k);
+        double de[24];
+        gather_elem(a.dy, a.fixed, i, j, k, a.nx + 1, a.ny + 1, de);
+        double t = 0.0, q2 = 0.0;
+        for (int r = 0; r < 24; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < 24; ++q) s += a.Ke[r * 24 + q] * de[q];
+            q2 += de[r] * s;
+            t += a.be[r * m + e] * de[r];
+        }
+        a.c1[e] = t;
+        a.c2[e] = 0.5 * q2;
+        const double tau = t - da;
+        const double r2 = a.r2[e], l2 = a.l2[e], h2 = a.h2[e], g3 = a.g3[e], g4 = a.g4[e];
+        const double det = r2 * (l2 + h2) + l2 * h2;
+        const double dl = -((r2 + h2) * g3 + r2 * g4 + r2 * h2 * tau) / det;
+        const double dh = -(r2 * g3 + (r2 + l2) * g4 - r2 * l2 * tau) / det;
+        a.dnl[e] = dl;
+        a.dnh[e] = dh;
+        acc[0] += g3 * dl + g4 * dh;
+    }
+    block_sum_store<1>(acc, a.partials, SL_SLOPE_NU);
+}
+
+void launch_dnu(Ctx& c) {
+    DnuArgs a{c.nx, c.ny, c.nz, c.ndof, c.Ke, c.be, c.dy, c.r2, c.l2, c.h2, c.g3, c.g4,
+              c.fixed, c.c1, c.c2, c.dnl, c.dnh, c.partials};
+    const int g = red_grid(c.m);
+    hipLaunchKernelGGL(k_dnu, dim3(g), dim3(kThreads), 0, c.s, a);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c.s, c.partials, g,
+                       (int)SL_SLOPE_NU, 0u, c.red);
+}
+
+// Elementwise part of L(xi + k dxi) - L(xi), eq. (3.9), summed term by term:
+//   rho p (phi(s+) - phi(s)) + mu_lo q_lo (phi(t_lo+) - phi(t_lo)) + ...
+//   - k rho_lo dnu_lo + k rho_hi dnu_hi
+struct LsArgs {
+    int64_t m;
+    double kappa, alpha, dalpha;
+    const double *e, *c1, *c2, *nlo, *nhi, *dnl, *dnh, *rho, *mlo, *mhi, *p, *qlo, *qhi, *rlo,
+        *rhi;
+    double* partials;
+};
+
+__global__ void __launch_bounds__(kThreads) k_linesearch(LsArgs a) {
+    double acc[1] = {0.0};
+    const double k = a.kappa;
+    for (int64_t e = gid(); e < a.m; e += (int64_t)gridDim.x * blockDim.x) {
+        const double pe = a.p[e], ql = a.qlo[e], qh = a.qhi[e];
+        const double e0 = a.e[e], e1 = e0 + k * a.c1[e] + k * k * a.c2[e];
+        const double nl0 = a.nlo[e], nh0 = a.nhi[e];
+        const double nl1 = nl0 + k * a.dnl[e], nh1 = nh0 + k * a.dnh[e];
+        const double s0 = (e0 - a.alpha + nl0 - nh0) / pe;
+        const double s1 = (e1 - (a.alpha + k * a.dalpha) + nl1 - nh1) / pe;
+        double v = a.rho[e] * pe * (pen_phi(s1) - pen_phi(s0));
+        v += a.mlo[e] * ql * (pen_phi(-nl1 / ql) - pen_phi(-nl0 / ql));
+        v += a.mhi[e] * qh * (pen_phi(-nh1 / qh) - pen_phi(-nh0 / qh));
+        v += -a.rlo[e] * (nl1 - nl0) + a.rhi[e] * (nh1 - nh0);
+        acc[0] += v;
+    }
+    block_sum_store<1>(acc, a.partials, SL_LS);
+}
+
+void launch_linesearch(Ctx& c, double kappa, double dalpha) {
+    LsArgs a{c.m, kappa, c.alpha, dalpha, c.e, c.c1, c.c2, c.nlo, c.nhi, c.dnl, c.dnh, c.rho,
+             c.mlo, c.mhi, c.p, c.qlo, c.qhi, c.rlo, c.rhi, c.partials};
+    const int g = red_grid(c.m);
+    hipLaunchKernelGGL(k_linesearch, dim3(g), dim3(kThreads), 0, c.s, a);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c.s, c.partials, g, (int)SL_LS, 0u,
+                       c.red);
+}
+
+__global__ void k_update(int64_t ndof, int64_t m, double kappa, double* __restrict__ u,
+                         const double* __restrict__ dy, double* __restrict__ nlo,
+                         double* __restrict__ nhi, const double* __restrict__ dnl,
+                         const double* __restrict__ dnh) {
+    const int64_t t = gid();
+    if (t < ndof) u[t] += kappa * dy[t];
+    if (t < m) {
+        nlo[t] += kappa * dnl[t];
+        nhi[t] += kappa * dnh[t];
+    }
+}
+
+void launch_update(Ctx& c, double kappa) {
+    const int64_t n = c.ndof > c.m ? c.ndof : c.m;
+    hipLaunchKernelGGL(k_update, dim3(grid1d(n)), dim3(kThreads), 0, c.s, c.ndof, c.m, kappa, c.u,
+                       c.dy, c.nlo, c.nhi, c.dnl, c.dnh);
+}
+
+// ---------------------------------------------------------------------------
+// PBM outer step (Algorithm 1): gap (2.6) and dual objective parts, the
+// candidate rho+ = clip(rho phi'(s)) and its stationarity estimate.
+// ---------------------------------------------------------------------------
+struct OuterArgs {
+    int64_t m;
+    double alpha, beta;
+    const double *e, *nlo, *nhi, *rho, *p, *rlo, *rhi;
+    double* partials;
+};
+
+__global__ void __launch_bounds__(kThreads) k_outer(OuterArgs a) {
+    // slots: GAP (sum min), NLO (rlo.nlo), NHI (rhi.nhi), STAT (max), SUM_RHO
+    double acc[5] = {0, 0, 0, -DBL_MAX, 0};
+    for (int64_t e = gid(); e < a.m; e += (int64_t)gridDim.x * blockDim.x) {
+        const double d = a.alpha - a.e[e];
+        acc[0] += fmin(a.rlo[e] * d, a.rhi[e] * d);
+        acc[1] += a.rlo[e] * a.nlo[e];
+        acc[2] += a.rhi[e] * a.nhi[e];
+        const double s = (a.e[e] - a.alpha + a.nlo[e] - a.nhi[e]) / a.p[e];
+        const double r = a.rho[e];
+        const double rp = fmin(fmax(r * pen_dphi(s), a.beta * r), r / a.beta);
+        const double proj = fmin(fmax(rp + (a.e[e] - a.alpha) / a.alpha, a.rlo[e]), a.rhi[e]);
+        acc[3] = fmax(acc[3], fabs(rp - proj) / a.rhi[e]);
+        acc[4] += r;
+    }
+    block_sum_store<5>(acc, a.partials, SL_GAP, 1u << 3);
+}
+
+void launch_outer_eval(Ctx& c) {
+    OuterArgs a{c.m, c.alpha, c.opt.beta, c.e, c.nlo, c.nhi, c.rho, c.p, c.rlo, c.rhi, c.partials};
+    const int g = red_grid(c.m);
+    hipLaunchKernelGGL(k_outer, dim3(g), dim3(kThreads), 0, c.s, a);
+    hipLaunchKernelGGL(k_finalize, dim3(5), dim3(kThreads), 0, c.s, c.partials, g, (int)SL_GAP,
+                       1u << 3, c.red);
+}
+
+// Multiplier update of Algorithm 1 with the safeguard beta x <= x+ <= x/beta.
+__global__ void k_mult(int64_t m, double alpha, double beta, int rho_only,
+                       const double* __restrict__ e, const double* __restrict__ nlo,
+                       const double* __restrict__ nhi, const double* __restrict__ p,
+                       const double* __restrict__ qlo, const double* __restrict__ qhi,
+                       double* __restrict__ rho, double* __restrict__ mlo,
+                       double* __restrict__ mhi) {
+    const int64_t t = gid();
+    if (t >= m) return;
+    const double s = (e[t] - alpha + nlo[t] - nhi[t]) / p[t];
+    const double r = rho[t];
+    rho[t] = fmin(fmax(r * pen_dphi(s), beta * r), r / beta);
+    if (rho_only) return;
+    const double a = mlo[t], b = mhi[t];
+    mlo[t] = fmin(fmax(a * pen_dphi(-nlo[t] / qlo[t]), beta * a), a / beta);
+    mhi[t] = fmin(fmax(b * pen_dphi(-nhi[t] / qhi[t]), beta * b), b / beta);
+}
+
+void launch_mult_update(Ctx& c, int rho_only) {
+    hipLaunchKernelGGL(k_mult, dim3(grid1d(c.m)), dim3(kThreads), 0, c.s, c.m, c.alpha,
+                       c.opt.beta, rho_only, c.e, c.nlo, c.nhi, c.p, c.qlo, c.qhi, c.rho, c.mlo,
+                       c.mhi);
+}
+
+__global__ void k_penalty(int64_t m, double gamma, double pmin, double* __restrict__ p,
+                          double* __restrict__ qlo, double* __restrict__ qhi) {
+    const int64_t t = gid();
+    if (t >= m) return;
+    p[t] = fmax(gamma * p[t], pmin);
+    qlo[t] = fmax(gamma * qlo[t], pmin);
+    qhi[t] = fmax(gamma * qhi[t], pmin);
+}
+
+void launch_penalty_update(Ctx& c) {
+    hipLaunchKernelGGL(k_penalty, dim3(grid1d(c.m)), dim3(kThreads), 0, c.s, c.m, c.opt.gamma,
+                       c.opt.p_min, c.p, c.qlo, c.qhi);
+}
+
+__global__ void k_init(int64_t ndof, int64_t m, double rho0, double* u, double* nlo,
+                       double* nhi, double* rho, double* mlo, double* mhi, double* p,
+                       double* qlo, double* qhi) {
+    const int64_t t = gid();
+    if (t < ndof) u[t] = 0.0;
+    if (t < m) {
+        nlo[t] = 1.0; nhi[t] = 1.0; rho[t] = rho0; mlo[t] = 1.0; mhi[t] = 1.0;
+        p[t] = 1.0; qlo[t] = 1.0; qhi[t] = 1.0;
+    }
+}
+
+void launch_init_state(Ctx& c) {
+    const int64_t n = c.ndof > c.m ? c.ndof : c.m;
+    hipLaunchKernelGGL(k_init, dim3(grid1d(n)), dim3(kThreads), 0, c.s, c.ndof, c.m,
+                       c.V / (double)c.m, c.u, c.nlo, c.nhi, c.rho, c.mlo, c.mhi, c.p, c.qlo,
+                       c.qhi);
+}
+
+__global__ void k_round(int64_t m, const double* __restrict__ a, float* __restrict__ b) {
+    const int64_t t = gid();
+    if (t < m) b[t] = (float)a[t];
+}
+void launch_round_rho(Ctx& c) {
+    hipLaunchKernelGGL(k_round, dim3(grid1d(c.m)), dim3(kThreads), 0, c.s, c.m, c.rho, c.rhof);
+}
+
+// ---------------------------------------------------------------------------
+// vector kernels (MINRES)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads)
+k_dot(const double* __restrict__ x, const double* __restrict__ y, int64_t n, int slot,
+      double* partials) {
+    double acc[1] = {0.0};
+    for (int64_t t = gid(); t < n; t += (int64_t)gridDim.x * blockDim.x) acc[0] += x[t] * y[t];
+    block_sum_store<1>(acc, partials, slot);
+}
+
+void launch_dot(Ctx& c, const double* x, const double* y, int64_t n, int slot) {
+    const int g = red_grid(n);
+    hipLaunchKernelGGL(k_dot, dim3(g), dim3(kThreads), 0, c.s, x, y, n, slot, c.partials);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c.s, c.partials, g, slot, 0u,
+                       c.red);
+}
+
+__global__ void k_copy1(const double* __restrict__ src, double* __restrict__ dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = src[0];
+}
+void launch_copy1(Ctx& c, const double* src, double* dst) {
+    hipLaunchKernelGGL(k_copy1, dim3(1), dim3(64), 0, c.s, src, dst);
+}
+
+__global__ void k_set(double* dst, double v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = v;
+}
+void launch_set(Ctx& c, double* dst, double v) {
+    hipLaunchKernelGGL(k_set, dim3(1), dim3(64), 0, c.s, dst, v);
+}
+
+__global__ void k_fill(double* __restrict__ d, double v, int64_t n) {
+    const int64_t t = gid();
+    if (t < n) d[t] = v;
+}
+void launch_fill(Ctx& c, double* dst, double v, int64_t n) {
+    hipLaunchKernelGGL(k_fill, dim3(grid1d(n)), dim3(kThreads), 0, c.s, dst, v, n);
+}
+
+__global__ void k_scale(double* __restrict__ d, const double* __restrict__ s, double a,
+                        int64_t n) {
+    const int64_t t = gid();
+    if (t < n) d[t] = a * s[t];
+}
+void launch_scale(Ctx& c, double* dst, const double* src, double a, int64_t n) {
+    hipLaunchKernelGGL(k_scale, dim3(grid1d(n)), dim3(kThreads), 0, c.s, dst, src, a, n);
+}
+
+__global__ void k_axpy(double* __restrict__ y, double a, const double* __restrict__ x,
+                       int64_t n) {
+    const int64_t t = gid();
+    if (t < n) y[t] += a * x[t];
+}
+void launch_axpy(Ctx& c, double* y, double a, const double* x, int64_t n) {
+    hipLaunchKernelGGL(k_axpy, dim3(grid1d(n)), dim3(kThreads), 0, c.s, y, a, x, n);
+}
+
+// w = (v - eps_old w1 - delta w2) / gamma ; x += phi w
+__global__ void k_minres_w(double* __restrict__ w, const double* __restrict__ v,
+                           const double* __restrict__ w1, const double* __restrict__ w2,
+                           double eps_old, double delta, double inv_gamma,
+                           double* __restrict__ x, double phi, int64_t n) {
+    const int64_t t = gid();
+    if (t >= n) return;
+    const double wn = (v[t] - eps_old * w1[t] - delta * w2[t]) * inv_gamma;
+    w[t] = wn;
+    x[t] += phi * wn;
+}
+void launch_minres_w(Ctx& c, double* w, const double* v, const double* w1, const double* w2,
+                     double eps_old, double delta, double inv_gamma, double* x, double phi,
+                     int64_t n) {
+    hipLaunchKernelGGL(k_minres_w, dim3(grid1d(n)), dim3(kThreads), 0, c.s, w, v, w1, w2,
+                       eps_old, delta, inv_gamma, x, phi, n);
+}
+
+}  // namespace vts

@@ -1,0 +1,708 @@
+// Geometric multigrid for the reduced Newton matrix S of eq. (3.12)
+// (Section 6.1: V-cycle correction scheme, Galerkin coarse operators,
+// Gauss-Seidel smoothing; Section 6.2: 27-point trilinear prolongation,
+// identity transfer of the scalar alpha).
+//
+// Each level's displacement block is stored as an assembled 27-point
+// stencil of 3x3 blocks in colour-major node order (colour = parity
+// (i&1) + 2(j&1) + 4(k&1)), so one Gauss-Seidel colour pass reads its
+// nodes' rows with unit stride.  Coarse operators are built element by
+// element: E_parent = sum_children Q_c^T E_child Q_c, which equals P^T A P
+// because each fine element lies in one coarse element and trilinear
+// interpolation restricted to it is the local map Q_c.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "vts_internal.hpp"
+
+namespace vts {
+
+namespace {
+
+__device__ __forceinline__ int64_t gidx() {
+    return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+}
+inline int grid_of(int64_t n) {
+    int64_t b = (n + kThreads - 1) / kThreads;
+    return (int)(b < 1 ? 1 : b);
+}
+inline int red_grid_of(int64_t n) {
+    int64_t b = (n + kThreads - 1) / kThreads;
+    if (b < 1) b = 1;
+    return (int)(b < kRedBlocks ? b : kRedBlocks);
+}
+
+template <typename T>
+__device__ __forceinline__ void cm_decode(const Level<T>& L, int64_t t, int& i, int& j, int& k) {
+    int col = 0;
+    while (col < 7 && t >= L.coff[col + 1]) ++col;
+    int64_t tl = t - L.coff[col];
+    const int cx = L.cnx[col], cy = L.cny[col];
+    i = 2 * (int)(tl % cx) + (col & 1);
+    tl /= cx;
+    j = 2 * (int)(tl % cy) + ((col >> 1) & 1);
+    k = 2 * (int)(tl / cy) + (col >> 2);
+}
+
+__device__ __forceinline__ int64_t nat(int i, int j, int k, int NX, int NY) {
+    return (int64_t)i + (int64_t)NX * ((int64_t)j + (int64_t)NY * k);
+}
+
+// inverse of the free sub-block of a 3x3 block (identity on fixed components,
+// then zeroed there)
+__device__ void masked_inverse3(const double (&D0)[9], const bool (&fx)[3], double (&Di)[9]) {
+    double D[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double v = D0[r * 3 + c];
+            if (fx[r] || fx[c]) v = (r == c) ? 1.0 : 0.0;
+            D[r * 3 + c] = v;
+        }
+    const double c00 = D[4] * D[8] - D[5] * D[7];
+    const double c01 = D[5] * D[6] - D[3] * D[8];
+    const double c02 = D[3] * D[7] - D[4] * D[6];
+    const double det = D[0] * c00 + D[1] * c01 + D[2] * c02;
+    const double id = 1.0 / det;
+    Di[0] = c00 * id;
+    Di[1] = (D[2] * D[7] - D[1] * D[8]) * id;
+    Di[2] = (D[1] * D[5] - D[2] * D[4]) * id;
+    Di[3] = c01 * id;
+    Di[4] = (D[0] * D[8] - D[2] * D[6]) * id;
+    Di[5] = (D[2] * D[3] - D[0] * D[5]) * id;
+    Di[6] = c02 * id;
+    Di[7] = (D[1] * D[6] - D[0] * D[7]) * id;
+    Di[8] = (D[0] * D[4] - D[1] * D[3]) * id;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            if (fx[r] || fx[c]) Di[r * 3 + c] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// finest level: stencil of K(rho') + sum_e w_e b_e b_e^T from (rho', w, b),
+// its inverse diagonal blocks, and the alpha column -sum_e w_e b_e
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_fine_stencil(Level<T> L, const double* __restrict__ Ke, const double* __restrict__ r1,
+               const double* __restrict__ w, const double* __restrict__ be) {
+    const int64_t t = gidx();
+    if (t >= L.nn) return;
+    int i, j, k;
+    cm_decode(L, t, i, j, k);
+    const int64_t n = nat(i, j, k, L.NX, L.NY);
+    const int64_t m = L.m;
+    double diag[9] = {0};
+    for (int s = 0; s < kStencil; ++s) {
+        const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+        double blk[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        const bool inside = (i + dx >= 0 && i + dx < L.NX && j + dy >= 0 && j + dy < L.NY &&
+                             k + dz >= 0 && k + dz < L.NZ);
+        if (inside) {
+            for (int ez = -1; ez <= 0; ++ez)
+                for (int ey = -1; ey <= 0; ++ey)
+                    for (int ex = -1; ex <= 0; ++ex) {
+                        const int ii = i + ex, jj = j + ey, kk = k + ez;
+                        if (ii < 0 || ii >= L.nx || jj < 0 || jj >= L.ny || kk < 0 || kk >= L.nz)
+                            continue;
+                        const int bx = dx - ex, by = dy - ey, bz = dz - ez;
+                        if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
+                        const int64_t e = ii + (int64_t)L.nx * (jj + (int64_t)L.ny * kk);
+                        const int la = -ex - 2 * ey - 4 * ez, lb = bx + 2 * by + 4 * bz;
+                        const double rr = r1[e], ww = w[e];
+                        for (int r = 0; r < 3; ++r) {
+                            const double wb = ww * be[(3 * la + r) * m + e];
+                            for (int c = 0; c < 3; ++c)
+                                blk[r * 3 + c] += rr * Ke[(3 * la + r) * 24 + 3 * lb + c] +
+                                                  wb * be[(3 * lb + c) * m + e];
+                        }
+                    }
+        }
+        for (int q = 0; q < 9; ++q) L.st[(int64_t)(s * 9 + q) * L.nn + t] = (T)blk[q];
+        if (s == 13)
+            for (int q = 0; q < 9; ++q) diag[q] = blk[q];
+    }
+    bool fx[3];
+    for (int c = 0; c < 3; ++c) fx[c] = L.fixed[3 * n + c] != 0;
+    // diagonal from the rounded values so that both precisions smooth with
+    // the inverse of the matrix they apply
+    double d0[9];
+    for (int q = 0; q < 9; ++q) d0[q] = (double)(T)diag[q];
+    double di[9];
+    masked_inverse3(d0, fx, di);
+    for (int q = 0; q < 9; ++q) L.dinv[(int64_t)q * L.nn + t] = (T)di[q];
+    double ac[3] = {0, 0, 0};
+    for (int ez = -1; ez <= 0; ++ez)
+        for (int ey = -1; ey <= 0; ++ey)
+            for (int ex = -1; ex <= 0; ++ex) {
+                const int ii = i + ex, jj = j + ey, kk = k + ez;
+                if (ii < 0 || ii >= L.nx || jj < 0 || jj >= L.ny || kk < 0 || kk >= L.nz) continue;
+                const int64_t e = ii + (int64_t)L.nx * (jj + (int64_t)L.ny * kk);
+                const int la = -ex - 2 * ey - 4 * ez;
+                for (int c = 0; c < 3; ++c) ac[c] -= w[e] * be[(3 * la + c) * m + e];
+            }
+    for (int c = 0; c < 3; ++c) L.acol[3 * n + c] = fx[c] ? T(0) : (T)ac[c];
+}
+
+// g_e = Q_{c(e)}^T b_e: the element force seen from the parent element's nodes
+__global__ void k_child_g(int nx, int ny, int nz, const double* __restrict__ Q,
+                          const double* __restrict__ be, double* __restrict__ gch) {
+    const int64_t m = (int64_t)nx * ny * nz;
+    const int64_t e = gidx();
+    if (e >= m) return;
+    const int i = (int)(e % nx);
+    const int64_t tt = e / nx;
+    const int j = (int)(tt % ny), k = (int)(tt / ny);
+    const int c = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+    for (int A = 0; A < 8; ++A)
+        for (int comp = 0; comp < 3; ++comp) {
+            double s = 0.0;
+            for (int a = 0; a < 8; ++a) s += Q[(c * 8 + a) * 8 + A] * be[(3 * a + comp) * m + e];
+            gch[(3 * A + comp) * m + e] = s;
+        }
+}
+
+// first coarse level: E_C = sum_c rho'_c M_c + w_c g_c g_c^T, one row per thread
+template <typename T>
+__global__ void k_coarse_first(Level<T> C, int fnx, int fny, int fnz, const double* __restrict__ Mc,
+                               const double* __restrict__ r1, const double* __restrict__ w,
+                               const double* __restrict__ gch) {
+    const int64_t t = gidx();
+    if (t >= C.m * 24) return;
+    const int64_t ec = t / 24;
+    const int R = (int)(t % 24);
+    const int I = (int)(ec % C.nx);
+    const int64_t tt = ec / C.nx;
+    const int J = (int)(tt % C.ny), K = (int)(tt / C.ny);
+    const int64_t mf = (int64_t)fnx * fny * fnz;
+    double row[24];
+    for (int q = 0; q < 24; ++q) row[q] = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        const int64_t ef = (2 * I + (c & 1)) + (int64_t)fnx * ((2 * J + ((c >> 1) & 1)) +
+                                                                (int64_t)fny * (2 * K + (c >> 2)));
+        const double rr = r1[ef];
+        const double wg = w[ef] * gch[(int64_t)R * mf + ef];
+        const double* M = Mc + c * 576 + R * 24;
+        for (int q = 0; q < 24; ++q) row[q] += rr * M[q] + wg * gch[(int64_t)q * mf + ef];
+    }
+    T* out = C.E + ec * 576 + R * 24;
+    for (int q = 0; q < 24; ++q) out[q] = (T)row[q];
+}
+
+// TQ_e = E_e (Q_c x I3) for every element e of level F (its parent is on the
+// next coarser level); one row per thread
+template <typename T>
+__global__ void k_coarsen_tq(Level<T> F, const double* __restrict__ Q) {
+    const int64_t t = gidx();
+    if (t >= F.m * 24) return;
+    const int64_t e = t / 24;
+    const int r = (int)(t % 24);
+    const int i = (int)(e % F.nx);
+    const int64_t tt = e / F.nx;
+    const int j = (int)(tt % F.ny), k = (int)(tt / F.ny);
+    const int c = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+    const T* Er = F.E + e * 576 + r * 24;
+    double x[24];
+    for (int q = 0; q < 24; ++q) x[q] = (double)Er[q];
+    T* out = F.TQ + e * 576 + r * 24;
+    for (int A = 0; A < 8; ++A)
+        for (int comp = 0; comp < 3; ++comp) {
+            double s = 0.0;
+            for (int a = 0; a < 8; ++a) s += x[3 * a + comp] * Q[(c * 8 + a) * 8 + A];
+            out[3 * A + comp] = (T)s;
+        }
+}
+
+// E_C[R, :] = sum_c sum_a Q_c[a][A] TQ_c[3a+comp, :],  R = 3A + comp
+template <typename T>
+__global__ void k_coarsen_e(Level<T> C, Level<T> F, const double* __restrict__ Q) {
+    const int64_t t = gidx();
+    if (t >= C.m * 24) return;
+    const int64_t ec = t / 24;
+    const int R = (int)(t % 24);
+    const int A = R / 3, comp = R % 3;
+    const int I = (int)(ec % C.nx);
+    const int64_t tt = ec / C.nx;
+    const int J = (int)(tt % C.ny), K = (int)(tt / C.ny);
+    double row[24];
+    for (int q = 0; q < 24; ++q) row[q] = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        const int64_t ef = (2 * I + (c & 1)) + (int64_t)F.nx * ((2 * J + ((c >> 1) & 1)) +
+                                                                 (int64_t)F.ny * (2 * K + (c >> 2)));
+        for (int a = 0; a < 8; ++a) {
+            const double qa = Q[(c * 8 + a) * 8 + A];
+            if (qa == 0.0) continue;
+            const T* src = F.TQ + ef * 576 + (3 * a + comp) * 24;
+            for (int q = 0; q < 24; ++q) row[q] += qa * (double)src[q];
+        }
+    }
+    T* out = C.E + ec * 576 + R * 24;
+    for (int q = 0; q < 24; ++q) out[q] = (T)row[q];
+}
+
+// coarse level stencil and inverse diagonal blocks from element matrices
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_elem_stencil(Level<T> L) {
+    const int64_t t = gidx();
+    if (t >= L.nn) return;
+    int i, j, k;
+    cm_decode(L, t, i, j, k);
+    const int64_t n = nat(i, j, k, L.NX, L.NY);
+    double diag[9] = {0};
+    for (int s = 0; s < kStencil; ++s) {
+        const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+        double blk[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int ez = -1; ez <= 0; ++ez)
+            for (int ey = -1; ey <= 0; ++ey)
+                for (int ex = -1; ex <= 0; ++ex) {
+                    const int ii = i + ex, jj = j + ey, kk = k + ez;
+                    if (ii < 0 || ii >= L.nx || jj < 0 || jj >= L.ny || kk < 0 || kk >= L.nz)
+                        continue;
+                    const int bx = dx - ex, by = dy - ey, bz = dz - ez;
+                    if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
+                    const int64_t e = ii + (int64_t)L.nx * (jj + (int64_t)L.ny * kk);
+                    const int la = -ex - 2 * ey - 4 * ez, lb = bx + 2 * by + 4 * bz;
+                    const T* Ee = L.E + e * 576;
+                    for (int r = 0; r < 3; ++r)
+                        for (int c = 0; c < 3; ++c)
+                            blk[r * 3 + c] += (double)Ee[(3 * la + r) * 24 + 3 * lb + c];
+                }
+        for (int q = 0; q < 9; ++q) L.st[(int64_t)(s * 9 + q) * L.nn + t] = (T)blk[q];
+        if (s == 13)
+            for (int q = 0; q < 9; ++q) diag[q] = blk[q];
+    }
+    bool fx[3];
+    for (int c = 0; c < 3; ++c) fx[c] = L.fixed[3 * n + c] != 0;
+    double d0[9];
+    for (int q = 0; q < 9; ++q) d0[q] = (double)(T)diag[q];
+    double di[9];
+    masked_inverse3(d0, fx, di);
+    for (int q = 0; q < 9; ++q) L.dinv[(int64_t)q * L.nn + t] = (T)di[q];
+}
+
+// ---------------------------------------------------------------------------
+// smoothing and residual
+// ---------------------------------------------------------------------------
+// One colour of nodal block Gauss-Seidel: z_n += D_n^{-1} (r - S z)_n for every
+// node of colour `col` (no two nodes of one colour share an element).
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_gs_color(Level<T> L, int col, const T* __restrict__ r, T* __restrict__ z) {
+    const int64_t tl = gidx();
+    const int64_t cnt = L.coff[col + 1] - L.coff[col];
+    if (tl >= cnt) return;
+    const int64_t t = L.coff[col] + tl;
+    int64_t q = tl;
+    const int i = 2 * (int)(q % L.cnx[col]) + (col & 1);
+    q /= L.cnx[col];
+    const int j = 2 * (int)(q % L.cny[col]) + ((col >> 1) & 1);
+    const int k = 2 * (int)(q / L.cny[col]) + (col >> 2);
+    const int64_t n = nat(i, j, k, L.NX, L.NY);
+    const T za = z[3 * L.nn];
+    T a0 = r[3 * n] - L.acol[3 * n] * za;
+    T a1 = r[3 * n + 1] - L.acol[3 * n + 1] * za;
+    T a2 = r[3 * n + 2] - L.acol[3 * n + 2] * za;
+    for (int s = 0; s < kStencil; ++s) {
+        const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+        const int ii = i + dx, jj = j + dy, kk = k + dz;
+        if (ii < 0 || ii >= L.NX || jj < 0 || jj >= L.NY || kk < 0 || kk >= L.NZ) continue;
+        const int64_t mm = nat(ii, jj, kk, L.NX, L.NY);
+        const T x0 = z[3 * mm], x1 = z[3 * mm + 1], x2 = z[3 * mm + 2];
+        const T* S = L.st + (int64_t)(s * 9) * L.nn + t;
+        a0 -= S[0] * x0 + S[L.nn] * x1 + S[2 * L.nn] * x2;
+        a1 -= S[3 * L.nn] * x0 + S[4 * L.nn] * x1 + S[5 * L.nn] * x2;
+        a2 -= S[6 * L.nn] * x0 + S[7 * L.nn] * x1 + S[8 * L.nn] * x2;
+    }
+    const T* D = L.dinv + t;
+    const int64_t N = L.nn;
+    z[3 * n] += D[0] * a0 + D[N] * a1 + D[2 * N] * a2;
+    z[3 * n + 1] += D[3 * N] * a0 + D[4 * N] * a1 + D[5 * N] * a2;
+    z[3 * n + 2] += D[6 * N] * a0 + D[7 * N] * a1 + D[8 * N] * a2;
+}
+
+// res = r - S z (displacement part, masked) and partial sums of acol . z
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_resid(Level<T> L, const T* __restrict__ r, const T* __restrict__ z, T* __restrict__ res,
+        double* partials) {
+    double acc = 0.0;
+    const T za = z[3 * L.nn];
+    for (int64_t t = gidx(); t < L.nn; t += (int64_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        cm_decode(L, t, i, j, k);
+        const int64_t n = nat(i, j, k, L.NX, L.NY);
+        T a0 = r[3 * n] - L.acol[3 * n] * za;
+        T a1 = r[3 * n + 1] - L.acol[3 * n + 1] * za;
+        T a2 = r[3 * n + 2] - L.acol[3 * n + 2] * za;
+        for (int s = 0; s < kStencil; ++s) {
+            const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+            const int ii = i + dx, jj = j + dy, kk = k + dz;
+            if (ii < 0 || ii >= L.NX || jj < 0 || jj >= L.NY || kk < 0 || kk >= L.NZ) continue;
+            const int64_t mm = nat(ii, jj, kk, L.NX, L.NY);
+            const T x0 = z[3 * mm], x1 = z[3 * mm + 1], x2 = z[3 * mm + 2];
+            const T* S = L.st + (int64_t)(s * 9) * L.nn + t;
+            a0 -= S[0] * x0 + S[L.nn] * x1 + S[2 * L.nn] * x2;
+            a1 -= S[3 * L.nn] * x0 + S[4 * L.nn] * x1 + S[5 * L.nn] * x2;
+            a2 -= S[6 * L.nn] * x0 + S[7 * L.nn] * x1 + S[8 * L.nn] * x2;
+        }
+        res[3 * n] = L.fixed[3 * n] ? T(0) : a0;
+        res[3 * n + 1] = L.fixed[3 * n + 1] ? T(0) : a1;
+        res[3 * n + 2] = L.fixed[3 * n + 2] ? T(0) : a2;
+        acc += (double)L.acol[3 * n] * z[3 * n] + (double)L.acol[3 * n + 1] * z[3 * n + 1] +
+               (double)L.acol[3 * n + 2] * z[3 * n + 2];
+    }
+    __shared__ double sh[kThreads];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[SL_AUX * kRedBlocks + blockIdx.x] = sh[0];
+}
+
+// partial sums of acol . z
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_acol_dot(Level<T> L, const T* __restrict__ z, double* partials) {
+    double acc = 0.0;
+    for (int64_t q = gidx(); q < 3 * L.nn; q += (int64_t)gridDim.x * blockDim.x)
+        acc += (double)L.acol[q] * (double)z[q];
+    __shared__ double sh[kThreads];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[SL_AUX * kRedBlocks + blockIdx.x] = sh[0];
+}
+
+// Sum the partials, then either the Gauss-Seidel update of alpha
+// (mode 0: z_a += (r_a - acol.z - d z_a)/d) or the alpha residual
+// (mode 1: res_a = r_a - acol.z - d z_a).
+template <typename T>
+__global__ void k_alpha_fin(const double* __restrict__ partials, int nb, int64_t nn, double d,
+                            const T* __restrict__ r, T* __restrict__ z, T* __restrict__ res,
+                            int mode) {
+    __shared__ double sh[kThreads];
+    double x = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) x += partials[SL_AUX * kRedBlocks + b];
+    sh[threadIdx.x] = x;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const T td = (T)d;
+        const T dot = (T)sh[0];
+        const T v = r[3 * nn] - dot - td * z[3 * nn];
+        if (mode == 0)
+            z[3 * nn] += v / td;
+        else
+            res[3 * nn] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// transfers (Section 6.2): trilinear prolongation P, restriction P^T,
+// identity on alpha
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_restrict(Level<T> F, Level<T> C, const T* __restrict__ rf, T* __restrict__ rc, int with_alpha) {
+    const int64_t N = gidx();
+    if (N >= C.nn) return;
+    const int I = (int)(N % C.NX);
+    const int64_t tt = N / C.NX;
+    const int J = (int)(tt % C.NY), K = (int)(tt / C.NY);
+    T a0 = 0, a1 = 0, a2 = 0;
+    for (int dk = -1; dk <= 1; ++dk) {
+        const int k = 2 * K + dk;
+        if (k < 0 || k >= F.NZ) continue;
+        const T wk = dk ? T(0.5) : T(1);
+        for (int dj = -1; dj <= 1; ++dj) {
+            const int j = 2 * J + dj;
+            if (j < 0 || j >= F.NY) continue;
+            const T wj = dj ? T(0.5) : T(1);
+            for (int di = -1; di <= 1; ++di) {
+                const int i = 2 * I + di;
+                if (i < 0 || i >= F.NX) continue;
+                const T wgt = wk * wj * (di ? T(0.5) : T(1));
+                const int64_t n = nat(i, j, k, F.NX, F.NY);
+                a0 += wgt * rf[3 * n];
+                a1 += wgt * rf[3 * n + 1];
+                a2 += wgt * rf[3 * n + 2];
+            }
+        }
+    }
+    rc[3 * N] = C.fixed[3 * N] ? T(0) : a0;
+    rc[3 * N + 1] = C.fixed[3 * N + 1] ? T(0) : a1;
+    rc[3 * N + 2] = C.fixed[3 * N + 2] ? T(0) : a2;
+    if (with_alpha && N == 0) rc[3 * C.nn] = rf[3 * F.nn];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_prolong_add(Level<T> C, Level<T> F, const T* __restrict__ zc, T* __restrict__ zf) {
+    const int64_t n = gidx();
+    if (n >= F.nn) return;
+    const int i = (int)(n % F.NX);
+    const int64_t tt = n / F.NX;
+    const int j = (int)(tt % F.NY), k = (int)(tt / F.NY);
+    const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1,
+              k1 = (k + 1) >> 1;
+    const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
+    T a0 = 0, a1 = 0, a2 = 0;
+    for (int b = 0; b < 8; ++b) {
+        const int I = (b & 1) ? i1 : i0, J = ((b >> 1) & 1) ? j1 : j0, K = (b >> 2) ? k1 : k0;
+        // an even index has a single parent: count it once
+        if ((b & 1) && !(i & 1)) continue;
+        if (((b >> 1) & 1) && !(j & 1)) continue;
+        if ((b >> 2) && !(k & 1)) continue;
+        const int64_t N = nat(I, J, K, C.NX, C.NY);
+        const T wgt = wi * wj * wk;
+        a0 += wgt * zc[3 * N];
+        a1 += wgt * zc[3 * N + 1];
+        a2 += wgt * zc[3 * N + 2];
+    }
+    if (!F.fixed[3 * n]) zf[3 * n] += a0;
+    if (!F.fixed[3 * n + 1]) zf[3 * n + 1] += a1;
+    if (!F.fixed[3 * n + 2]) zf[3 * n + 2] += a2;
+    if (n == 0) zf[3 * F.nn] += zc[3 * C.nn];
+}
+
+// ---------------------------------------------------------------------------
+// coarsest level: dense S_1 on (free DOFs, alpha), Cholesky, solve (FP64)
+// ---------------------------------------------------------------------------
+__global__ void k_zero(double* a, int64_t n) {
+    const int64_t t = gidx();
+    if (t < n) a[t] = 0.0;
+}
+
+template <typename T>
+__global__ void k_coarse_assemble(Level<T> L, const int* __restrict__ cmap, int nc, double d,
+                                  double* __restrict__ A) {
+    const int64_t g = gidx();
+    if (g >= L.nn * kStencil) return;
+    const int64_t t = g / kStencil;
+    const int s = (int)(g % kStencil);
+    int i, j, k;
+    cm_decode(L, t, i, j, k);
+    const int64_t n = nat(i, j, k, L.NX, L.NY);
+    const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+    const int ii = i + dx, jj = j + dy, kk = k + dz;
+    if (ii >= 0 && ii < L.NX && jj >= 0 && jj < L.NY && kk >= 0 && kk < L.NZ) {
+        const int64_t mm = nat(ii, jj, kk, L.NX, L.NY);
+        for (int r = 0; r < 3; ++r) {
+            const int row = cmap[3 * n + r];
+            if (row < 0) continue;
+            for (int c = 0; c < 3; ++c) {
+                const int col = cmap[3 * mm + c];
+                if (col < 0) continue;
+                A[(int64_t)row * nc + col] = (double)L.st[(int64_t)(s * 9 + r * 3 + c) * L.nn + t];
+            }
+        }
+    }
+    if (s == 0) {
+        for (int r = 0; r < 3; ++r) {
+            const int row = cmap[3 * n + r];
+            if (row < 0) continue;
+            const double v = (double)L.acol[3 * n + r];
+            A[(int64_t)row * nc + nc - 1] = v;
+            A[(int64_t)(nc - 1) * nc + row] = v;
+        }
+    }
+    if (g == 0) A[(int64_t)(nc - 1) * nc + nc - 1] = d;
+}
+
+// in-place lower Cholesky, one block; flag = 1 on a non-positive pivot
+__global__ void __launch_bounds__(1024) k_cholesky(double* __restrict__ A, int nc, int* flag) {
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int k = 0; k < nc; ++k) {
+        if (threadIdx.x == 0) {
+            const double akk = A[(int64_t)k * nc + k];
+            if (!(akk > 0.0)) {
+                bad = 1;
+                A[(int64_t)k * nc + k] = 1.0;
+            } else {
+                A[(int64_t)k * nc + k] = sqrt(akk);
+            }
+        }
+        __syncthreads();
+        const double dkk = A[(int64_t)k * nc + k];
+        for (int i = k + 1 + threadIdx.x; i < nc; i += blockDim.x) A[(int64_t)i * nc + k] /= dkk;
+        __syncthreads();
+        const int T = nc - k - 1;
+        for (int p = threadIdx.x; p < T * T; p += blockDim.x) {
+            const int i = k + 1 + p / T, j = k + 1 + p % T;
+            if (j <= i) A[(int64_t)i * nc + j] -= A[(int64_t)i * nc + k] * A[(int64_t)j * nc + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *flag = bad;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_coarse_solve(const double* __restrict__ A, int nc, const int* __restrict__ cmap, int64_t nn,
+               const T* __restrict__ r, T* __restrict__ z) {
+    __shared__ double x[kMaxCoarse];
+    for (int64_t q = threadIdx.x; q < 3 * nn; q += blockDim.x) {
+        const int c = cmap[q];
+        if (c >= 0) x[c] = (double)r[q];
+    }
+    if (threadIdx.x == 0) x[nc - 1] = (double)r[3 * nn];
+    __syncthreads();
+    for (int k = 0; k < nc; ++k) {
+        if (threadIdx.x == 0) x[k] /= A[(int64_t)k * nc + k];
+        __syncthreads();
+        const double xk = x[k];
+        for (int i = k + 1 + threadIdx.x; i < nc; i += blockDim.x) x[i] -= A[(int64_t)i * nc + k] * xk;
+        __syncthreads();
+    }
+    for (int k = nc - 1; k >= 0; --k) {
+        if (threadIdx.x == 0) x[k] /= A[(int64_t)k * nc + k];
+        __syncthreads();
+        const double xk = x[k];
+        for (int i = threadIdx.x; i < k; i += blockDim.x) x[i] -= A[(int64_t)k * nc + i] * xk;
+        __syncthreads();
+    }
+    for (int64_t q = threadIdx.x; q < 3 * nn; q += blockDim.x) {
+        const int c = cmap[q];
+        z[q] = c >= 0 ? (T)x[c] : T(0);
+    }
+    if (threadIdx.x == 0) z[3 * nn] = (T)x[nc - 1];
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_convert(const Tin* __restrict__ a, Tout* __restrict__ b, int64_t n) {
+    const int64_t t = gidx();
+    if (t < n) b[t] = (Tout)a[t];
+}
+
+template <typename T>
+__global__ void k_zero_t(T* a, int64_t n) {
+    const int64_t t = gidx();
+    if (t < n) a[t] = T(0);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host drivers
+// ---------------------------------------------------------------------------
+template <typename T>
+void mg_build(Ctx& c, Hierarchy<T>& H) {
+    const int L = (int)H.lev.size();
+    Level<T>& fine = H.lev[L - 1];
+    hipLaunchKernelGGL(k_fine_stencil<T>, dim3(grid_of(fine.nn)), dim3(kThreads), 0, c.s, fine,
+                       c.Ke, c.r1, c.w, c.be);
+    if (L >= 2) {
+        hipLaunchKernelGGL(k_child_g, dim3(grid_of(c.m)), dim3(kThreads), 0, c.s, c.nx, c.ny, c.nz,
+                           c.Qc, c.be, c.gch);
+        Level<T>& C = H.lev[L - 2];
+        hipLaunchKernelGGL(k_coarse_first<T>, dim3(grid_of(C.m * 24)), dim3(kThreads), 0, c.s, C,
+                           c.nx, c.ny, c.nz, c.Mc, c.r1, c.w, c.gch);
+        for (int k = L - 3; k >= 0; --k) {
+            Level<T>& F = H.lev[k + 1];
+            Level<T>& Cc = H.lev[k];
+            hipLaunchKernelGGL(k_coarsen_tq<T>, dim3(grid_of(F.m * 24)), dim3(kThreads), 0, c.s, F,
+                               c.Qc);
+            hipLaunchKernelGGL(k_coarsen_e<T>, dim3(grid_of(Cc.m * 24)), dim3(kThreads), 0, c.s, Cc,
+                               F, c.Qc);
+        }
+        for (int k = L - 2; k >= 0; --k) {
+            Level<T>& Lk = H.lev[k];
+            hipLaunchKernelGGL(k_elem_stencil<T>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s, Lk);
+            hipLaunchKernelGGL(k_restrict<T>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s,
+                               H.lev[k + 1], Lk, H.lev[k + 1].acol, Lk.acol, 0);
+        }
+    }
+    Level<T>& L0 = H.lev[0];
+    const int64_t nA = (int64_t)H.nc * H.nc;
+    hipLaunchKernelGGL(k_zero, dim3(grid_of(nA)), dim3(kThreads), 0, c.s, H.A, nA);
+    hipLaunchKernelGGL(k_coarse_assemble<T>, dim3(grid_of(L0.nn * kStencil)), dim3(kThreads), 0,
+                       c.s, L0, H.cmap, H.nc, c.sum_w, H.A);
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, c.s, H.A, H.nc, H.flag);
+}
+
+template <typename T>
+static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
+    Level<T>& Lk = H.lev[k];
+    if (k == 0) {
+        hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(1024), 0, c.s, H.A, H.nc, H.cmap,
+                           Lk.nn, Lk.r, Lk.z);
+        return;
+    }
+    const int64_t nv = 3 * Lk.nn + 1;
+    const double d = c.sum_w;
+    const int gr = red_grid_of(3 * Lk.nn);
+    hipLaunchKernelGGL(k_zero_t<T>, dim3(grid_of(nv)), dim3(kThreads), 0, c.s, Lk.z, nv);
+    // forward sweep: colours 0..7, then alpha
+    for (int col = 0; col < 8; ++col) {
+        const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
+        if (cnt == 0) continue;
+        hipLaunchKernelGGL(k_gs_color<T>, dim3(grid_of(cnt)), dim3(kThreads), 0, c.s, Lk, col,
+                           (const T*)Lk.r, Lk.z);
+    }
+    hipLaunchKernelGGL(k_acol_dot<T>, dim3(gr), dim3(kThreads), 0, c.s, Lk, (const T*)Lk.z,
+                       c.partials);
+    hipLaunchKernelGGL(k_alpha_fin<T>, dim3(1), dim3(kThreads), 0, c.s, c.partials, gr, Lk.nn, d,
+                       (const T*)Lk.r, Lk.z, Lk.res, 0);
+    // residual, restriction, coarse correction, prolongation
+    const int grr = red_grid_of(Lk.nn);
+    hipLaunchKernelGGL(k_resid<T>, dim3(grr), dim3(kThreads), 0, c.s, Lk, (const T*)Lk.r,
+                       (const T*)Lk.z, Lk.res, c.partials);
+    hipLaunchKernelGGL(k_alpha_fin<T>, dim3(1), dim3(kThreads), 0, c.s, c.partials, grr, Lk.nn, d,
+                       (const T*)Lk.r, Lk.z, Lk.res, 1);
+    Level<T>& Lc = H.lev[k - 1];
+    hipLaunchKernelGGL(k_restrict<T>, dim3(grid_of(Lc.nn)), dim3(kThreads), 0, c.s, Lk, Lc,
+                       (const T*)Lk.res, Lc.r, 1);
+    vcycle_level(c, H, k - 1);
+    hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s, Lc, Lk,
+                       (const T*)Lc.z, Lk.z);
+    // backward sweep: alpha, then colours 7..0
+    hipLaunchKernelGGL(k_acol_dot<T>, dim3(gr), dim3(kThreads), 0, c.s, Lk, (const T*)Lk.z,
+                       c.partials);
+    hipLaunchKernelGGL(k_alpha_fin<T>, dim3(1), dim3(kThreads), 0, c.s, c.partials, gr, Lk.nn, d,
+                       (const T*)Lk.r, Lk.z, Lk.res, 0);
+    for (int col = 7; col >= 0; --col) {
+        const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
+        if (cnt == 0) continue;
+        hipLaunchKernelGGL(k_gs_color<T>, dim3(grid_of(cnt)), dim3(kThreads), 0, c.s, Lk, col,
+                           (const T*)Lk.r, Lk.z);
+    }
+}
+
+template <typename T>
+void mg_vcycle(Ctx& c, Hierarchy<T>& H, const double* r, double* z) {
+    const int L = (int)H.lev.size();
+    Level<T>& fine = H.lev[L - 1];
+    const int64_t nv = 3 * fine.nn + 1;
+    hipLaunchKernelGGL((k_convert<double, T>), dim3(grid_of(nv)), dim3(kThreads), 0, c.s, r,
+                       fine.r, nv);
+    vcycle_level(c, H, L - 1);
+    hipLaunchKernelGGL((k_convert<T, double>), dim3(grid_of(nv)), dim3(kThreads), 0, c.s,
+                       (const T*)fine.z, z, nv);
+}
+
+template <typename T>
+int mg_check_factor(Ctx& c, Hierarchy<T>& H) {
+    int flag = 0;
+    hipMemcpyAsync(&flag, H.flag, sizeof(int), hipMemcpyDeviceToHost, c.s);
+    hipStreamSynchronize(c.s);
+    return flag;
+}
+
+template void mg_build<double>(Ctx&, Hierarchy<double>&);
+template void mg_build<float>(Ctx&, Hierarchy<float>&);
+template void mg_vcycle<double>(Ctx&, Hierarchy<double>&, const double*, double*);
+template void mg_vcycle<float>(Ctx&, Hierarchy<float>&, const double*, double*);
+template int mg_check_factor<double>(Ctx&, Hierarchy<double>&);
+template int mg_check_factor<float>(Ctx&, Hierarchy<float>&);
+
+}  // namespace vts

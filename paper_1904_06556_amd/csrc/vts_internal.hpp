@@ -1,0 +1,174 @@
+// Internal declarations of libvts (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/vts.h"
+
+namespace vts {
+
+constexpr int kThreads = 256;          // block size of every 1D launch
+constexpr int kRedBlocks = 1024;       // max blocks of a reduction launch
+constexpr int kRedSlots = 16;          // quantities per reduction buffer
+constexpr int kMaxCoarse = 4096;       // largest dense coarsest system
+
+// Block of 27 neighbours: offset (dx,dy,dz) in {-1,0,1}^3 -> s = (dx+1) + 3(dy+1) + 9(dz+1).
+constexpr int kStencil = 27;
+constexpr int kStencilVals = 27 * 9;   // 3x3 block per neighbour
+
+// One multigrid level (all sizes for that level's grid).  Device pointers.
+template <typename T>
+struct Level {
+    int nx, ny, nz;            // elements
+    int NX, NY, NZ;            // nodes per direction
+    int64_t nn, m;             // nodes, elements
+    int cnx[8], cny[8], cnz[8];// nodes per colour and direction
+    int64_t coff[9];           // colour offsets in colour-major order
+    uint8_t* fixed;            // 3*nn DOF mask
+    T* st;                     // 243*nn stencil, [value][colour-major node]
+    T* dinv;                   // 9*nn inverse diagonal block, [value][colour-major node]
+    T* acol;                   // 3*nn alpha column, natural order
+    T* E;                      // 576*m element matrices (coarse levels), [e][row][col]
+    T* TQ;                     // 576*m scratch for the Galerkin product
+    T* r;                      // S-vectors (3*nn + 1)
+    T* z;
+    T* res;
+};
+
+template <typename T>
+struct Hierarchy {
+    std::vector<Level<T>> lev;   // 0 = coarsest
+    double* A = nullptr;         // dense coarsest matrix / Cholesky factor, nc x nc
+    int nc = 0;
+    int* cmap = nullptr;         // 3*nn_0 -> dense index or -1
+    int* flag = nullptr;         // device: 1 if the factorization met a non-positive pivot
+};
+
+struct Ctx {
+    // problem
+    int nx, ny, nz, L;
+    int64_t nn, ndof, m, nfree;
+    double E, nu, h, V;
+    int prec;
+    vts_options opt;
+    hipStream_t s = nullptr;
+    int device = 0;
+
+    // constants (device)
+    double* Ke = nullptr;        // 576
+    float* Kef = nullptr;        // 576
+    double* Mc = nullptr;        // 8 x 576: Q_c^T K_e Q_c
+    double* Qc = nullptr;        // 8 x 8 x 8: Q_c[a][A] nodal interpolation weights
+
+    // problem data (device)
+    uint8_t* fixed = nullptr;    // ndof
+    double* f = nullptr;         // ndof
+    double* rlo = nullptr;       // m
+    double* rhi = nullptr;       // m
+    double norm_f = 0, norm_bounds = 0;
+
+    // PBM state (device)
+    double* u = nullptr;         // ndof
+    double alpha = 1.0;
+    double* nlo = nullptr;       // nu_lo, m
+    double* nhi = nullptr;
+    double* rho = nullptr;
+    double* mlo = nullptr;
+    double* mhi = nullptr;
+    double* p = nullptr;
+    double* qlo = nullptr;
+    double* qhi = nullptr;
+    float* rhof = nullptr;       // rho rounded to FP32 (for vts_apply_K_f32)
+
+    // evaluation at the current state (device)
+    double* e = nullptr;         // m
+    double* be = nullptr;        // 24*m, [j][e]
+    double* r1 = nullptr;        // rho'
+    double* r2 = nullptr;        // rho''
+    double* l2 = nullptr;        // mu_lo''
+    double* h2 = nullptr;        // mu_hi''
+    double* g3 = nullptr;
+    double* g4 = nullptr;
+    double* w = nullptr;
+    double* zc = nullptr;        // z of the right-hand side
+    double* gch = nullptr;       // 24*m, Q_c^T b_e (Galerkin helper)
+    double* g1 = nullptr;        // ndof
+    double* rhs = nullptr;       // ndof+1
+    double* dy = nullptr;        // ndof+1
+    double* dnl = nullptr;       // m
+    double* dnh = nullptr;
+    double* c1 = nullptr;        // b_e^T du_e
+    double* c2 = nullptr;        // 1/2 du_e^T K_e du_e
+    double* wt = nullptr;        // scratch per element (S-apply)
+    double g2 = 0, sum_w = 0, sum_z = 0, sum_r1 = 0, n_g1 = 0, n_g3 = 0, n_g4 = 0;
+    bool setup_valid = false;
+    bool eval_valid = false;
+
+    // MINRES vectors (device), each ndof+1
+    double* mv[8] = {};
+
+    // reductions
+    double* partials = nullptr;  // kRedSlots * kRedBlocks
+    double* red = nullptr;       // kRedSlots results (device)
+    double* red_host = nullptr;  // pinned mirror
+
+    // multigrid
+    Hierarchy<double>* h64 = nullptr;
+    Hierarchy<float>* h32 = nullptr;
+
+    // algorithm state (host)
+    double eps_nwt = 1.0, eps_mr = 0.0, res_prev = -1.0;
+    int outer = 0, newton_total = 0, minres_total = 0;
+    int status = VTS_OK;
+    bool converged = false;
+    std::string err;
+
+    std::vector<void*> allocs;
+};
+
+// host-side finite-element tables (host_fe.cpp)
+void element_stiffness(double E, double nu, double h, double* Ke576);
+void child_interp(double* Q512);                       // Q[c][a][A]
+void galerkin_child_matrices(const double* Ke, const double* Q, double* Mc);
+
+// launchers (kernels.hip); all asynchronous on ctx.s
+void launch_apply_K_f64(Ctx& c, const double* rho, const double* x, double* y);
+void launch_apply_K_f32(Ctx& c, const float* rho, const float* x, float* y);
+void launch_energy(Ctx& c, const double* u, double* e);
+void launch_eval(Ctx& c);                    // e, be, coefficients, sums -> red[0..]
+void launch_grad(Ctx& c);                    // g1, rhs_u, ||g1||^2 -> red
+void launch_apply_S(Ctx& c, const double* x, double* y);
+void launch_dnu(Ctx& c);                     // c1, c2, dnl, dnh, slope parts -> red
+void launch_linesearch(Ctx& c, double kappa, double dalpha); // elementwise Delta L -> red
+void launch_update(Ctx& c, double kappa);    // u, nu
+void launch_outer_eval(Ctx& c);              // gap, dual parts, stationarity -> red
+void launch_mult_update(Ctx& c, int rho_only);
+void launch_penalty_update(Ctx& c);
+void launch_init_state(Ctx& c);
+void launch_dot(Ctx& c, const double* x, const double* y, int64_t n, int slot);
+void launch_copy1(Ctx& c, const double* src, double* dst);
+void launch_set(Ctx& c, double* dst, double v);
+void launch_fill(Ctx& c, double* dst, double v, int64_t n);
+void launch_scale(Ctx& c, double* dst, const double* src, double a, int64_t n);
+void launch_axpy(Ctx& c, double* y, double a, const double* x, int64_t n);
+void launch_minres_w(Ctx& c, double* w, const double* v, const double* w1, const double* w2,
+                     double eps_old, double delta, double inv_gamma, double* x, double phi,
+                     int64_t n);
+void launch_round_rho(Ctx& c);
+
+template <typename T> void mg_build(Ctx& c, Hierarchy<T>& H);
+template <typename T> void mg_vcycle(Ctx& c, Hierarchy<T>& H, const double* r, double* z);
+template <typename T> int mg_check_factor(Ctx& c, Hierarchy<T>& H);
+
+// reduction slot names
+enum Slot {
+    SL_SUM_R1 = 0, SL_SUM_Z, SL_SUM_W, SL_G3SQ, SL_G4SQ, SL_G1SQ,
+    SL_DOT = 6, SL_SLOPE_NU = 7, SL_LS = 8, SL_GAP = 9, SL_NLO = 10, SL_NHI = 11,
+    SL_STAT = 12, SL_SUM_RHO = 13, SL_WT = 14, SL_AUX = 15
+};
+
+}  // namespace vts
