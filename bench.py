@@ -1,0 +1,205 @@
+"""Benchmark of the PBM + multigrid-MINRES hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload N]
+
+A step is one complete PBM solve (Algorithm 1 with its Newton method,
+Algorithm 2, and MINRES preconditioned by one V-cycle) of the workload from
+the initial point to a KKT residual of 1e-6; every row of the hot path runs
+in each step.  Inputs (grid, supports, loads, bounds) are resident on the
+device before the timed region; each step re-initializes the PBM state on the
+device (vts_reset) and solves.
+
+Printed: one JSON line with the throughput (VTS solves per second, i.e.
+1/time-to-KKT), the K(rho)u and MINRES-MG rates, the roofline figures of the
+dominant kernel measured with HIP events, and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "K(rho)u GDOF/s + MINRES-MG iters/s; time-to-KKT 1e-6 per VTS; p50/p99"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=1,
+                    help="0: cantilever 8x4x4, 1: cantilever 64x32x32 (default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    return ap.parse_args()
+
+
+def kernel_roofline(torch, ctx, pr, reps=200):
+    """K(rho)x in FP64 timed with HIP events on the library's stream.
+    Algorithmic bytes per launch: read x and write y (8 B x n_dof each), read
+    rho (8 B x m) and the DOF mask (1 B x n_dof)."""
+    n_dof, m = pr.n_dof, pr.m
+    bytes_per = 8 * n_dof * 2 + 8 * m + n_dof
+    # rotating buffers so that the working set exceeds the 256 MB Infinity Cache
+    per_set = 16 * n_dof
+    nsets = max(2, int(math.ceil(512e6 / per_set)))
+    xs = [torch.rand(n_dof, dtype=torch.float64, device="cuda") for _ in range(nsets)]
+    ys = [torch.empty(n_dof, dtype=torch.float64, device="cuda") for _ in range(nsets)]
+    stream = torch.cuda.current_stream()
+    for i in range(nsets):
+        ctx.apply_K(xs[i], ys[i])
+    res = {}
+    for label, sets in (("rotating", nsets), ("hot", 1)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(reps):
+            k = i % sets
+            ctx.apply_K(xs[k], ys[k])
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[label] = dict(ms=ms, gbs=bytes_per / (ms * 1e-3) / 1e9,
+                          gdofs=n_dof / (ms * 1e-3) / 1e9)
+    del xs, ys
+    return bytes_per, res
+
+
+def minres_rate(torch, ctx, its=50):
+    """MINRES-MG iterations per second at the converged Newton point (fixed
+    iteration count: tolerance 0)."""
+    ctx.newton_setup()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = ctx.solve_newton(0.0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return st["iterations"] / dt, st["iterations"]
+
+
+def cpu_baseline(pr, eps_mr0, newton_steps_gpu, budget_s):
+    """The FP64 oracle on the host cores: Newton steps of the same solve from
+    the same initial point until `budget_s` is spent; scaled to VTS/s with the
+    GPU solve's Newton count."""
+    from oracle import pbm as opbm
+    opts = opbm.Options(max_newton=1000)
+    if eps_mr0:
+        opts.eps_mr0 = eps_mr0
+    s = opbm.Solver(pr, opts)
+    st = opbm.initial_state(s.P.grid.n_dof, s.P.grid.m, s.P.V)
+    t0 = time.perf_counter()
+    done = 0
+    eps = opts.eps_nwt0
+    while time.perf_counter() - t0 < budget_s and done < 50:
+        s.opts.max_newton = 1
+        st, _ = s.newton(st, 0.0)
+        done += 1
+    dt = time.perf_counter() - t0
+    per_newton = dt / max(done, 1)
+    vts_per_s = 1.0 / (per_newton * max(newton_steps_gpu, 1))
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count()
+    return dict(value=vts_per_s, unit="VTS/s", cores=1, cores_available=cores, kind="oracle",
+                sample=(f"first {done} Newton steps of the same {pr.name} solve "
+                        f"({per_newton:.2f} s each: evaluation, assembled S, Galerkin "
+                        f"hierarchy, MINRES-MG, line search), scaled by the GPU solve's "
+                        f"{newton_steps_gpu} Newton steps; SciPy sparse kernels run on one "
+                        f"thread"),
+                seconds_per_newton=per_newton)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {a.gpus} is not supported "
+              f"(this build has no multi-GPU path; see DESIGN.md)", file=sys.stderr)
+        return 2
+    import torch
+    import workloads as W
+    from paper_1904_06556_amd import vts as V
+
+    pr = W.config(a.workload)
+    eps_mr0 = pr.extra.get("eps_mr0")
+    opts = V.default_options()
+    if eps_mr0:
+        opts.eps_mr0 = eps_mr0
+    prec = V.VTS_MIXED if pr.extra.get("precision") == "mixed" else V.VTS_FP64
+    ctx = V.Context.from_problem(pr, precision=prec, options=opts)
+    torch.cuda.synchronize()
+
+    for w in range(a.warmup):
+        ctx.reset()
+        r = ctx.pbm_solve()
+        print(f"warmup {w}: outer {r['outer']} newton {r['newton']} minres {r['minres']}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ctx.reset()
+        results.append(ctx.pbm_solve())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    print(f"timed: {a.steps} solves in {t1 - t0:.2f} s", file=sys.stderr, flush=True)
+    ms_per_step = (t1 - t0) * 1e3 / a.steps
+    last = results[-1]
+
+    # KKT of the last result by the definition (oracle checker, host)
+    from oracle import pbm as opbm, kkt
+    d = ctx.state_dict()
+    P = opbm.VTS(pr)
+    k = kkt.kkt_residual(P.grid, P.Ke, P.f, P.V, P.rho_lo, P.rho_hi, d["rho"], d["u"], d["alpha"])
+    gold = os.path.join(ROOT, "tests", "golden", f"oracle_{pr.name}.json")
+    c_err = None
+    if os.path.exists(gold):
+        g = json.load(open(gold))
+        c_err = abs(last["compliance"] - g["compliance_half_fu"]) / g["compliance_half_fu"]
+
+    mr_rate, mr_its = minres_rate(torch, ctx)
+    bytes_per, kr = kernel_roofline(torch, ctx, pr)
+    rot = kr["rotating"]
+    line = {
+        "metric": METRIC,
+        "value": 1e3 / ms_per_step,
+        "unit": "VTS solves/s (1/time-to-KKT)",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == V.VTS_FP64 else "f64+f32mg",
+        "data": "synthetic",
+        "config": {"workload": pr.name, "grid": [pr.nx, pr.ny, pr.nz], "levels": pr.levels,
+                   "m": pr.m, "n": pr.n, "V_over_m": pr.V / pr.m,
+                   "precision": "fp64" if prec == V.VTS_FP64 else "mixed",
+                   "eps_mr0": eps_mr0, "parallelism": "1 GPU"},
+        "time_to_kkt_s": ms_per_step / 1e3,
+        "kkt": k["kkt"], "kkt_terms": k,
+        "compliance": last["compliance"], "compliance_rel_err_vs_oracle": c_err,
+        "outer": last["outer"], "newton": last["newton"], "minres": last["minres"],
+        "k_apply_gdofs": rot["gdofs"], "k_apply_gdofs_hot_cache": kr["hot"]["gdofs"],
+        "minres_mg_iters_per_s": mr_rate,
+        "roofline": {"kernel": "k_apply_K<double> (K(rho)x, FP64)", "bound": "hbm",
+                     "achieved": rot["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": rot["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": bytes_per, "avg_launch_ms": rot["ms"]},
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(pr, eps_mr0, last["newton"], a.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

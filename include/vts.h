@@ -80,12 +80,17 @@ typedef struct {
 } vts_problem;
 
 /* Parameters of Algorithms 1 and 2 and of the MINRES rule of Section 6.2.
- * vts_default_options() fills the values used by this library (the paper's
- * beta = gamma = 0.3, p_min = 1e-8, eps_NWT = 1, eps_MR rule; tighter
- * eps_PBM = 1e-8, eps_NWT_min = 1e-5, final eps_NWT = 5e-7 and a
- * stationarity test so that results meet a KKT residual of 1e-6). */
+ * vts_default_options() fills the values used by this library: the paper's
+ * beta = gamma = 0.3, eps_NWT = 1 and eps_MR rule; tighter eps_PBM = 1e-8,
+ * eps_NWT_min = 1e-5, final eps_NWT = 5e-7 and a stationarity test so that
+ * results meet a KKT residual of 1e-6; floors p_min = 1e-4 for the penalties
+ * p of the energy constraints and q_min = 1e-8 (the paper's value) for the
+ * penalties q of nu >= 0.  The Schur weights grow like 1/p, so the paper's
+ * p_min = 1e-8 makes the Newton systems too ill-conditioned for the
+ * Gauss-Seidel multigrid at these tolerances; PBM converges for any
+ * positive floor, and a small q keeps the bound multipliers converging fast. */
 typedef struct {
-    double beta, gamma, p_min;
+    double beta, gamma, p_min, q_min;
     double eps_pbm, eps_nwt0, eps_nwt_min, eps_nwt_final;
     double eps_stat;              /* <= 0: outer loop stops on the gap test alone */
     double accept_stall;          /* final-Newton stall accepted if res_PBM below this */
@@ -151,6 +156,11 @@ void vts_default_options(vts_options* opt);
 vts_status vts_create(const vts_problem* pr, const vts_options* opt, void* stream,
                       vts_ctx** out);
 void vts_destroy(vts_ctx* ctx);
+
+/* Re-initializes the PBM state on the device to the initial point stated
+ * after Algorithm 1 (as vts_create does) and resets the counters and
+ * tolerances; the problem data stay resident. */
+vts_status vts_reset(vts_ctx* ctx);
 
 /* Device bytes vts_create would allocate for this problem (for admission). */
 size_t vts_footprint_bytes(const vts_problem* pr, const vts_options* opt);

@@ -37,10 +37,17 @@ class Options:
     MINRES rule are the values stated after Algorithm 1 and in Section 6.2.
     eps_pbm, eps_nwt_min and eps_nwt_final are tighter than the paper's
     (1e-5..1e-6, 1e-3, 10 eps_pbm) so that the result meets a KKT residual of
-    1e-6; `paper_options()` returns the paper's values."""
+    1e-6.  The floor of the energy-constraint penalties p is p_min = 1e-4
+    instead of the paper's 1e-8 (the floor q_min of q_lo, q_hi keeps the
+    paper's 1e-8): the multiplier method converges for any positive floor,
+    the Schur weights are bounded by rho'' ~ rho/p, so a higher p floor keeps
+    the Newton systems within reach of the Gauss-Seidel multigrid, while a
+    small q keeps weakly active bound multipliers converging quickly.
+    `paper_options()` returns the paper's values."""
     beta: float = 0.3
     gamma: float = 0.3
-    p_min: float = 1e-8
+    p_min: float = 1e-4                       # floor of p; paper: 1e-8 (see paper_options)
+    q_min: float = 1e-8                       # floor of q_lo, q_hi (the paper's value)
     eps_pbm: float = 1e-8
     eps_nwt0: float = 1.0
     eps_nwt_min: float = 1e-5
@@ -60,7 +67,8 @@ class Options:
 def paper_options(eps_pbm: float = 1e-5) -> "Options":
     """The parameter values of the paper's experiments (Section 7)."""
     return Options(eps_pbm=eps_pbm, eps_nwt_min=1e-3, eps_nwt_final=None,
-                   final_res4=False, eps_stat=None, accept_stall=0.0)
+                   final_res4=False, eps_stat=None, accept_stall=0.0, p_min=1e-8,
+                   q_min=1e-8)
 
 
 @dataclass
@@ -448,8 +456,8 @@ class Solver:
                 break
             st.rho, st.mu_lo, st.mu_hi = rho_n, mul_n, muh_n
             st.p = np.maximum(o.gamma * st.p, o.p_min)
-            st.q_lo = np.maximum(o.gamma * st.q_lo, o.p_min)
-            st.q_hi = np.maximum(o.gamma * st.q_hi, o.p_min)
+            st.q_lo = np.maximum(o.gamma * st.q_lo, o.q_min)
+            st.q_hi = np.maximum(o.gamma * st.q_hi, o.q_min)
             eps_nwt = max(min(100.0 * ratio, eps_nwt), o.eps_nwt_min)
         eps_final = o.eps_nwt_final if o.eps_nwt_final is not None else 10.0 * o.eps_pbm
         if self.status == "ok":

@@ -139,6 +139,7 @@ Plan make_plan(const vts_problem* pr) {
     for (int q = 0; q < 5; ++q) add(m * 8);                          // dnl dnh c1 c2 wt
     for (int q = 0; q < 8; ++q) add((ndof + 1) * 8);                 // MINRES
     add(kRedSlots * kRedBlocks * 8); add(kRedSlots * 8);             // partials, red
+    add(8 * 4096);                                                   // tiled S partials
     const size_t ts = pr->precision == VTS_MIXED ? 4 : 8;
     Dims dl = d;
     for (int k = pr->levels - 1; k >= 0; --k) {
@@ -225,7 +226,21 @@ vts_status build_hierarchy(Ctx& c, Hierarchy<T>& H, const std::vector<uint8_t>& 
     ALLOC(H.A, (int64_t)nc * nc);
     ALLOC(H.cmap, (int64_t)cmap.size());
     HIPCHK(hipMemcpy(H.cmap, cmap.data(), cmap.size() * sizeof(int), hipMemcpyHostToDevice));
+    std::vector<int> cinv(nc - 1);
+    for (size_t q = 0; q < cmap.size(); ++q)
+        if (cmap[q] >= 0) cinv[cmap[q]] = (int)q;
+    ALLOC(H.cinv, nc - 1);
+    HIPCHK(hipMemcpy(H.cinv, cinv.data(), (nc - 1) * sizeof(int), hipMemcpyHostToDevice));
     ALLOC(H.flag, 1);
+    // levels small enough for the one-workgroup V-cycle (needs the inverse)
+    H.ksmall = -1;
+    if (nc <= kSmallCoarse) {
+        for (int k = 0; k < L && k < kMaxSmallLevels; ++k) {
+            if (H.lev[k].nn > kSmallNodes) break;
+            H.ksmall = k;
+        }
+    }
+    if (H.ksmall >= 0) ALLOC(H.Ainv, (int64_t)nc * nc);
     return VTS_OK;
 }
 
@@ -565,6 +580,7 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
     child_interp(Q);
     galerkin_child_matrices(Ke, Q, Mc);
     for (int q = 0; q < 576; ++q) Kef[q] = (float)Ke[q];
+    c.kh_ok = walsh_form(Ke, c.kh8) && c.ndof < (int64_t(1) << 31);
     ALLOC(c.Ke, 576); ALLOC(c.Kef, 576); ALLOC(c.Mc, 8 * 576); ALLOC(c.Qc, 512);
     HIPCHK(hipMemcpy(c.Ke, Ke, sizeof(Ke), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c.Kef, Kef, sizeof(Kef), hipMemcpyHostToDevice));
@@ -588,6 +604,7 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
     ALLOC(c.dnl, c.m); ALLOC(c.dnh, c.m); ALLOC(c.c1, c.m); ALLOC(c.c2, c.m); ALLOC(c.wt, c.m);
     for (int q = 0; q < 8; ++q) ALLOC(c.mv[q], c.ndof + 1);
     ALLOC(c.partials, kRedSlots * kRedBlocks);
+    ALLOC(c.spart, apply_S_tile_blocks(c));
     ALLOC(c.red, kRedSlots);
     {
         void* hp = nullptr;
@@ -638,7 +655,8 @@ void vts_default_options(vts_options* o) {
     if (!o) return;
     o->beta = 0.3;
     o->gamma = 0.3;
-    o->p_min = 1e-8;
+    o->p_min = 1e-4;
+    o->q_min = 1e-8;
     o->eps_pbm = 1e-8;
     o->eps_nwt0 = 1.0;
     o->eps_nwt_min = 1e-5;
@@ -674,6 +692,23 @@ vts_status vts_create(const vts_problem* pr, const vts_options* opt, void* strea
         return st;
     }
     *out = c;
+    return VTS_OK;
+}
+
+vts_status vts_reset(vts_ctx* cp) {
+    if (!cp) return VTS_EINVAL;
+    Ctx& c = *cp;
+    launch_init_state(c);
+    launch_round_rho(c);
+    c.alpha = 1.0;
+    c.eps_nwt = c.opt.eps_nwt0;
+    c.eps_mr = c.opt.eps_mr0 > 0 ? c.opt.eps_mr0 : 1e-4 * std::sqrt((double)c.nfree);
+    c.res_prev = -1.0;
+    c.outer = c.newton_total = c.minres_total = 0;
+    c.converged = false;
+    c.eval_valid = c.setup_valid = false;
+    c.status = VTS_OK;
+    HIPCHK(hipGetLastError());
     return VTS_OK;
 }
 

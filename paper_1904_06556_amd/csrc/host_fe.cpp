@@ -9,6 +9,7 @@
 // evaluated exactly as a product of 1D integrals of the linear shape
 // functions (the integrand is separable); the result scales with h in 3D.
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 
 #include "vts_internal.hpp"
@@ -97,6 +98,52 @@ void galerkin_child_matrices(const double* Ke, const double* Q, double* Mc) {
                         M[(3 * A + i) * 24 + 3 * B + j] = s;
                     }
     }
+}
+
+// Kh = H K_e H / 64 with H = H8 x I3, H8[m][a] = (-1)^popcount(m & a).
+// Returns true (and the coefficients A..H) if Kh has exactly the structure
+// that the tiled kernels expand: 45 non-zeros in the classes below, every
+// other entry zero (relative tolerance 1e-13).
+bool walsh_form(const double* Ke, double* kh8) {
+    auto h8 = [](int m, int a) { return (__builtin_popcount(m & a) & 1) ? -1.0 : 1.0; };
+    double Kh[24][24];
+    double mx = 0.0;
+    for (int r = 0; r < 24; ++r)
+        for (int c = 0; c < 24; ++c) {
+            double sum = 0.0;
+            for (int a = 0; a < 8; ++a)
+                for (int b = 0; b < 8; ++b)
+                    sum += h8(r / 3, a) * Ke[(3 * a + r % 3) * 24 + 3 * b + c % 3] * h8(b, c / 3);
+            Kh[r][c] = sum / 64.0;
+            mx = std::max(mx, std::fabs(Kh[r][c]));
+        }
+    // class of each entry: 0..7 = A..H, -1 = zero
+    int cls[24][24];
+    for (int r = 0; r < 24; ++r)
+        for (int c = 0; c < 24; ++c) cls[r][c] = -1;
+    const int nrm[3] = {3, 7, 14};
+    for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) cls[nrm[p]][nrm[q]] = (p == q) ? 0 : 1;
+    const int shear[3][2] = {{4, 6}, {5, 12}, {8, 13}};
+    for (auto& sp : shear)
+        for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) cls[sp[p]][sp[q]] = 2;
+    const int pair[3][2] = {{9, 20}, {10, 17}, {15, 19}};
+    for (auto& pp : pair)
+        for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) cls[pp[p]][pp[q]] = (p == q) ? 3 : 4;
+    const int tri[3] = {11, 16, 18};
+    for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) cls[tri[p]][tri[q]] = (p == q) ? 5 : 6;
+    for (int q = 21; q < 24; ++q) cls[q][q] = 7;
+    const int rep[8][2] = {{3, 3}, {3, 7}, {4, 4}, {9, 9}, {9, 20}, {11, 11}, {11, 16}, {21, 21}};
+    for (int q = 0; q < 8; ++q) kh8[q] = Kh[rep[q][0]][rep[q][1]];
+    for (int r = 0; r < 24; ++r)
+        for (int c = 0; c < 24; ++c) {
+            const double want = cls[r][c] < 0 ? 0.0 : kh8[cls[r][c]];
+            if (std::fabs(Kh[r][c] - want) > 1e-13 * mx) return false;
+        }
+    return true;
 }
 
 }  // namespace vts

@@ -146,10 +146,18 @@ k_apply_K(int nx, int ny, int nz, const T* __restrict__ Ke, const T* __restrict_
 }
 
 void launch_apply_K_f64(Ctx& c, const double* rho, const double* x, double* y) {
+    if (tile_ok(c)) {
+        launch_apply_K_tile_f64(c, rho, x, y);
+        return;
+    }
     hipLaunchKernelGGL(k_apply_K<double>, dim3(grid1d(c.nn)), dim3(kThreads), 0, c.s,
                        c.nx, c.ny, c.nz, c.Ke, rho, x, c.fixed, y);
 }
 void launch_apply_K_f32(Ctx& c, const float* rho, const float* x, float* y) {
+    if (tile_ok(c)) {
+        launch_apply_K_tile_f32(c, rho, x, y);
+        return;
+    }
     hipLaunchKernelGGL(k_apply_K<float>, dim3(grid1d(c.nn)), dim3(kThreads), 0, c.s,
                        c.nx, c.ny, c.nz, c.Kef, rho, x, c.fixed, y);
 }
@@ -407,6 +415,10 @@ __global__ void k_store_neg(const double* __restrict__ red, int slot, double* __
 }
 
 void launch_apply_S(Ctx& c, const double* x, double* y) {
+    if (tile_ok(c)) {
+        launch_apply_S_tile(c, x, y);
+        return;
+    }
     const int g = red_grid(c.m);
     hipLaunchKernelGGL(k_S_pass1, dim3(g), dim3(kThreads), 0, c.s, c.nx, c.ny, c.nz, c.be, c.w,
                        x, c.ndof, c.fixed, c.wt, c.partials);
@@ -588,18 +600,19 @@ void launch_mult_update(Ctx& c, int rho_only) {
                        c.mhi);
 }
 
-__global__ void k_penalty(int64_t m, double gamma, double pmin, double* __restrict__ p,
-                          double* __restrict__ qlo, double* __restrict__ qhi) {
+__global__ void k_penalty(int64_t m, double gamma, double pmin, double qmin,
+                          double* __restrict__ p, double* __restrict__ qlo,
+                          double* __restrict__ qhi) {
     const int64_t t = gid();
     if (t >= m) return;
     p[t] = fmax(gamma * p[t], pmin);
-    qlo[t] = fmax(gamma * qlo[t], pmin);
-    qhi[t] = fmax(gamma * qhi[t], pmin);
+    qlo[t] = fmax(gamma * qlo[t], qmin);
+    qhi[t] = fmax(gamma * qhi[t], qmin);
 }
 
 void launch_penalty_update(Ctx& c) {
     hipLaunchKernelGGL(k_penalty, dim3(grid1d(c.m)), dim3(kThreads), 0, c.s, c.m, c.opt.gamma,
-                       c.opt.p_min, c.p, c.qlo, c.qhi);
+                       c.opt.p_min, c.opt.q_min, c.p, c.qlo, c.qhi);
 }
 
 __global__ void k_init(int64_t ndof, int64_t m, double rho0, double* u, double* nlo,

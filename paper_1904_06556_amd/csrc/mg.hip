@@ -283,84 +283,6 @@ __global__ void __launch_bounds__(kThreads) k_elem_stencil(Level<T> L) {
 // ---------------------------------------------------------------------------
 // smoothing and residual
 // ---------------------------------------------------------------------------
-// One colour of nodal block Gauss-Seidel: z_n += D_n^{-1} (r - S z)_n for every
-// node of colour `col` (no two nodes of one colour share an element).
-template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_gs_color(Level<T> L, int col, const T* __restrict__ r, T* __restrict__ z) {
-    const int64_t tl = gidx();
-    const int64_t cnt = L.coff[col + 1] - L.coff[col];
-    if (tl >= cnt) return;
-    const int64_t t = L.coff[col] + tl;
-    int64_t q = tl;
-    const int i = 2 * (int)(q % L.cnx[col]) + (col & 1);
-    q /= L.cnx[col];
-    const int j = 2 * (int)(q % L.cny[col]) + ((col >> 1) & 1);
-    const int k = 2 * (int)(q / L.cny[col]) + (col >> 2);
-    const int64_t n = nat(i, j, k, L.NX, L.NY);
-    const T za = z[3 * L.nn];
-    T a0 = r[3 * n] - L.acol[3 * n] * za;
-    T a1 = r[3 * n + 1] - L.acol[3 * n + 1] * za;
-    T a2 = r[3 * n + 2] - L.acol[3 * n + 2] * za;
-    for (int s = 0; s < kStencil; ++s) {
-        const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
-        const int ii = i + dx, jj = j + dy, kk = k + dz;
-        if (ii < 0 || ii >= L.NX || jj < 0 || jj >= L.NY || kk < 0 || kk >= L.NZ) continue;
-        const int64_t mm = nat(ii, jj, kk, L.NX, L.NY);
-        const T x0 = z[3 * mm], x1 = z[3 * mm + 1], x2 = z[3 * mm + 2];
-        const T* S = L.st + (int64_t)(s * 9) * L.nn + t;
-        a0 -= S[0] * x0 + S[L.nn] * x1 + S[2 * L.nn] * x2;
-        a1 -= S[3 * L.nn] * x0 + S[4 * L.nn] * x1 + S[5 * L.nn] * x2;
-        a2 -= S[6 * L.nn] * x0 + S[7 * L.nn] * x1 + S[8 * L.nn] * x2;
-    }
-    const T* D = L.dinv + t;
-    const int64_t N = L.nn;
-    z[3 * n] += D[0] * a0 + D[N] * a1 + D[2 * N] * a2;
-    z[3 * n + 1] += D[3 * N] * a0 + D[4 * N] * a1 + D[5 * N] * a2;
-    z[3 * n + 2] += D[6 * N] * a0 + D[7 * N] * a1 + D[8 * N] * a2;
-}
-
-// res = r - S z (displacement part, masked) and partial sums of acol . z
-template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_resid(Level<T> L, const T* __restrict__ r, const T* __restrict__ z, T* __restrict__ res,
-        double* partials) {
-    double acc = 0.0;
-    const T za = z[3 * L.nn];
-    for (int64_t t = gidx(); t < L.nn; t += (int64_t)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cm_decode(L, t, i, j, k);
-        const int64_t n = nat(i, j, k, L.NX, L.NY);
-        T a0 = r[3 * n] - L.acol[3 * n] * za;
-        T a1 = r[3 * n + 1] - L.acol[3 * n + 1] * za;
-        T a2 = r[3 * n + 2] - L.acol[3 * n + 2] * za;
-        for (int s = 0; s < kStencil; ++s) {
-            const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
-            const int ii = i + dx, jj = j + dy, kk = k + dz;
-            if (ii < 0 || ii >= L.NX || jj < 0 || jj >= L.NY || kk < 0 || kk >= L.NZ) continue;
-            const int64_t mm = nat(ii, jj, kk, L.NX, L.NY);
-            const T x0 = z[3 * mm], x1 = z[3 * mm + 1], x2 = z[3 * mm + 2];
-            const T* S = L.st + (int64_t)(s * 9) * L.nn + t;
-            a0 -= S[0] * x0 + S[L.nn] * x1 + S[2 * L.nn] * x2;
-            a1 -= S[3 * L.nn] * x0 + S[4 * L.nn] * x1 + S[5 * L.nn] * x2;
-            a2 -= S[6 * L.nn] * x0 + S[7 * L.nn] * x1 + S[8 * L.nn] * x2;
-        }
-        res[3 * n] = L.fixed[3 * n] ? T(0) : a0;
-        res[3 * n + 1] = L.fixed[3 * n + 1] ? T(0) : a1;
-        res[3 * n + 2] = L.fixed[3 * n + 2] ? T(0) : a2;
-        acc += (double)L.acol[3 * n] * z[3 * n] + (double)L.acol[3 * n + 1] * z[3 * n + 1] +
-               (double)L.acol[3 * n + 2] * z[3 * n + 2];
-    }
-    __shared__ double sh[kThreads];
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partials[SL_AUX * kRedBlocks + blockIdx.x] = sh[0];
-}
-
 // partial sums of acol . z
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
@@ -578,6 +500,414 @@ k_coarse_solve(const double* __restrict__ A, int nc, const int* __restrict__ cma
     if (threadIdx.x == 0) z[3 * nn] = (T)x[nc - 1];
 }
 
+
+// ---------------------------------------------------------------------------
+// large levels: one colour pass / residual with 9 waves per 64 nodes; wave g
+// sums the three neighbours of row (dy, dz) = (g%3 - 1, g/3 - 1), the partial
+// sums are combined in LDS in a fixed order
+// ---------------------------------------------------------------------------
+constexpr int kRowWaves = 9;
+constexpr int kBlk9 = 64 * kRowWaves;
+
+template <typename T>
+__device__ __forceinline__ void row_partial(const Level<T>& L, int64_t t, int i, int j, int k,
+                                            int g, const T* __restrict__ z, T& a0, T& a1, T& a2) {
+    const int dy = g % 3 - 1, dz = g / 3 - 1;
+    const int jj = j + dy, kk = k + dz;
+    a0 = a1 = a2 = T(0);
+    if (jj < 0 || jj >= L.NY || kk < 0 || kk >= L.NZ) return;
+    const int64_t N = L.nn;
+    for (int dx = -1; dx <= 1; ++dx) {
+        const int ii = i + dx;
+        if (ii < 0 || ii >= L.NX) continue;
+        const int s = (dx + 1) + 3 * g;
+        const int64_t mm = nat(ii, jj, kk, L.NX, L.NY);
+        const T x0 = z[3 * mm], x1 = z[3 * mm + 1], x2 = z[3 * mm + 2];
+        const T* S = L.st + (int64_t)(s * 9) * N + t;
+        a0 += S[0] * x0 + S[N] * x1 + S[2 * N] * x2;
+        a1 += S[3 * N] * x0 + S[4 * N] * x1 + S[5 * N] * x2;
+        a2 += S[6 * N] * x0 + S[7 * N] * x1 + S[8 * N] * x2;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlk9)
+k_gs_color9(Level<T> L, int col, const T* __restrict__ r, T* __restrict__ z) {
+    __shared__ T part[kRowWaves][3][64];
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int64_t cnt = L.coff[col + 1] - L.coff[col];
+    const int64_t tl = (int64_t)blockIdx.x * 64 + lane;
+    const bool valid = tl < cnt;
+    int i = 0, j = 0, k = 0;
+    int64_t t = 0;
+    T a0 = 0, a1 = 0, a2 = 0;
+    int64_t n = 0;
+    T b0 = 0, b1 = 0, b2 = 0, z0 = 0, z1 = 0, z2 = 0, D[9];
+    if (valid) {
+        t = L.coff[col] + tl;
+        int64_t q = tl;
+        i = 2 * (int)(q % L.cnx[col]) + (col & 1);
+        q /= L.cnx[col];
+        j = 2 * (int)(q % L.cny[col]) + ((col >> 1) & 1);
+        k = 2 * (int)(q / L.cny[col]) + (col >> 2);
+        n = nat(i, j, k, L.NX, L.NY);
+        if (g == 0) {
+            // operands of the update, loaded while the rows are summed
+            const T za = z[3 * L.nn];
+            b0 = r[3 * n] - L.acol[3 * n] * za;
+            b1 = r[3 * n + 1] - L.acol[3 * n + 1] * za;
+            b2 = r[3 * n + 2] - L.acol[3 * n + 2] * za;
+            z0 = z[3 * n];
+            z1 = z[3 * n + 1];
+            z2 = z[3 * n + 2];
+            for (int q9 = 0; q9 < 9; ++q9) D[q9] = L.dinv[(int64_t)q9 * L.nn + t];
+        }
+        row_partial(L, t, i, j, k, g, z, a0, a1, a2);
+    }
+    part[g][0][lane] = a0;
+    part[g][1][lane] = a1;
+    part[g][2][lane] = a2;
+    __syncthreads();
+    if (g == 0 && valid) {
+        for (int h = 0; h < kRowWaves; ++h) {
+            b0 -= part[h][0][lane];
+            b1 -= part[h][1][lane];
+            b2 -= part[h][2][lane];
+        }
+        z[3 * n] = z0 + (D[0] * b0 + D[1] * b1 + D[2] * b2);
+        z[3 * n + 1] = z1 + (D[3] * b0 + D[4] * b1 + D[5] * b2);
+        z[3 * n + 2] = z2 + (D[6] * b0 + D[7] * b1 + D[8] * b2);
+    }
+}
+
+// res = r - S z (displacement part, masked) and per-block partial sums of acol . z
+template <typename T>
+__global__ void __launch_bounds__(kBlk9)
+k_resid9(Level<T> L, const T* __restrict__ r, const T* __restrict__ z, T* __restrict__ res,
+         double* partials) {
+    __shared__ T part[kRowWaves][3][64];
+    __shared__ double red[64];
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const T za = z[3 * L.nn];
+    double acc = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * 64; base < L.nn; base += (int64_t)gridDim.x * 64) {
+        const int64_t t = base + lane;
+        const bool valid = t < L.nn;
+        int i = 0, j = 0, k = 0;
+        T a0 = 0, a1 = 0, a2 = 0;
+        if (valid) {
+            cm_decode(L, t, i, j, k);
+            row_partial(L, t, i, j, k, g, z, a0, a1, a2);
+        }
+        part[g][0][lane] = a0;
+        part[g][1][lane] = a1;
+        part[g][2][lane] = a2;
+        __syncthreads();
+        if (g == 0 && valid) {
+            const int64_t n = nat(i, j, k, L.NX, L.NY);
+            T b0 = r[3 * n] - L.acol[3 * n] * za;
+            T b1 = r[3 * n + 1] - L.acol[3 * n + 1] * za;
+            T b2 = r[3 * n + 2] - L.acol[3 * n + 2] * za;
+            for (int h = 0; h < kRowWaves; ++h) {
+                b0 -= part[h][0][lane];
+                b1 -= part[h][1][lane];
+                b2 -= part[h][2][lane];
+            }
+            res[3 * n] = L.fixed[3 * n] ? T(0) : b0;
+            res[3 * n + 1] = L.fixed[3 * n + 1] ? T(0) : b1;
+            res[3 * n + 2] = L.fixed[3 * n + 2] ? T(0) : b2;
+            acc += (double)L.acol[3 * n] * z[3 * n] + (double)L.acol[3 * n + 1] * z[3 * n + 1] +
+                   (double)L.acol[3 * n + 2] * z[3 * n + 2];
+        }
+        __syncthreads();
+    }
+    if (g == 0) {
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if (lane == 0) partials[SL_AUX * kRedBlocks + blockIdx.x] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// small levels: the whole V-cycle below a level in one workgroup (phases
+// separated by barriers), ending in the coarsest solve by the explicit inverse
+// ---------------------------------------------------------------------------
+template <typename T>
+struct SmallArgs {
+    Level<T> lev[kMaxSmallLevels];
+    int ks;                  // top level handled here
+    double d;                // alpha diagonal
+    const double* Ainv;
+    int nc;
+    const int* cinv;
+};
+
+// One workgroup of 1024 threads.  A colour pass splits each node's 9 neighbour
+// rows over G lanes (G = 9, 3 or 1, the largest that lets one pass cover the
+// colour); partial sums meet in LDS in a fixed order.
+constexpr int kSmallThreads = 1024;
+
+template <typename T>
+struct SmallShared {
+    T part[3][kSmallThreads];
+};
+
+template <typename T>
+__device__ void blk_gs_color(const Level<T>& L, int col, const T* r, T* z, SmallShared<T>& sh,
+                             bool first) {
+    const int64_t cnt = L.coff[col + 1] - L.coff[col];
+    const int G = cnt * 9 <= kSmallThreads ? 9 : (cnt * 3 <= kSmallThreads ? 3 : 1);
+    const int slots = kSmallThreads / G;
+    const int slot = threadIdx.x % slots, g = threadIdx.x / slots;
+    const bool lane_on = g < G;
+    const T za = first ? T(0) : z[3 * L.nn];
+    for (int64_t base = 0; base < cnt; base += slots) {
+        const int64_t tl = base + slot;
+        const bool valid = lane_on && tl < cnt;
+        int i = 0, j = 0, k = 0;
+        int64_t t = 0, n = 0;
+        T a0 = 0, a1 = 0, a2 = 0;
+        T c0 = 0, c1 = 0, c2 = 0, y0 = 0, y1 = 0, y2 = 0, D[9];
+        if (valid) {
+            t = L.coff[col] + tl;
+            int64_t q = tl;
+            i = 2 * (int)(q % L.cnx[col]) + (col & 1);
+            q /= L.cnx[col];
+            j = 2 * (int)(q % L.cny[col]) + ((col >> 1) & 1);
+            k = 2 * (int)(q / L.cny[col]) + (col >> 2);
+            n = nat(i, j, k, L.NX, L.NY);
+            if (g == 0) {
+                c0 = r[3 * n] - L.acol[3 * n] * za;
+                c1 = r[3 * n + 1] - L.acol[3 * n + 1] * za;
+                c2 = r[3 * n + 2] - L.acol[3 * n + 2] * za;
+                if (!first) {
+                    y0 = z[3 * n];
+                    y1 = z[3 * n + 1];
+                    y2 = z[3 * n + 2];
+                }
+                for (int q9 = 0; q9 < 9; ++q9) D[q9] = L.dinv[(int64_t)q9 * L.nn + t];
+            }
+            if (!first) {
+                const int per = kRowWaves / G;
+                for (int h = g * per; h < (g + 1) * per; ++h) {
+                    T b0, b1, b2;
+                    row_partial(L, t, i, j, k, h, z, b0, b1, b2);
+                    a0 += b0;
+                    a1 += b1;
+                    a2 += b2;
+                }
+            }
+        }
+        if (G > 1) {
+            if (lane_on) {
+                sh.part[0][threadIdx.x] = a0;
+                sh.part[1][threadIdx.x] = a1;
+                sh.part[2][threadIdx.x] = a2;
+            }
+            __syncthreads();
+        }
+        if (valid && g == 0) {
+            for (int h = 1; h < G; ++h) {
+                a0 += sh.part[0][h * slots + slot];
+                a1 += sh.part[1][h * slots + slot];
+                a2 += sh.part[2][h * slots + slot];
+            }
+            const T b0 = c0 - a0, b1 = c1 - a1, b2 = c2 - a2;
+            z[3 * n] = y0 + (D[0] * b0 + D[1] * b1 + D[2] * b2);
+            z[3 * n + 1] = y1 + (D[3] * b0 + D[4] * b1 + D[5] * b2);
+            z[3 * n + 2] = y2 + (D[6] * b0 + D[7] * b1 + D[8] * b2);
+        }
+        __syncthreads();
+    }
+}
+
+// mode 0: z_a += (r_a - acol.z - d z_a)/d ; mode 1: res_a = r_a - acol.z - d z_a
+template <typename T>
+__device__ void blk_alpha(const Level<T>& L, const T* r, T* z, T* res, double d, double* red,
+                          int mode) {
+    double acc = 0.0;
+    for (int64_t q = threadIdx.x; q < 3 * L.nn; q += blockDim.x)
+        acc += (double)L.acol[q] * (double)z[q];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += red[w];
+        const T td = (T)d;
+        const T v = r[3 * L.nn] - (T)sum - td * z[3 * L.nn];
+        if (mode == 0)
+            z[3 * L.nn] += v / td;
+        else
+            res[3 * L.nn] = v;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void blk_resid(const Level<T>& L, const T* r, const T* z, T* res) {
+    const T za = z[3 * L.nn];
+    for (int64_t t = threadIdx.x; t < L.nn; t += blockDim.x) {
+        int i, j, k;
+        cm_decode(L, t, i, j, k);
+        const int64_t n = nat(i, j, k, L.NX, L.NY);
+        T b0 = r[3 * n] - L.acol[3 * n] * za;
+        T b1 = r[3 * n + 1] - L.acol[3 * n + 1] * za;
+        T b2 = r[3 * n + 2] - L.acol[3 * n + 2] * za;
+        for (int h = 0; h < kRowWaves; ++h) {
+            T a0, a1, a2;
+            row_partial(L, t, i, j, k, h, z, a0, a1, a2);
+            b0 -= a0;
+            b1 -= a1;
+            b2 -= a2;
+        }
+        res[3 * n] = L.fixed[3 * n] ? T(0) : b0;
+        res[3 * n + 1] = L.fixed[3 * n + 1] ? T(0) : b1;
+        res[3 * n + 2] = L.fixed[3 * n + 2] ? T(0) : b2;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void blk_restrict(const Level<T>& F, const Level<T>& C, const T* rf, T* rc) {
+    for (int64_t N = threadIdx.x; N < C.nn; N += blockDim.x) {
+        const int I = (int)(N % C.NX);
+        const int64_t tt = N / C.NX;
+        const int J = (int)(tt % C.NY), K = (int)(tt / C.NY);
+        T a0 = 0, a1 = 0, a2 = 0;
+        for (int dk = -1; dk <= 1; ++dk) {
+            const int k = 2 * K + dk;
+            if (k < 0 || k >= F.NZ) continue;
+            const T wk = dk ? T(0.5) : T(1);
+            for (int dj = -1; dj <= 1; ++dj) {
+                const int j = 2 * J + dj;
+                if (j < 0 || j >= F.NY) continue;
+                const T wj = dj ? T(0.5) : T(1);
+                for (int di = -1; di <= 1; ++di) {
+                    const int i = 2 * I + di;
+                    if (i < 0 || i >= F.NX) continue;
+                    const T wgt = wk * wj * (di ? T(0.5) : T(1));
+                    const int64_t n = nat(i, j, k, F.NX, F.NY);
+                    a0 += wgt * rf[3 * n];
+                    a1 += wgt * rf[3 * n + 1];
+                    a2 += wgt * rf[3 * n + 2];
+                }
+            }
+        }
+        rc[3 * N] = C.fixed[3 * N] ? T(0) : a0;
+        rc[3 * N + 1] = C.fixed[3 * N + 1] ? T(0) : a1;
+        rc[3 * N + 2] = C.fixed[3 * N + 2] ? T(0) : a2;
+    }
+    if (threadIdx.x == 0) rc[3 * C.nn] = rf[3 * F.nn];
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void blk_prolong(const Level<T>& C, const Level<T>& F, const T* zc, T* zf) {
+    for (int64_t n = threadIdx.x; n < F.nn; n += blockDim.x) {
+        const int i = (int)(n % F.NX);
+        const int64_t tt = n / F.NX;
+        const int j = (int)(tt % F.NY), k = (int)(tt / F.NY);
+        const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1,
+                  k1 = (k + 1) >> 1;
+        const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1),
+                wk = (k & 1) ? T(0.5) : T(1);
+        T a0 = 0, a1 = 0, a2 = 0;
+        for (int b = 0; b < 8; ++b) {
+            if ((b & 1) && !(i & 1)) continue;
+            if (((b >> 1) & 1) && !(j & 1)) continue;
+            if ((b >> 2) && !(k & 1)) continue;
+            const int I = (b & 1) ? i1 : i0, J = ((b >> 1) & 1) ? j1 : j0, K = (b >> 2) ? k1 : k0;
+            const int64_t N = nat(I, J, K, C.NX, C.NY);
+            const T wgt = wi * wj * wk;
+            a0 += wgt * zc[3 * N];
+            a1 += wgt * zc[3 * N + 1];
+            a2 += wgt * zc[3 * N + 2];
+        }
+        if (!F.fixed[3 * n]) zf[3 * n] += a0;
+        if (!F.fixed[3 * n + 1]) zf[3 * n + 1] += a1;
+        if (!F.fixed[3 * n + 2]) zf[3 * n + 2] += a2;
+    }
+    if (threadIdx.x == 0) zf[3 * F.nn] += zc[3 * C.nn];
+    __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_vcycle_small(SmallArgs<T> a) {
+    __shared__ double red[kSmallThreads / 64];
+    __shared__ double xs[kSmallCoarse];
+    __shared__ SmallShared<T> sh;
+    // restriction phase: levels ks .. 1
+    for (int k = a.ks; k >= 1; --k) {
+        const Level<T>& L = a.lev[k];
+        // z = 0 except colour 0, which the first pass sets to D^{-1} r
+        for (int64_t t = L.coff[1] + threadIdx.x; t < L.nn; t += blockDim.x) {
+            int i, j, kk;
+            cm_decode(L, t, i, j, kk);
+            const int64_t n = nat(i, j, kk, L.NX, L.NY);
+            L.z[3 * n] = T(0);
+            L.z[3 * n + 1] = T(0);
+            L.z[3 * n + 2] = T(0);
+        }
+        if (threadIdx.x == 0) L.z[3 * L.nn] = T(0);
+        blk_gs_color(L, 0, L.r, L.z, sh, true);
+        for (int col = 1; col < 8; ++col) blk_gs_color(L, col, L.r, L.z, sh, false);
+        blk_alpha(L, L.r, L.z, L.res, a.d, red, 0);
+        blk_resid(L, L.r, L.z, L.res);
+        blk_alpha(L, L.r, L.z, L.res, a.d, red, 1);
+        blk_restrict(L, a.lev[k - 1], L.res, a.lev[k - 1].r);
+    }
+    // coarsest level: z0 = S_0^{-1} r0 with the explicit inverse
+    {
+        const Level<T>& L = a.lev[0];
+        const int nc = a.nc;
+        for (int q = threadIdx.x; q < nc - 1; q += blockDim.x) xs[q] = (double)L.r[a.cinv[q]];
+        if (threadIdx.x == 0) xs[nc - 1] = (double)L.r[3 * L.nn];
+        for (int64_t q = threadIdx.x; q < 3 * L.nn + 1; q += blockDim.x) L.z[q] = T(0);
+        __syncthreads();
+        for (int row = threadIdx.x; row < nc; row += blockDim.x) {
+            const double* Ar = a.Ainv + (int64_t)row * nc;
+            double y = 0.0;
+            for (int col = 0; col < nc; ++col) y += Ar[col] * xs[col];
+            if (row < nc - 1)
+                L.z[a.cinv[row]] = (T)y;
+            else
+                L.z[3 * L.nn] = (T)y;
+        }
+        __syncthreads();
+    }
+    // prolongation phase: levels 1 .. ks
+    for (int k = 1; k <= a.ks; ++k) {
+        const Level<T>& L = a.lev[k];
+        blk_prolong(a.lev[k - 1], L, a.lev[k - 1].z, L.z);
+        blk_alpha(L, L.r, L.z, L.res, a.d, red, 0);
+        for (int col = 7; col >= 0; --col) blk_gs_color(L, col, L.r, L.z, sh, false);
+    }
+}
+
+// column j of the inverse of L L^T (Cholesky factor in A), one block per column
+__global__ void __launch_bounds__(256)
+k_chol_inverse(const double* __restrict__ A, int nc, double* __restrict__ Ainv) {
+    __shared__ double x[kMaxCoarse];
+    const int jcol = blockIdx.x;
+    for (int q = threadIdx.x; q < nc; q += blockDim.x) x[q] = (q == jcol) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int k = 0; k < nc; ++k) {
+        if (threadIdx.x == 0) x[k] /= A[(int64_t)k * nc + k];
+        __syncthreads();
+        const double xk = x[k];
+        for (int i = k + 1 + threadIdx.x; i < nc; i += blockDim.x) x[i] -= A[(int64_t)i * nc + k] * xk;
+        __syncthreads();
+    }
+    for (int k = nc - 1; k >= 0; --k) {
+        if (threadIdx.x == 0) x[k] /= A[(int64_t)k * nc + k];
+        __syncthreads();
+        const double xk = x[k];
+        for (int i = threadIdx.x; i < k; i += blockDim.x) x[i] -= A[(int64_t)k * nc + i] * xk;
+        __syncthreads();
+    }
+    for (int q = threadIdx.x; q < nc; q += blockDim.x) Ainv[(int64_t)q * nc + jcol] = x[q];
+}
+
 template <typename Tin, typename Tout>
 __global__ void k_convert(const Tin* __restrict__ a, Tout* __restrict__ b, int64_t n) {
     const int64_t t = gidx();
@@ -628,11 +958,24 @@ void mg_build(Ctx& c, Hierarchy<T>& H) {
     hipLaunchKernelGGL(k_coarse_assemble<T>, dim3(grid_of(L0.nn * kStencil)), dim3(kThreads), 0,
                        c.s, L0, H.cmap, H.nc, c.sum_w, H.A);
     hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, c.s, H.A, H.nc, H.flag);
+    if (H.ksmall >= 0)
+        hipLaunchKernelGGL(k_chol_inverse, dim3(H.nc), dim3(256), 0, c.s, H.A, H.nc, H.Ainv);
 }
 
 template <typename T>
 static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
     Level<T>& Lk = H.lev[k];
+    if (k <= H.ksmall) {
+        SmallArgs<T> a;
+        for (int q = 0; q <= k; ++q) a.lev[q] = H.lev[q];
+        a.ks = k;
+        a.d = c.sum_w;
+        a.Ainv = H.Ainv;
+        a.nc = H.nc;
+        a.cinv = H.cinv;
+        hipLaunchKernelGGL(k_vcycle_small<T>, dim3(1), dim3(1024), 0, c.s, a);
+        return;
+    }
     if (k == 0) {
         hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(1024), 0, c.s, H.A, H.nc, H.cmap,
                            Lk.nn, Lk.r, Lk.z);
@@ -646,16 +989,17 @@ static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
     for (int col = 0; col < 8; ++col) {
         const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
         if (cnt == 0) continue;
-        hipLaunchKernelGGL(k_gs_color<T>, dim3(grid_of(cnt)), dim3(kThreads), 0, c.s, Lk, col,
-                           (const T*)Lk.r, Lk.z);
+        hipLaunchKernelGGL(k_gs_color9<T>, dim3((unsigned)((cnt + 63) / 64)), dim3(kBlk9), 0, c.s,
+                           Lk, col, (const T*)Lk.r, Lk.z);
     }
     hipLaunchKernelGGL(k_acol_dot<T>, dim3(gr), dim3(kThreads), 0, c.s, Lk, (const T*)Lk.z,
                        c.partials);
     hipLaunchKernelGGL(k_alpha_fin<T>, dim3(1), dim3(kThreads), 0, c.s, c.partials, gr, Lk.nn, d,
                        (const T*)Lk.r, Lk.z, Lk.res, 0);
     // residual, restriction, coarse correction, prolongation
-    const int grr = red_grid_of(Lk.nn);
-    hipLaunchKernelGGL(k_resid<T>, dim3(grr), dim3(kThreads), 0, c.s, Lk, (const T*)Lk.r,
+    int64_t chunks = (Lk.nn + 63) / 64;
+    const int grr = (int)(chunks < kRedBlocks ? chunks : kRedBlocks);
+    hipLaunchKernelGGL(k_resid9<T>, dim3(grr), dim3(kBlk9), 0, c.s, Lk, (const T*)Lk.r,
                        (const T*)Lk.z, Lk.res, c.partials);
     hipLaunchKernelGGL(k_alpha_fin<T>, dim3(1), dim3(kThreads), 0, c.s, c.partials, grr, Lk.nn, d,
                        (const T*)Lk.r, Lk.z, Lk.res, 1);
@@ -673,8 +1017,8 @@ static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
     for (int col = 7; col >= 0; --col) {
         const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
         if (cnt == 0) continue;
-        hipLaunchKernelGGL(k_gs_color<T>, dim3(grid_of(cnt)), dim3(kThreads), 0, c.s, Lk, col,
-                           (const T*)Lk.r, Lk.z);
+        hipLaunchKernelGGL(k_gs_color9<T>, dim3((unsigned)((cnt + 63) / 64)), dim3(kBlk9), 0, c.s,
+                           Lk, col, (const T*)Lk.r, Lk.z);
     }
 }
 

@@ -43,10 +43,17 @@ template <typename T>
 struct Hierarchy {
     std::vector<Level<T>> lev;   // 0 = coarsest
     double* A = nullptr;         // dense coarsest matrix / Cholesky factor, nc x nc
+    double* Ainv = nullptr;      // explicit inverse of the coarsest matrix, nc x nc
     int nc = 0;
     int* cmap = nullptr;         // 3*nn_0 -> dense index or -1
+    int* cinv = nullptr;         // dense index -> DOF of level 0 (nc-1 entries)
     int* flag = nullptr;         // device: 1 if the factorization met a non-positive pivot
+    int ksmall = -1;             // levels 0..ksmall run in one workgroup (-1: none)
 };
+
+constexpr int kSmallNodes = 4096;   // largest level handled by the one-workgroup V-cycle
+constexpr int kSmallCoarse = 2048;  // largest coarsest system for that kernel
+constexpr int kMaxSmallLevels = 6;
 
 struct Ctx {
     // problem
@@ -63,6 +70,9 @@ struct Ctx {
     float* Kef = nullptr;        // 576
     double* Mc = nullptr;        // 8 x 576: Q_c^T K_e Q_c
     double* Qc = nullptr;        // 8 x 8 x 8: Q_c[a][A] nodal interpolation weights
+    double kh8[8] = {};          // the 8 coefficients of H K_e H / 64 (sum/difference basis)
+    bool kh_ok = false;          // K_e has the cube's structure in that basis
+    double* spart = nullptr;     // per-workgroup partial sums of the tiled S-apply
 
     // problem data (device)
     uint8_t* fixed = nullptr;    // ndof
@@ -159,6 +169,14 @@ void launch_minres_w(Ctx& c, double* w, const double* v, const double* w1, const
                      double eps_old, double delta, double inv_gamma, double* x, double phi,
                      int64_t n);
 void launch_round_rho(Ctx& c);
+
+// operator.hip: tiled element operators (sum/difference form of K_e)
+bool tile_ok(const Ctx& c);
+int apply_S_tile_blocks(const Ctx& c);
+void launch_apply_K_tile_f64(Ctx& c, const double* rho, const double* x, double* y);
+void launch_apply_K_tile_f32(Ctx& c, const float* rho, const float* x, float* y);
+void launch_apply_S_tile(Ctx& c, const double* x, double* y);
+bool walsh_form(const double* Ke, double* kh8);    // host_fe.cpp
 
 template <typename T> void mg_build(Ctx& c, Hierarchy<T>& H);
 template <typename T> void mg_vcycle(Ctx& c, Hierarchy<T>& H, const double* r, double* z);

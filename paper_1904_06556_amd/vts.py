@@ -43,6 +43,7 @@ class Problem_t(C.Structure):
 
 class Options_t(C.Structure):
     _fields_ = [("beta", C.c_double), ("gamma", C.c_double), ("p_min", C.c_double),
+                ("q_min", C.c_double),
                 ("eps_pbm", C.c_double), ("eps_nwt0", C.c_double), ("eps_nwt_min", C.c_double),
                 ("eps_nwt_final", C.c_double), ("eps_stat", C.c_double),
                 ("accept_stall", C.c_double), ("eps_mr0", C.c_double),
@@ -83,6 +84,7 @@ SIGNATURES = {
     "vts_default_options": (None, [C.POINTER(Options_t)]),
     "vts_create": (C.c_int, [C.POINTER(Problem_t), C.POINTER(Options_t), _P, C.POINTER(_P)]),
     "vts_destroy": (None, [_P]),
+    "vts_reset": (C.c_int, [_P]),
     "vts_footprint_bytes": (C.c_size_t, [C.POINTER(Problem_t), C.POINTER(Options_t)]),
     "vts_sizes": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                             C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
@@ -219,6 +221,9 @@ class Context:
     def _check(self, st):
         if st != VTS_OK:
             raise VtsError(st, lib().vts_last_error(self.h).decode())
+
+    def reset(self):
+        self._check(lib().vts_reset(self.h))
 
     # --- operators -------------------------------------------------------
     def set_rho(self, rho):

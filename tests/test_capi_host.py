@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_options_match_oracle_defaults():
     o = V.default_options()
     p = opbm.Options()
-    for k in ("beta", "gamma", "p_min", "eps_pbm", "eps_nwt0", "eps_nwt_min", "eps_nwt_final",
+    for k in ("beta", "gamma", "p_min", "q_min", "eps_pbm", "eps_nwt0", "eps_nwt_min", "eps_nwt_final",
               "eps_stat", "accept_stall", "eps_mr_min", "armijo_c1", "armijo_min",
               "max_outer", "max_newton", "max_minres"):
         assert getattr(o, k) == pytest.approx(getattr(p, k), rel=0, abs=0), k
