@@ -75,6 +75,20 @@ def kernel_roofline(torch, ctx, pr, reps=200):
     return bytes_per, res
 
 
+def profiled(ctx, kernel_class, run):
+    """Average duration and algorithmic bytes of every launch of one kernel
+    class during `run()`, timed by the library with HIP events recorded on
+    its own stream around each launch."""
+    ctx.profile_start(kernel_class)
+    run()
+    p = ctx.profile_stop()
+    n = max(p["launches"], 1)
+    ms = p["total_ms"] / n
+    bpl = p["bytes"] / n
+    return dict(launches=p["launches"], avg_launch_ms=ms, bytes_per_launch=bpl,
+                gbs=bpl / (ms * 1e-3) / 1e9 if ms > 0 else 0.0)
+
+
 def minres_rate(torch, ctx, its=50):
     """MINRES-MG iterations per second at the converged Newton point (fixed
     iteration count: tolerance 0)."""
@@ -167,6 +181,16 @@ def main():
         g = json.load(open(gold))
         c_err = abs(last["compliance"] - g["compliance_half_fu"]) / g["compliance_half_fu"]
 
+    # dominant kernel (Gauss-Seidel colour pass on the finest level) and the
+    # S-apply, each timed over every launch of one further complete solve
+    def solve_again():
+        ctx.reset()
+        ctx.pbm_solve()
+    gs = profiled(ctx, "gs_fine", solve_again)
+    sa = profiled(ctx, "apply_S", solve_again)
+    print(f"profiled: gs_fine {gs['launches']} launches {gs['avg_launch_ms'] * 1e3:.2f} us, "
+          f"apply_S {sa['launches']} launches {sa['avg_launch_ms'] * 1e3:.2f} us",
+          file=sys.stderr, flush=True)
     mr_rate, mr_its = minres_rate(torch, ctx)
     bytes_per, kr = kernel_roofline(torch, ctx, pr)
     rot = kr["rotating"]
@@ -189,10 +213,20 @@ def main():
         "outer": last["outer"], "newton": last["newton"], "minres": last["minres"],
         "k_apply_gdofs": rot["gdofs"], "k_apply_gdofs_hot_cache": kr["hot"]["gdofs"],
         "minres_mg_iters_per_s": mr_rate,
-        "roofline": {"kernel": "k_apply_K<double> (K(rho)x, FP64)", "bound": "hbm",
-                     "achieved": rot["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": rot["gbs"] / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": bytes_per, "avg_launch_ms": rot["ms"]},
+        "roofline": {"kernel": "k_gs_color9<double, true> (finest-level multicolour "
+                               "block Gauss-Seidel pass)",
+                     "bound": "hbm", "achieved": gs["gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": gs["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": gs["bytes_per_launch"],
+                     "avg_launch_ms": gs["avg_launch_ms"], "launches": gs["launches"]},
+        "kernels": {
+            "apply_S_tile": {"avg_launch_ms": sa["avg_launch_ms"], "gbs": sa["gbs"],
+                             "bytes_per_launch": sa["bytes_per_launch"],
+                             "launches_per_solve": sa["launches"]},
+            "apply_K_tile_f64": {"avg_launch_ms": rot["ms"], "gbs": rot["gbs"],
+                                 "gdofs": rot["gdofs"], "bytes_per_launch": bytes_per,
+                                 "buffers": "rotating, working set > 512 MB"},
+            "gs_fine_launches_per_solve": gs["launches"]},
     }
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pr, eps_mr0, last["newton"], a.cpu_seconds)

@@ -233,6 +233,26 @@ vts_status vts_pbm_solve(vts_ctx* ctx, vts_result* result);
 /* Copies an internal vector (see vts_vector) to dst_dev (device). */
 vts_status vts_get_vector(const vts_ctx* ctx, int32_t which, double* dst_dev);
 
+/* Kernel classes that vts_profile_start can time. */
+typedef enum {
+    VTS_PROF_NONE = 0,
+    VTS_PROF_GS_FINE = 1,   /* Gauss-Seidel colour pass on the finest level */
+    VTS_PROF_APPLY_K = 2,   /* K(rho) x (vts_apply_K) */
+    VTS_PROF_APPLY_S = 3    /* S-apply (MINRES and vts_apply_S) */
+} vts_prof_kernel;
+
+/* Starts timing every launch of one kernel class with HIP events recorded
+ * on the context's stream (a measurement aid; it adds two event records per
+ * launch).  Any previous profile is discarded. */
+vts_status vts_profile_start(vts_ctx* ctx, int32_t kernel_class);
+
+/* Stops profiling, synchronizes the stream and returns the summed kernel
+ * time in ms, the number of timed launches and their summed algorithmic
+ * bytes (the compulsory traffic of each launch, as documented in the
+ * kernels).  Any output pointer may be NULL. */
+vts_status vts_profile_stop(vts_ctx* ctx, double* total_ms, int64_t* launches,
+                            double* bytes);
+
 /* Checkpoint of the PBM state to host memory, layout (FP64):
  *   u[n_dof], alpha, nu_lo[m], nu_hi[m], rho[m], mu_lo[m], mu_hi[m],
  *   p[m], q_lo[m], q_hi[m], eps_nwt, eps_mr

@@ -635,6 +635,8 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
 void ctx_free(Ctx& c) {
     if (c.s) hipStreamSynchronize(c.s);
     else hipDeviceSynchronize();
+    for (hipEvent_t e : c.prof_ev) hipEventDestroy(e);
+    c.prof_ev.clear();
     for (void* p : c.allocs) hipFree(p);
     c.allocs.clear();
     if (c.red_host) hipHostFree(c.red_host);
@@ -648,6 +650,28 @@ void ctx_free(Ctx& c) {
 thread_local std::string g_create_err;
 
 }  // namespace
+
+namespace vts {
+
+bool prof_begin(Ctx& c, int cls) {
+    if (c.prof_class != cls) return false;
+    const size_t need = 2 * (c.prof_n + 1);
+    while (c.prof_ev.size() < need) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return false;
+        c.prof_ev.push_back(e);
+    }
+    hipEventRecord(c.prof_ev[2 * c.prof_n], c.s);
+    return true;
+}
+
+void prof_end(Ctx& c, double bytes) {
+    hipEventRecord(c.prof_ev[2 * c.prof_n + 1], c.s);
+    c.prof_n += 1;
+    c.prof_bytes += bytes;
+}
+
+}  // namespace vts
 
 extern "C" {
 
@@ -932,6 +956,35 @@ vts_status vts_set_state(vts_ctx* cp, const void* buf, size_t bytes) {
     c.eval_valid = false;
     c.setup_valid = false;
     c.converged = false;
+    return VTS_OK;
+}
+
+vts_status vts_profile_start(vts_ctx* cp, int32_t cls) {
+    if (!cp || cls < VTS_PROF_NONE || cls > VTS_PROF_APPLY_S) return VTS_EINVAL;
+    Ctx& c = *cp;
+    HIPCHK(hipStreamSynchronize(c.s));
+    c.prof_class = cls;
+    c.prof_n = 0;
+    c.prof_bytes = 0.0;
+    return VTS_OK;
+}
+
+vts_status vts_profile_stop(vts_ctx* cp, double* total_ms, int64_t* launches, double* bytes) {
+    if (!cp) return VTS_EINVAL;
+    Ctx& c = *cp;
+    HIPCHK(hipStreamSynchronize(c.s));
+    double ms = 0.0;
+    for (size_t q = 0; q < c.prof_n; ++q) {
+        float t = 0.0f;
+        HIPCHK(hipEventElapsedTime(&t, c.prof_ev[2 * q], c.prof_ev[2 * q + 1]));
+        ms += t;
+    }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = (int64_t)c.prof_n;
+    if (bytes) *bytes = c.prof_bytes;
+    c.prof_class = 0;
+    c.prof_n = 0;
+    c.prof_bytes = 0.0;
     return VTS_OK;
 }
 

@@ -147,7 +147,10 @@ k_apply_K(int nx, int ny, int nz, const T* __restrict__ Ke, const T* __restrict_
 
 void launch_apply_K_f64(Ctx& c, const double* rho, const double* x, double* y) {
     if (tile_ok(c)) {
+        // algorithmic bytes: x, y, rho (8 B each entry) and the DOF mask
+        const bool prof = prof_begin(c, VTS_PROF_APPLY_K);
         launch_apply_K_tile_f64(c, rho, x, y);
+        if (prof) prof_end(c, 16.0 * c.ndof + 8.0 * c.m + c.ndof);
         return;
     }
     hipLaunchKernelGGL(k_apply_K<double>, dim3(grid1d(c.nn)), dim3(kThreads), 0, c.s,
@@ -416,7 +419,10 @@ __global__ void k_store_neg(const double* __restrict__ red, int slot, double* __
 
 void launch_apply_S(Ctx& c, const double* x, double* y) {
     if (tile_ok(c)) {
+        // algorithmic bytes: x, u, y, rho', w and the DOF mask
+        const bool prof = prof_begin(c, VTS_PROF_APPLY_S);
         launch_apply_S_tile(c, x, y);
+        if (prof) prof_end(c, 24.0 * c.ndof + 16.0 * c.m + c.ndof);
         return;
     }
     const int g = red_grid(c.m);

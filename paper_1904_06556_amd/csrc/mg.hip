@@ -530,7 +530,8 @@ __device__ __forceinline__ void row_partial(const Level<T>& L, int64_t t, int i,
     }
 }
 
-template <typename T>
+// TOP = finest level (a separate instantiation so profiles tell them apart)
+template <typename T, bool TOP>
 __global__ void __launch_bounds__(kBlk9)
 k_gs_color9(Level<T> L, int col, const T* __restrict__ r, T* __restrict__ z) {
     __shared__ T part[kRowWaves][3][64];
@@ -581,7 +582,7 @@ k_gs_color9(Level<T> L, int col, const T* __restrict__ r, T* __restrict__ z) {
 }
 
 // res = r - S z (displacement part, masked) and per-block partial sums of acol . z
-template <typename T>
+template <typename T, bool TOP>
 __global__ void __launch_bounds__(kBlk9)
 k_resid9(Level<T> L, const T* __restrict__ r, const T* __restrict__ z, T* __restrict__ res,
          double* partials) {
@@ -962,9 +963,27 @@ void mg_build(Ctx& c, Hierarchy<T>& H) {
         hipLaunchKernelGGL(k_chol_inverse, dim3(H.nc), dim3(256), 0, c.s, H.A, H.nc, H.Ainv);
 }
 
+// one colour pass; on the finest level optionally bracketed by the
+// profiling events of the context (kernel class VTS_PROF_GS_FINE)
+template <typename T>
+static void gs_color_launch(Ctx& c, Level<T>& Lk, int col, bool top) {
+    const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
+    const dim3 grid((unsigned)((cnt + 63) / 64));
+    if (top) {
+        const bool prof = prof_begin(c, VTS_PROF_GS_FINE);
+        hipLaunchKernelGGL((k_gs_color9<T, true>), grid, dim3(kBlk9), 0, c.s, Lk, col,
+                           (const T*)Lk.r, Lk.z);
+        if (prof) prof_end(c, gs_color_bytes(Lk, col, sizeof(T)));
+    } else {
+        hipLaunchKernelGGL((k_gs_color9<T, false>), grid, dim3(kBlk9), 0, c.s, Lk, col,
+                           (const T*)Lk.r, Lk.z);
+    }
+}
+
 template <typename T>
 static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
     Level<T>& Lk = H.lev[k];
+    const bool top = k == (int)H.lev.size() - 1;
     if (k <= H.ksmall) {
         SmallArgs<T> a;
         for (int q = 0; q <= k; ++q) a.lev[q] = H.lev[q];
@@ -989,8 +1008,7 @@ static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
     for (int col = 0; col < 8; ++col) {
         const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
         if (cnt == 0) continue;
-        hipLaunchKernelGGL(k_gs_color9<T>, dim3((unsigned)((cnt + 63) / 64)), dim3(kBlk9), 0, c.s,
-                           Lk, col, (const T*)Lk.r, Lk.z);
+        gs_color_launch(c, Lk, col, top);
     }
     hipLaunchKernelGGL(k_acol_dot<T>, dim3(gr), dim3(kThreads), 0, c.s, Lk, (const T*)Lk.z,
                        c.partials);
@@ -999,8 +1017,12 @@ static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
     // residual, restriction, coarse correction, prolongation
     int64_t chunks = (Lk.nn + 63) / 64;
     const int grr = (int)(chunks < kRedBlocks ? chunks : kRedBlocks);
-    hipLaunchKernelGGL(k_resid9<T>, dim3(grr), dim3(kBlk9), 0, c.s, Lk, (const T*)Lk.r,
-                       (const T*)Lk.z, Lk.res, c.partials);
+    if (top)
+        hipLaunchKernelGGL((k_resid9<T, true>), dim3(grr), dim3(kBlk9), 0, c.s, Lk, (const T*)Lk.r,
+                           (const T*)Lk.z, Lk.res, c.partials);
+    else
+        hipLaunchKernelGGL((k_resid9<T, false>), dim3(grr), dim3(kBlk9), 0, c.s, Lk, (const T*)Lk.r,
+                           (const T*)Lk.z, Lk.res, c.partials);
     hipLaunchKernelGGL(k_alpha_fin<T>, dim3(1), dim3(kThreads), 0, c.s, c.partials, grr, Lk.nn, d,
                        (const T*)Lk.r, Lk.z, Lk.res, 1);
     Level<T>& Lc = H.lev[k - 1];
@@ -1017,8 +1039,7 @@ static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
     for (int col = 7; col >= 0; --col) {
         const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
         if (cnt == 0) continue;
-        hipLaunchKernelGGL(k_gs_color9<T>, dim3((unsigned)((cnt + 63) / 64)), dim3(kBlk9), 0, c.s,
-                           Lk, col, (const T*)Lk.r, Lk.z);
+        gs_color_launch(c, Lk, col, top);
     }
 }
 

@@ -51,7 +51,7 @@ struct Hierarchy {
     int ksmall = -1;             // levels 0..ksmall run in one workgroup (-1: none)
 };
 
-constexpr int kSmallNodes = 4096;   // largest level handled by the one-workgroup V-cycle
+constexpr int kSmallNodes = 512;    // largest level handled by the one-workgroup V-cycle
 constexpr int kSmallCoarse = 2048;  // largest coarsest system for that kernel
 constexpr int kMaxSmallLevels = 6;
 
@@ -138,7 +138,26 @@ struct Ctx {
     std::string err;
 
     std::vector<void*> allocs;
+
+    // kernel-class profiling (vts_profile_start/stop): HIP events around
+    // every launch of one class on this context's stream
+    int prof_class = 0;
+    std::vector<hipEvent_t> prof_ev;
+    size_t prof_n = 0;
+    double prof_bytes = 0.0;
 };
+
+// profiling hooks (capi.cpp); prof_begin returns true if this launch is timed
+bool prof_begin(Ctx& c, int cls);
+void prof_end(Ctx& c, double bytes);
+
+// algorithmic bytes of one colour pass: the colour's stencil rows and
+// inverse diagonal blocks, r, acol, z (read and write), neighbour z values
+template <typename T>
+inline double gs_color_bytes(const Level<T>& L, int col, size_t ts) {
+    const double cnt = (double)(L.coff[col + 1] - L.coff[col]);
+    return cnt * (kStencilVals + 9 + 12) * ts + ((double)L.nn - cnt) * 3 * ts;
+}
 
 // host-side finite-element tables (host_fe.cpp)
 void element_stiffness(double E, double nu, double h, double* Ke576);

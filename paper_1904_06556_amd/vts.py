@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "VTS_OK", 1: "VTS_EINVAL", 2: "VTS_ENOMEM", 3: "VTS_EDEVICE",
                 4: "VTS_ESTATE", 5: "VTS_ENOTCONV", 6: "VTS_ENONDESCENT", 7: "VTS_ENONSPD"}
 VTS_FP64, VTS_MIXED = 0, 1
 
+PROF = dict(gs_fine=1, apply_K=2, apply_S=3)
 VEC = dict(u=0, rho=1, energy=2, rhs=3, dy=4, g1=5, dnu_lo=6, dnu_hi=7, rho1=8, w=9)
 
 
@@ -103,6 +104,9 @@ SIGNATURES = {
     "vts_get_vector": (C.c_int, [_P, C.c_int32, _P]),
     "vts_get_state": (C.c_int, [_P, _P, C.POINTER(C.c_size_t)]),
     "vts_set_state": (C.c_int, [_P, _P, C.c_size_t]),
+    "vts_profile_start": (C.c_int, [_P, C.c_int32]),
+    "vts_profile_stop": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_double)]),
     "vts_last_error": (C.c_char_p, [_P]),
 }
 
@@ -285,6 +289,16 @@ class Context:
         if check:
             self._check(st)
         return _struct_dict(r)
+
+    # --- profiling -------------------------------------------------------
+    def profile_start(self, kernel_class):
+        k = PROF[kernel_class] if isinstance(kernel_class, str) else kernel_class
+        self._check(lib().vts_profile_start(self.h, k))
+
+    def profile_stop(self):
+        ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+        self._check(lib().vts_profile_stop(self.h, C.byref(ms), C.byref(n), C.byref(b)))
+        return dict(total_ms=ms.value, launches=n.value, bytes=b.value)
 
     # --- state -----------------------------------------------------------
     def get_vector(self, which, out):
