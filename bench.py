@@ -41,6 +41,11 @@ def parse():
                     help="0: cantilever 8x4x4, 1: cantilever 64x32x32 (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--kernels", action="store_true",
+                    help="kernel-only run for hardware-counter passes: R V-cycles, R K(rho)x, "
+                         "R S-applies at the initial Newton point and R plain copies of "
+                         "256 MiB (the counter scale reference); prints one JSON line")
+    ap.add_argument("--reps", type=int, default=10)
     return ap.parse_args()
 
 
@@ -73,6 +78,35 @@ def kernel_roofline(torch, ctx, pr, reps=200):
                           gdofs=n_dof / (ms * 1e-3) / 1e9)
     del xs, ys
     return bytes_per, res
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pmc_cant-64x32x32_fp64.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("mg.hip", "vts_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1904_06556_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_name):
+    """HBM bytes per launch of the finest-level Gauss-Seidel pass from the
+    committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary (scaled by the copy
+    reference); None if it covers another workload or the kernel sources
+    changed since the counters were taken."""
+    if workload_name != "cant-64x32x32" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    val, src = None, None
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if line.startswith("traffic_bytes_per_launch k_gs_color9<double, true>"):
+                val = float(line.split("=")[1])
+            elif line.startswith("kernel_source_sha256_16"):
+                src = line.split("=")[1].strip()
+    return val if (val is not None and src == kernel_source_hash()) else None
 
 
 def profiled(ctx, kernel_class, run):
@@ -134,6 +168,38 @@ def cpu_baseline(pr, eps_mr0, newton_steps_gpu, budget_s):
                 seconds_per_newton=per_newton)
 
 
+def kernels_only(a, torch, W, V):
+    """Each hot kernel a fixed number of times, for rocprofv3 counter passes."""
+    pr = W.config(a.workload)
+    prec = V.VTS_MIXED if pr.extra.get("precision") == "mixed" else V.VTS_FP64
+    ctx = V.Context.from_problem(pr, precision=prec)
+    ctx.reset()
+    ctx.newton_setup()
+    g = torch.Generator(device="cpu").manual_seed(1)
+    r = (torch.rand(ctx.n_dof + 1, generator=g, dtype=torch.float64) - 0.5).cuda()
+    z = torch.empty_like(r)
+    x = (torch.rand(ctx.n_dof, generator=g, dtype=torch.float64) - 0.5).cuda()
+    y = torch.empty_like(x)
+    for _ in range(a.reps):
+        ctx.precondition(r, z)
+    for _ in range(a.reps):
+        ctx.apply_K(x, y)
+    for _ in range(a.reps):
+        ctx.apply_S(r, z)
+    copy_bytes = 256 << 20
+    src = torch.ones(copy_bytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(a.reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "kernels", "workload": pr.name, "reps": a.reps,
+                      "n_dof": ctx.n_dof, "m": ctx.m,
+                      "copy_bytes_read": copy_bytes, "copy_bytes_written": copy_bytes}),
+          flush=True)
+    ctx.close()
+    return 0
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -144,6 +210,8 @@ def main():
     import workloads as W
     from paper_1904_06556_amd import vts as V
 
+    if a.kernels:
+        return kernels_only(a, torch, W, V)
     pr = W.config(a.workload)
     eps_mr0 = pr.extra.get("eps_mr0")
     opts = V.default_options()
@@ -216,7 +284,9 @@ def main():
         "roofline": {"kernel": "k_gs_color9<double, true> (finest-level multicolour "
                                "block Gauss-Seidel pass)",
                      "bound": "hbm", "achieved": gs["gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": gs["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": gs["gbs"] / HBM_PEAK_GBS,
+                     "traffic": (measured_traffic(pr.name)
+                                 if prec == V.VTS_FP64 else None),
                      "bytes_per_launch": gs["bytes_per_launch"],
                      "avg_launch_ms": gs["avg_launch_ms"], "launches": gs["launches"]},
         "kernels": {

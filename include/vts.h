@@ -242,12 +242,14 @@ typedef enum {
 } vts_prof_kernel;
 
 /* Starts timing every launch of one kernel class with HIP events recorded
- * on the context's stream (a measurement aid; it adds two event records per
- * launch).  Any previous profile is discarded. */
+ * on the context's stream (a measurement aid).  Consecutive launches of the
+ * class (the 8 colour passes of one Gauss-Seidel sweep) share one event
+ * pair; single launches (K(rho)x, S-apply) get one pair each, which adds
+ * the event overhead to their times.  Any previous profile is discarded. */
 vts_status vts_profile_start(vts_ctx* ctx, int32_t kernel_class);
 
 /* Stops profiling, synchronizes the stream and returns the summed kernel
- * time in ms, the number of timed launches and their summed algorithmic
+ * time in ms, the number of kernel launches timed and their summed algorithmic
  * bytes (the compulsory traffic of each launch, as documented in the
  * kernels).  Any output pointer may be NULL. */
 vts_status vts_profile_stop(vts_ctx* ctx, double* total_ms, int64_t* launches,

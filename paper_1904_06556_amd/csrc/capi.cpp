@@ -665,9 +665,10 @@ bool prof_begin(Ctx& c, int cls) {
     return true;
 }
 
-void prof_end(Ctx& c, double bytes) {
+void prof_end(Ctx& c, double bytes, int launches) {
     hipEventRecord(c.prof_ev[2 * c.prof_n + 1], c.s);
     c.prof_n += 1;
+    c.prof_launches += launches;
     c.prof_bytes += bytes;
 }
 
@@ -965,6 +966,7 @@ vts_status vts_profile_start(vts_ctx* cp, int32_t cls) {
     HIPCHK(hipStreamSynchronize(c.s));
     c.prof_class = cls;
     c.prof_n = 0;
+    c.prof_launches = 0;
     c.prof_bytes = 0.0;
     return VTS_OK;
 }
@@ -980,10 +982,11 @@ vts_status vts_profile_stop(vts_ctx* cp, double* total_ms, int64_t* launches, do
         ms += t;
     }
     if (total_ms) *total_ms = ms;
-    if (launches) *launches = (int64_t)c.prof_n;
+    if (launches) *launches = c.prof_launches;
     if (bytes) *bytes = c.prof_bytes;
     c.prof_class = 0;
     c.prof_n = 0;
+    c.prof_launches = 0;
     c.prof_bytes = 0.0;
     return VTS_OK;
 }

@@ -963,21 +963,30 @@ void mg_build(Ctx& c, Hierarchy<T>& H) {
         hipLaunchKernelGGL(k_chol_inverse, dim3(H.nc), dim3(256), 0, c.s, H.A, H.nc, H.Ainv);
 }
 
-// one colour pass; on the finest level optionally bracketed by the
-// profiling events of the context (kernel class VTS_PROF_GS_FINE)
+// one Gauss-Seidel sweep over the 8 colours (forward 0..7 or backward
+// 7..0); on the finest level the whole sweep is optionally bracketed by the
+// profiling events of the context (kernel class VTS_PROF_GS_FINE), so the
+// average per launch carries no per-launch event overhead
 template <typename T>
-static void gs_color_launch(Ctx& c, Level<T>& Lk, int col, bool top) {
-    const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
-    const dim3 grid((unsigned)((cnt + 63) / 64));
-    if (top) {
-        const bool prof = prof_begin(c, VTS_PROF_GS_FINE);
-        hipLaunchKernelGGL((k_gs_color9<T, true>), grid, dim3(kBlk9), 0, c.s, Lk, col,
-                           (const T*)Lk.r, Lk.z);
-        if (prof) prof_end(c, gs_color_bytes(Lk, col, sizeof(T)));
-    } else {
-        hipLaunchKernelGGL((k_gs_color9<T, false>), grid, dim3(kBlk9), 0, c.s, Lk, col,
-                           (const T*)Lk.r, Lk.z);
+static void gs_sweep(Ctx& c, Level<T>& Lk, bool forward, bool top) {
+    const bool prof = top && prof_begin(c, VTS_PROF_GS_FINE);
+    double bytes = 0.0;
+    int launches = 0;
+    for (int q = 0; q < 8; ++q) {
+        const int col = forward ? q : 7 - q;
+        const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
+        if (cnt == 0) continue;
+        const dim3 grid((unsigned)((cnt + 63) / 64));
+        if (top)
+            hipLaunchKernelGGL((k_gs_color9<T, true>), grid, dim3(kBlk9), 0, c.s, Lk, col,
+                               (const T*)Lk.r, Lk.z);
+        else
+            hipLaunchKernelGGL((k_gs_color9<T, false>), grid, dim3(kBlk9), 0, c.s, Lk, col,
+                               (const T*)Lk.r, Lk.z);
+        bytes += gs_color_bytes(Lk, col, sizeof(T));
+        ++launches;
     }
+    if (prof) prof_end(c, bytes, launches);
 }
 
 template <typename T>
@@ -1005,11 +1014,7 @@ static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
     const int gr = red_grid_of(3 * Lk.nn);
     hipLaunchKernelGGL(k_zero_t<T>, dim3(grid_of(nv)), dim3(kThreads), 0, c.s, Lk.z, nv);
     // forward sweep: colours 0..7, then alpha
-    for (int col = 0; col < 8; ++col) {
-        const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
-        if (cnt == 0) continue;
-        gs_color_launch(c, Lk, col, top);
-    }
+    gs_sweep(c, Lk, true, top);
     hipLaunchKernelGGL(k_acol_dot<T>, dim3(gr), dim3(kThreads), 0, c.s, Lk, (const T*)Lk.z,
                        c.partials);
     hipLaunchKernelGGL(k_alpha_fin<T>, dim3(1), dim3(kThreads), 0, c.s, c.partials, gr, Lk.nn, d,
@@ -1036,11 +1041,7 @@ static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
                        c.partials);
     hipLaunchKernelGGL(k_alpha_fin<T>, dim3(1), dim3(kThreads), 0, c.s, c.partials, gr, Lk.nn, d,
                        (const T*)Lk.r, Lk.z, Lk.res, 0);
-    for (int col = 7; col >= 0; --col) {
-        const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
-        if (cnt == 0) continue;
-        gs_color_launch(c, Lk, col, top);
-    }
+    gs_sweep(c, Lk, false, top);
 }
 
 template <typename T>

@@ -143,13 +143,14 @@ struct Ctx {
     // every launch of one class on this context's stream
     int prof_class = 0;
     std::vector<hipEvent_t> prof_ev;
-    size_t prof_n = 0;
+    size_t prof_n = 0;        // event pairs recorded
+    int64_t prof_launches = 0;
     double prof_bytes = 0.0;
 };
 
 // profiling hooks (capi.cpp); prof_begin returns true if this launch is timed
 bool prof_begin(Ctx& c, int cls);
-void prof_end(Ctx& c, double bytes);
+void prof_end(Ctx& c, double bytes, int launches = 1);
 
 // algorithmic bytes of one colour pass: the colour's stencil rows and
 // inverse diagonal blocks, r, acol, z (read and write), neighbour z values
