@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", type=int, default=1,
                     help="0: cantilever 8x4x4, 1: cantilever 64x32x32 (default)")
+    ap.add_argument("--precision", choices=["config", "fp64", "mixed"], default="config",
+                    help="override the workload's precision (mixed: FP32 multigrid)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--kernels", action="store_true",
@@ -217,7 +219,8 @@ def main():
     opts = V.default_options()
     if eps_mr0:
         opts.eps_mr0 = eps_mr0
-    prec = V.VTS_MIXED if pr.extra.get("precision") == "mixed" else V.VTS_FP64
+    want = pr.extra.get("precision") if a.precision == "config" else a.precision
+    prec = V.VTS_MIXED if want == "mixed" else V.VTS_FP64
     ctx = V.Context.from_problem(pr, precision=prec, options=opts)
     torch.cuda.synchronize()
 

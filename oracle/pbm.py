@@ -37,16 +37,21 @@ class Options:
     MINRES rule are the values stated after Algorithm 1 and in Section 6.2.
     eps_pbm, eps_nwt_min and eps_nwt_final are tighter than the paper's
     (1e-5..1e-6, 1e-3, 10 eps_pbm) so that the result meets a KKT residual of
-    1e-6.  The floor of the energy-constraint penalties p is p_min = 1e-4
-    instead of the paper's 1e-8 (the floor q_min of q_lo, q_hi keeps the
-    paper's 1e-8): the multiplier method converges for any positive floor,
-    the Schur weights are bounded by rho'' ~ rho/p, so a higher p floor keeps
-    the Newton systems within reach of the Gauss-Seidel multigrid, while a
-    small q keeps weakly active bound multipliers converging quickly.
-    `paper_options()` returns the paper's values."""
+    1e-6.  The floor of the energy-constraint penalties p is relative to the
+    energy scale of the problem: p >= p_min |alpha| (alpha, the volume
+    multiplier, equals the common element energy of the optimum), instead of
+    the paper's absolute 1e-8 (the floor q_min of q_lo, q_hi keeps the
+    paper's absolute 1e-8).  The constraint functions e_i - alpha + nu_lo -
+    nu_hi scale with the square of the load, and an absolute floor makes
+    the method's behaviour depend on that scale; the multiplier method
+    converges for any positive floor, the Schur weights grow like rho/p, so a
+    moderate floor keeps the Newton systems within reach of the Gauss-Seidel
+    multigrid, while a small q keeps weakly active bound multipliers
+    converging quickly.  `paper_options()` returns the paper's values."""
     beta: float = 0.3
     gamma: float = 0.3
-    p_min: float = 1e-4                       # floor of p; paper: 1e-8 (see paper_options)
+    p_min: float = 1e-3                       # floor of p / |alpha|; paper: 1e-8 absolute
+    p_min_relative: bool = True               # False: p_min is an absolute floor
     q_min: float = 1e-8                       # floor of q_lo, q_hi (the paper's value)
     eps_pbm: float = 1e-8
     eps_nwt0: float = 1.0
@@ -64,11 +69,18 @@ class Options:
     final_res4: bool = True                   # final Newton also tests res_4
 
 
+def p_floor(o: "Options", alpha: float) -> float:
+    """Floor of the penalty parameters p after an outer iteration."""
+    if o.p_min_relative and alpha != 0.0:
+        return o.p_min * abs(alpha)
+    return o.p_min
+
+
 def paper_options(eps_pbm: float = 1e-5) -> "Options":
     """The parameter values of the paper's experiments (Section 7)."""
     return Options(eps_pbm=eps_pbm, eps_nwt_min=1e-3, eps_nwt_final=None,
                    final_res4=False, eps_stat=None, accept_stall=0.0, p_min=1e-8,
-                   q_min=1e-8)
+                   p_min_relative=False, q_min=1e-8)
 
 
 @dataclass
@@ -455,7 +467,7 @@ class Solver:
             if self.status != "ok" or (ratio < o.eps_pbm and stat < (o.eps_stat or 1.0)):
                 break
             st.rho, st.mu_lo, st.mu_hi = rho_n, mul_n, muh_n
-            st.p = np.maximum(o.gamma * st.p, o.p_min)
+            st.p = np.maximum(o.gamma * st.p, p_floor(o, st.alpha))
             st.q_lo = np.maximum(o.gamma * st.q_lo, o.q_min)
             st.q_hi = np.maximum(o.gamma * st.q_hi, o.q_min)
             eps_nwt = max(min(100.0 * ratio, eps_nwt), o.eps_nwt_min)

@@ -680,7 +680,7 @@ void vts_default_options(vts_options* o) {
     if (!o) return;
     o->beta = 0.3;
     o->gamma = 0.3;
-    o->p_min = 1e-4;
+    o->p_min = 1e-3;
     o->q_min = 1e-8;
     o->eps_pbm = 1e-8;
     o->eps_nwt0 = 1.0;
@@ -696,6 +696,7 @@ void vts_default_options(vts_options* o) {
     o->max_newton = 100;
     o->max_minres = 500;
     o->final_res4 = 1;
+    o->p_min_relative = 1;
 }
 
 vts_status vts_create(const vts_problem* pr, const vts_options* opt, void* stream, vts_ctx** out) {

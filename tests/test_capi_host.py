@@ -36,6 +36,8 @@ def test_default_options_match_oracle_defaults():
               "eps_stat", "accept_stall", "eps_mr_min", "armijo_c1", "armijo_min",
               "max_outer", "max_newton", "max_minres"):
         assert getattr(o, k) == pytest.approx(getattr(p, k), rel=0, abs=0), k
+    assert bool(o.final_res4) == p.final_res4
+    assert bool(o.p_min_relative) == p.p_min_relative
 
 
 def test_footprint_grows_with_problem():

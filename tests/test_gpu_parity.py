@@ -38,6 +38,7 @@ OP_CASES = {
     "cant-8x4x4-l3": lambda: W.cantilever_edge(8, 4, 4, 3),
     "cant-10x6x4-l2": lambda: W.cantilever_edge(10, 6, 4, 2),
     "bridge-16x8x8-l3": lambda: W.bridge_top(16, 8, 8, 3),
+    "bridge-32x16x16-l4-h": lambda: W.bridge_top(32, 16, 16, 4, h=0.125),
     "cant-64x32x32-l5": lambda: W.config(1),
 }
 
@@ -48,7 +49,7 @@ def test_apply_K_parity(case):
     say("apply_K", case)
     ctx = V.Context.from_problem(pr, precision=V.VTS_FP64)
     g = fe.Grid(pr.nx, pr.ny, pr.nz, pr.fixed)
-    Ke = fe.element_stiffness()
+    Ke = fe.element_stiffness(pr.E, pr.nu, pr.h)
     rho = W.random_rho(pr.m, seed=1)
     x = W.random_vector(pr.n_dof, seed=2)          # fixed entries non-zero: masked on read
     ctx.set_rho(dev(rho))
@@ -130,7 +131,7 @@ def _sv(P, y_free_alpha):
 
 SYS_CASES = {
     "cant-8x4x4-l3": lambda: W.cantilever_edge(8, 4, 4, 3),
-    "bridge-16x8x8-l3": lambda: W.bridge_top(16, 8, 8, 3),
+    "bridge-16x8x8-l3-h": lambda: W.bridge_top(16, 8, 8, 3, h=0.25),
     "cant-12x8x4-l2": lambda: W.cantilever_edge(12, 8, 4, 2),
 }
 
@@ -243,6 +244,26 @@ def test_pbm_solve_config0_matches_oracle(precision):
     assert r["kkt"] <= 1e-6, r
     s = pbm.Solver(pr)
     so = s.solve()
+    c_gpu = kkt.compliance(P.grid, P.Ke, d["rho"], P.f)
+    c_or = kkt.compliance(P.grid, P.Ke, so.rho, P.f)
+    assert abs(c_gpu - c_or) <= 1e-6 * c_or
+    assert abs(res["compliance"] - 0.5 * P.f @ so.u) <= 1e-6 * c_or
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [V.VTS_FP64, V.VTS_MIXED])
+def test_pbm_solve_bridge_matches_oracle(precision):
+    """Bridge on the unit-cube coarse box (element side 1/4), the shape of
+    the 128x64x64 bridge workload at 3 levels."""
+    pr = W.bridge_top(16, 8, 8, 3, vol_frac=0.15, h=0.25)
+    say("PBM solve", pr.name, "h", pr.h, "precision", precision)
+    ctx = V.Context.from_problem(pr, precision=precision)
+    res = ctx.pbm_solve()
+    d = ctx.state_dict()
+    P = pbm.VTS(pr)
+    r = kkt.kkt_residual(P.grid, P.Ke, P.f, P.V, P.rho_lo, P.rho_hi, d["rho"], d["u"], d["alpha"])
+    assert r["kkt"] <= 1e-6, r
+    so = pbm.Solver(pr).solve()
     c_gpu = kkt.compliance(P.grid, P.Ke, d["rho"], P.f)
     c_or = kkt.compliance(P.grid, P.Ke, so.rho, P.f)
     assert abs(c_gpu - c_or) <= 1e-6 * c_or

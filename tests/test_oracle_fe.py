@@ -224,5 +224,11 @@ def test_load_vectors():
     assert pr.f.sum() == -5.0 and np.count_nonzero(pr.f) == 5
     br = W.bridge_top(8, 4, 4, 3)
     assert abs(br.f.sum() + 8 * 4) < 1e-12          # unit pressure x top area
+    # domain of unit coarse cubes: the total load is the coarse top area at
+    # every refinement
+    for L in (2, 3, 4):
+        s = 2 ** (L - 1)
+        bh = W.bridge_top(4 * s, 2 * s, 2 * s, L, h=2.0 ** (1 - L))
+        assert abs(bh.f.sum() + 8.0) < 1e-12 and bh.h == 2.0 ** (1 - L)
     pt = W.cantilever_points(16, 8, 8, 3, seed=0)
     assert np.count_nonzero(pt.f) == 3 and pt.f.sum() == -3.0

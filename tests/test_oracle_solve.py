@@ -68,8 +68,10 @@ def test_config0_kkt_and_duality_certificate(c1):
     # rho itself is feasible only to the KKT tolerance: its compliance sits
     # within that tolerance of the bracket
     assert lb * (1 - 1e-6) <= c <= ub * (1 + 1e-6)
-    # Section 7.1: the PBM volume is met from above within one permille
-    assert 0 <= st.rho.sum() - P.V <= 1e-3 * P.V
+    # Section 7.1 reports the volume met from above within one permille at
+    # the paper's looser tolerances; at KKT 1e-6 it is met to rounding level
+    # from either side
+    assert -1e-9 * P.V <= st.rho.sum() - P.V <= 1e-3 * P.V
 
 
 def test_config0_mirror_symmetry(c1):

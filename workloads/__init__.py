@@ -36,7 +36,7 @@ __all__ = [
 
 @dataclass
 class Problem:
-    """A VTS instance on an nx x ny x nz grid of unit hexahedra."""
+    """A VTS instance on an nx x ny x nz grid of cubic hexahedra of side h."""
     name: str
     nx: int
     ny: int
@@ -151,10 +151,13 @@ def cantilever_points(nx, ny, nz, levels, npoints=3, seed=0, V=None,
 
 
 def bridge_top(nx, ny, nz, levels, V=None, vol_frac=0.15, rho_lo=1e-3,
-               rho_hi=1.0, name=None) -> Problem:
+               rho_hi=1.0, name=None, h=1.0) -> Problem:
     """Bridge: the four bottom corners fixed; unit downward pressure on the
     whole top face z = nz, lumped to nodes as the consistent bilinear face
-    load (each unit face gives -1/4 to each of its 4 nodes)."""
+    load (each face of side h gives -h^2/4 to each of its 4 nodes).  With
+    h = 2^(1 - levels) the domain is the coarse box of unit cubes refined
+    levels - 1 times (the paper's BRIDGE-mx-my-mz-l domain), and the total
+    load is the coarse top-face area at every refinement."""
     fixed = _bottom_corners(nx, ny, nz)
     f = np.zeros(fixed.size)
     i, j, k = _node_grid(nx, ny, nz)
@@ -162,12 +165,12 @@ def bridge_top(nx, ny, nz, levels, V=None, vol_frac=0.15, rho_lo=1e-3,
     wx = np.where((i == 0) | (i == nx), 0.5, 1.0)
     wy = np.where((j == 0) | (j == ny), 0.5, 1.0)
     nodes = np.nonzero(top)[0]
-    f[3 * nodes + 2] = -(wx * wy)[nodes]
+    f[3 * nodes + 2] = -(h * h) * (wx * wy)[nodes]
     f[fixed == 1] = 0.0
     m = nx * ny * nz
     V = vol_frac * m if V is None else V
     return Problem(name or f"bridge-{nx}x{ny}x{nz}-l{levels}", nx, ny, nz,
-                   levels, fixed, f, float(V), rho_lo, rho_hi)
+                   levels, fixed, f, float(V), rho_lo, rho_hi, h=float(h))
 
 
 def bar_rollers(nx, ny, nz, levels, vol_frac=0.5, traction=1.0,
@@ -230,7 +233,8 @@ def config(idx: int) -> Problem:
         pr = cantilever_edge(64, 32, 32, 5, vol_frac=0.2, name="cant-64x32x32")
         pr.extra.update(precision="fp64", eps_mr0=1e-2)
     elif idx == 2:
-        pr = bridge_top(128, 64, 64, 6, vol_frac=0.15, name="bridge-128x64x64")
+        pr = bridge_top(128, 64, 64, 6, vol_frac=0.15, name="bridge-128x64x64",
+                        h=2.0 ** -5)
         pr.extra.update(precision="mixed", eps_mr0=None)
     elif idx == 3:
         pr = cantilever_points(192, 96, 96, 6, npoints=3, seed=0,
@@ -275,6 +279,6 @@ def serving_requests(n_req: int = 256, rate: float = 1.0, seed: int = 0):
         if int(rk.integers(0, 2)) == 0:
             pr = cantilever_edge(nx, ny, nz, l, vol_frac=frac)
         else:
-            pr = bridge_top(nx, ny, nz, l, vol_frac=frac)
+            pr = bridge_top(nx, ny, nz, l, vol_frac=frac, h=2.0 ** (1 - l))
         out.append((float(t[r]), pr))
     return out
