@@ -48,6 +48,12 @@ def parse():
                          "R S-applies at the initial Newton point and R plain copies of "
                          "256 MiB (the counter scale reference); prints one JSON line")
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--serve", action="store_true",
+                    help="serving stream: Poisson arrivals of mixed VTS requests against the "
+                         "request loop; prints one JSON line with p50/p99 latency per rate")
+    ap.add_argument("--requests", type=int, default=20, help="requests per rate (--serve)")
+    ap.add_argument("--slots", type=int, default=4, help="concurrent requests (--serve)")
+    ap.add_argument("--pool-gb", type=float, default=16.0, help="device pool (--serve)")
     return ap.parse_args()
 
 
@@ -202,6 +208,57 @@ def kernels_only(a, torch, W, V):
     return 0
 
 
+def serving(a, torch, W, V):
+    """Latency of a Poisson stream of mixed requests (grids 16x8x8 .. 96x48x48,
+    cantilever edge / bridge face loads, V/m ~ U[0.1, 0.4]) at three arrival
+    rates, relative to the mean service time of the mix run alone."""
+    from paper_1904_06556_amd import serve
+    # serving policy: a penalty floor and outer budget that also carry the
+    # larger bridges to KKT 1e-6
+    opts = V.default_options(p_min=2e-3, max_outer=300)
+    base = W.serving_requests(a.requests, rate=1.0, seed=0)
+    probs = [p for _, p in base]
+    n_alone = min(8, len(probs))
+    alone = serve.time_alone(probs[:n_alone], precision=V.VTS_MIXED, options=opts)
+    for r, p in zip(alone, probs):
+        print(f"alone {p.name} status {r['status']} service {r['service']:.2f} s",
+              file=sys.stderr, flush=True)
+    t_alone = float(np.mean([r["service"] for r in alone]))
+    pool = int(a.pool_gb * (1 << 30))
+    rates = {}
+    same = True
+    for factor in (0.5, 0.8, 1.2):
+        lam = factor / t_alone
+        reqs = W.serving_requests(a.requests, rate=lam, seed=0)
+        srv = V.Server(a.slots, pool)
+        recs = serve.run_stream(srv, reqs, precision=V.VTS_MIXED, options=opts,
+                                on_done=lambda r: print(
+                                    f"  rate x{factor}: request {r['index']} status {r['status']} "
+                                    f"latency {r['latency']:.2f} s", file=sys.stderr, flush=True))
+        srv.close()
+        for k in range(n_alone):
+            same &= (recs[k]["compliance"] == alone[k]["compliance"] and
+                     recs[k]["minres"] == alone[k]["minres"])
+        rates[f"x{factor}"] = dict(rate_per_s=lam, **serve.summarize(recs))
+    mid = rates["x0.8"]
+    line = {
+        "metric": METRIC, "value": mid["throughput_per_s"],
+        "unit": "VTS solves/s (served stream at 0.8 x capacity of one-at-a-time service)",
+        "n_gpus": 1, "steps": a.requests, "warmup": 0,
+        "ms_per_step": 1e3 / mid["throughput_per_s"] if mid["throughput_per_s"] else None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32mg", "data": "synthetic",
+        "config": {"workload": "serving stream", "grids": [list(g) for g in W.SERVING_GRIDS],
+                   "requests_per_rate": a.requests, "slots": a.slots, "pool_gb": a.pool_gb,
+                   "precision": "mixed", "p_min": opts.p_min, "max_outer": opts.max_outer},
+        "p50_s": mid["p50_s"], "p99_s": mid["p99_s"],
+        "mean_service_alone_s": t_alone, "rates": rates,
+        "mix_equals_alone": bool(same),
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -214,6 +271,8 @@ def main():
 
     if a.kernels:
         return kernels_only(a, torch, W, V)
+    if a.serve:
+        return serving(a, torch, W, V)
     pr = W.config(a.workload)
     eps_mr0 = pr.extra.get("eps_mr0")
     opts = V.default_options()

@@ -167,8 +167,13 @@ void vts_destroy(vts_ctx* ctx);
  * tolerances; the problem data stay resident. */
 vts_status vts_reset(vts_ctx* ctx);
 
-/* Device bytes vts_create would allocate for this problem (for admission). */
+/* Device bytes vts_create would allocate for this problem (for admission):
+ * an upper bound of vts_allocated_bytes, counted in 256-byte granules.
+ * Returns 0 for an invalid problem. */
 size_t vts_footprint_bytes(const vts_problem* pr, const vts_options* opt);
+
+/* Device bytes this context holds (256-byte granules). */
+size_t vts_allocated_bytes(const vts_ctx* ctx);
 
 /* Sizes of this context: n_dof, m, number of free DOFs n, levels. */
 vts_status vts_sizes(const vts_ctx* ctx, int64_t* n_dof, int64_t* m, int64_t* n_free,
@@ -269,6 +274,60 @@ vts_status vts_set_state(vts_ctx* ctx, const void* host_buf, size_t bytes);
 
 /* Message of the last failure on this context (static storage of ctx). */
 const char* vts_last_error(const vts_ctx* ctx);
+
+/* ---------------------------------------------------------------------
+ * Serving: a request loop for streams of independent VTS problems (the
+ * problem (1.1) of each request solved by Algorithm 1 to the options'
+ * tolerances).  The server owns one device pool of hbm_bytes, allocated
+ * once, and `slots` worker threads, each with its own non-blocking HIP
+ * stream.  A pending request is admitted, in arrival order with first-fit
+ * bypass, as soon as a slot is idle and a contiguous range of the pool
+ * holds its vts_footprint_bytes; its context is built inside that range (no
+ * hipMalloc or hipFree while serving), solved, and its range returned.
+ * Admitted problems run concurrently on the device, each on its own stream;
+ * every problem's arithmetic is the same as in a context of its own (fixed
+ * reduction orders, no atomics), so results do not depend on the mix.
+ * --------------------------------------------------------------------- */
+typedef struct vts_server vts_server;
+
+typedef struct {
+    int64_t id;
+    int32_t status;               /* vts_status of the solve */
+    int32_t outer, newton, minres;
+    double compliance, alpha, sum_rho;
+    double t_submit, t_admit, t_done;   /* seconds on the server's clock */
+    size_t footprint;             /* bytes of the pool the request held */
+    int64_t n_dof, m;
+} vts_request_info;
+
+/* slots >= 1 workers; hbm_bytes of device memory on the current device.
+ * VTS_ENOMEM if the pool cannot be allocated. */
+vts_status vts_server_create(int32_t slots, size_t hbm_bytes, vts_server** out);
+
+/* Copies the problem (host arrays) and options (NULL: defaults) into the
+ * queue and returns its id.  VTS_EINVAL for an invalid problem, VTS_ENOMEM
+ * if its footprint exceeds the whole pool.  Thread-safe. */
+vts_status vts_server_submit(vts_server* srv, const vts_problem* pr, const vts_options* opt,
+                             int64_t* id);
+
+/* Moves up to max finished requests into out[] (oldest first), waiting up to
+ * timeout_s seconds for the first one; returns how many were written. */
+int32_t vts_server_poll(vts_server* srv, vts_request_info* out, int32_t max, double timeout_s);
+
+/* Copies the final rho (m doubles) and u (n_dof doubles) of a finished
+ * request to host memory (either pointer may be NULL) and forgets it.
+ * VTS_EINVAL for an unknown id. */
+vts_status vts_server_fetch(vts_server* srv, int64_t id, double* rho_host, double* u_host);
+
+/* Seconds since the server was created (the clock of vts_request_info). */
+double vts_server_clock(const vts_server* srv);
+
+/* Numbers of requests waiting, running and finished-but-not-polled. */
+void vts_server_counts(const vts_server* srv, int32_t* pending, int32_t* running,
+                       int32_t* finished);
+
+/* Finishes the running requests, drops the pending ones, frees the pool. */
+void vts_server_destroy(vts_server* srv);
 
 #ifdef __cplusplus
 }

@@ -16,8 +16,6 @@
 
 using namespace vts;
 
-struct vts_ctx : public Ctx {};
-
 namespace {
 
 #define HIPCHK(expr)                                                                   \
@@ -139,7 +137,11 @@ Plan make_plan(const vts_problem* pr) {
     for (int q = 0; q < 5; ++q) add(m * 8);                          // dnl dnh c1 c2 wt
     for (int q = 0; q < 8; ++q) add((ndof + 1) * 8);                 // MINRES
     add(kRedSlots * kRedBlocks * 8); add(kRedSlots * 8);             // partials, red
-    add(8 * 4096);                                                   // tiled S partials
+    {
+        Ctx t;                                                       // tiled S partials
+        t.nx = d.nx; t.ny = d.ny; t.nz = d.nz;
+        add(8 * (size_t)apply_S_tile_blocks(t));
+    }
     const size_t ts = pr->precision == VTS_MIXED ? 4 : 8;
     Dims dl = d;
     for (int k = pr->levels - 1; k >= 0; --k) {
@@ -151,20 +153,40 @@ Plan make_plan(const vts_problem* pr) {
             if (k > 0) add(576 * lm * ts);                           // TQ (levels with a parent)
         }
         for (int q = 0; q < 3; ++q) add((3 * lnn + 1) * ts);         // r z res
+        if (k == 0) {
+            // dense coarsest system and its inverse, DOF maps, flag (bounded
+            // by an all-free coarsest level)
+            const size_t nc = (size_t)(3 * lnn + 1);
+            add(nc * nc * 8); add(nc * nc * 8);
+            add(3 * lnn * 4); add(nc * 4); add(4);
+        }
         dl = Dims{dl.nx / 2, dl.ny / 2, dl.nz / 2};
     }
     return p;
 }
 
+// device buffer of `count` elements: from the context's arena if it has one
+// (256-byte granules, no hipMalloc), else hipMalloc
 template <typename T>
 vts_status alloc_t(Ctx& c, T** ptr, int64_t count) {
+    const size_t b = ((size_t)std::max<int64_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
     void* q = nullptr;
-    const size_t b = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
-    if (hipMalloc(&q, b) != hipSuccess) {
-        c.err = "hipMalloc failed (" + std::to_string(b) + " bytes)";
-        return VTS_ENOMEM;
+    if (c.arena) {
+        if (c.arena_used + b > c.arena_size) {
+            c.err = "device arena exhausted (" + std::to_string(c.arena_used + b) + " > " +
+                    std::to_string(c.arena_size) + " bytes)";
+            return VTS_ENOMEM;
+        }
+        q = c.arena + c.arena_used;
+        c.arena_used += b;
+    } else {
+        if (hipMalloc(&q, b) != hipSuccess) {
+            c.err = "hipMalloc failed (" + std::to_string(b) + " bytes)";
+            return VTS_ENOMEM;
+        }
+        c.allocs.push_back(q);
     }
-    c.allocs.push_back(q);
+    c.alloc_bytes += b;
     *ptr = (T*)q;
     return VTS_OK;
 }
@@ -196,7 +218,7 @@ vts_status build_hierarchy(Ctx& c, Hierarchy<T>& H, const std::vector<uint8_t>& 
         std::memset(&Lk, 0, sizeof(Lk));
         fill_level_geom(Lk, dims[k]);
         ALLOC(Lk.fixed, 3 * Lk.nn);
-        HIPCHK(hipMemcpy(Lk.fixed, masks[k].data(), 3 * Lk.nn, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpyAsync(Lk.fixed, masks[k].data(), 3 * Lk.nn, hipMemcpyHostToDevice, c.s));
         ALLOC(Lk.st, (int64_t)kStencilVals * Lk.nn);
         ALLOC(Lk.dinv, 9 * Lk.nn);
         ALLOC(Lk.acol, 3 * Lk.nn);
@@ -225,12 +247,14 @@ vts_status build_hierarchy(Ctx& c, Hierarchy<T>& H, const std::vector<uint8_t>& 
     H.nc = nc;
     ALLOC(H.A, (int64_t)nc * nc);
     ALLOC(H.cmap, (int64_t)cmap.size());
-    HIPCHK(hipMemcpy(H.cmap, cmap.data(), cmap.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(H.cmap, cmap.data(), cmap.size() * sizeof(int), hipMemcpyHostToDevice,
+                          c.s));
     std::vector<int> cinv(nc - 1);
     for (size_t q = 0; q < cmap.size(); ++q)
         if (cmap[q] >= 0) cinv[cmap[q]] = (int)q;
     ALLOC(H.cinv, nc - 1);
-    HIPCHK(hipMemcpy(H.cinv, cinv.data(), (nc - 1) * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(H.cinv, cinv.data(), (nc - 1) * sizeof(int), hipMemcpyHostToDevice,
+                          c.s));
     ALLOC(H.flag, 1);
     // levels small enough for the one-workgroup V-cycle (needs the inverse)
     H.ksmall = -1;
@@ -241,6 +265,8 @@ vts_status build_hierarchy(Ctx& c, Hierarchy<T>& H, const std::vector<uint8_t>& 
         }
     }
     if (H.ksmall >= 0) ALLOC(H.Ainv, (int64_t)nc * nc);
+    // the host masks and maps above go out of scope: finish their copies
+    HIPCHK(hipStreamSynchronize(c.s));
     return VTS_OK;
 }
 
@@ -515,6 +541,67 @@ vts_status pbm_iterate(Ctx& c, vts_pbmstats* out) {
     return VTS_OK;
 }
 
+// host-side checks of the data (assumptions after problem (1.1)) and the
+// cleaned host arrays: the DOF mask as 0/1, loads zeroed at fixed DOFs, the
+// bounds expanded to m entries; nested supports and the coarsest size
+struct HostData {
+    std::vector<uint8_t> mask;
+    std::vector<double> f, lo, hi;
+    int64_t nfree = 0;
+    double norm_f = 0.0, norm_bounds = 0.0;
+};
+
+vts_status prepare_host(const vts_problem* pr, HostData& hd, std::string& err) {
+    const Dims d0{pr->nx, pr->ny, pr->nz};
+    const int64_t ndof = 3 * nodes_of(d0), m = (int64_t)pr->nx * pr->ny * pr->nz;
+    hd.mask.assign(pr->fixed_host, pr->fixed_host + ndof);
+    hd.f.assign(pr->f_host, pr->f_host + ndof);
+    int64_t nfixed = 0;
+    double nf2 = 0.0;
+    for (int64_t q = 0; q < ndof; ++q) {
+        hd.mask[q] = hd.mask[q] ? 1 : 0;
+        nfixed += hd.mask[q];
+        if (hd.mask[q]) hd.f[q] = 0.0;
+        if (!std::isfinite(hd.f[q])) { err = "load vector is not finite"; return VTS_EINVAL; }
+        nf2 += hd.f[q] * hd.f[q];
+    }
+    if (nfixed == 0) { err = "no fixed DOF: K(rho) is singular"; return VTS_EINVAL; }
+    if (nf2 == 0.0) { err = "zero load"; return VTS_EINVAL; }
+    hd.nfree = ndof - nfixed;
+    hd.norm_f = std::sqrt(nf2);
+    hd.lo.resize(m);
+    hd.hi.resize(m);
+    double slo = 0, shi = 0, nlo2 = 0, nhi2 = 0;
+    for (int64_t e = 0; e < m; ++e) {
+        const double lo = pr->rho_lo_host ? pr->rho_lo_host[e] : pr->rho_lo_s;
+        const double hi = pr->rho_hi_host ? pr->rho_hi_host[e] : pr->rho_hi_s;
+        if (!(hi > lo) || lo < 0) { err = "need 0 <= rho_lo < rho_hi"; return VTS_EINVAL; }
+        hd.lo[e] = lo;
+        hd.hi[e] = hi;
+        slo += lo; shi += hi; nlo2 += lo * lo; nhi2 += hi * hi;
+    }
+    if (!(slo < pr->V && pr->V < shi)) { err = "volume not strictly feasible"; return VTS_EINVAL; }
+    hd.norm_bounds = std::sqrt(nlo2) + std::sqrt(nhi2);
+    std::vector<uint8_t> mk = hd.mask;
+    Dims dk = d0;
+    for (int k = pr->levels - 1; k > 0; --k) {
+        std::vector<uint8_t> mc = coarsen_mask(mk, dk);
+        if (!nested(mk, dk, mc)) {
+            err = "fixed DOFs are not nested across multigrid levels";
+            return VTS_EINVAL;
+        }
+        mk.swap(mc);
+        dk = Dims{dk.nx / 2, dk.ny / 2, dk.nz / 2};
+    }
+    int64_t nc = 1;
+    for (uint8_t v : mk) nc += v ? 0 : 1;
+    if (nc > kMaxCoarse) {
+        err = "coarsest level too large for the dense solver (" + std::to_string(nc) + ")";
+        return VTS_EINVAL;
+    }
+    return VTS_OK;
+}
+
 vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, void* stream) {
     c.nx = pr->nx; c.ny = pr->ny; c.nz = pr->nz; c.L = pr->levels;
     c.nn = nodes_of(Dims{c.nx, c.ny, c.nz});
@@ -525,52 +612,18 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
     if (opt) c.opt = *opt; else vts_default_options(&c.opt);
     c.s = (hipStream_t)stream;
 
-    // host-side checks of the data (assumptions after problem (1.1))
-    std::vector<uint8_t> mask(pr->fixed_host, pr->fixed_host + c.ndof);
-    std::vector<double> f(pr->f_host, pr->f_host + c.ndof);
-    int64_t nfixed = 0;
-    double nf2 = 0.0;
-    for (int64_t q = 0; q < c.ndof; ++q) {
-        mask[q] = mask[q] ? 1 : 0;
-        nfixed += mask[q];
-        if (mask[q]) f[q] = 0.0;
-        if (!std::isfinite(f[q])) { c.err = "load vector is not finite"; return VTS_EINVAL; }
-        nf2 += f[q] * f[q];
-    }
-    if (nfixed == 0) { c.err = "no fixed DOF: K(rho) is singular"; return VTS_EINVAL; }
-    if (nf2 == 0.0) { c.err = "zero load"; return VTS_EINVAL; }
-    c.nfree = c.ndof - nfixed;
-    c.norm_f = std::sqrt(nf2);
-    std::vector<double> lo(c.m), hi(c.m);
-    double slo = 0, shi = 0, nlo2 = 0, nhi2 = 0;
-    for (int64_t e = 0; e < c.m; ++e) {
-        lo[e] = pr->rho_lo_host ? pr->rho_lo_host[e] : pr->rho_lo_s;
-        hi[e] = pr->rho_hi_host ? pr->rho_hi_host[e] : pr->rho_hi_s;
-        if (!(hi[e] > lo[e]) || lo[e] < 0) { c.err = "need 0 <= rho_lo < rho_hi"; return VTS_EINVAL; }
-        slo += lo[e]; shi += hi[e]; nlo2 += lo[e] * lo[e]; nhi2 += hi[e] * hi[e];
-    }
-    if (!(slo < c.V && c.V < shi)) { c.err = "volume not strictly feasible"; return VTS_EINVAL; }
-    c.norm_bounds = std::sqrt(nlo2) + std::sqrt(nhi2);
+    HostData hd;
     {
-        // nested fixed DOFs and the size of the dense coarsest system
-        std::vector<uint8_t> mk = mask;
-        Dims dk{c.nx, c.ny, c.nz};
-        for (int k = c.L - 1; k > 0; --k) {
-            std::vector<uint8_t> mc = coarsen_mask(mk, dk);
-            if (!nested(mk, dk, mc)) {
-                c.err = "fixed DOFs are not nested across multigrid levels";
-                return VTS_EINVAL;
-            }
-            mk.swap(mc);
-            dk = Dims{dk.nx / 2, dk.ny / 2, dk.nz / 2};
-        }
-        int64_t nc = 1;
-        for (uint8_t v : mk) nc += v ? 0 : 1;
-        if (nc > kMaxCoarse) {
-            c.err = "coarsest level too large for the dense solver (" + std::to_string(nc) + ")";
-            return VTS_EINVAL;
-        }
+        vts_status st0 = prepare_host(pr, hd, c.err);
+        if (st0 != VTS_OK) return st0;
     }
+    std::vector<uint8_t>& mask = hd.mask;
+    std::vector<double>& f = hd.f;
+    std::vector<double>& lo = hd.lo;
+    std::vector<double>& hi = hd.hi;
+    c.nfree = hd.nfree;
+    c.norm_f = hd.norm_f;
+    c.norm_bounds = hd.norm_bounds;
     HIPCHK(hipGetDevice(&c.device));
 
     // constants
@@ -582,16 +635,16 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
     for (int q = 0; q < 576; ++q) Kef[q] = (float)Ke[q];
     c.kh_ok = walsh_form(Ke, c.kh8) && c.ndof < (int64_t(1) << 31);
     ALLOC(c.Ke, 576); ALLOC(c.Kef, 576); ALLOC(c.Mc, 8 * 576); ALLOC(c.Qc, 512);
-    HIPCHK(hipMemcpy(c.Ke, Ke, sizeof(Ke), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c.Kef, Kef, sizeof(Kef), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c.Mc, Mc, sizeof(Mc), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c.Qc, Q, sizeof(Q), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(c.Ke, Ke, sizeof(Ke), hipMemcpyHostToDevice, c.s));
+    HIPCHK(hipMemcpyAsync(c.Kef, Kef, sizeof(Kef), hipMemcpyHostToDevice, c.s));
+    HIPCHK(hipMemcpyAsync(c.Mc, Mc, sizeof(Mc), hipMemcpyHostToDevice, c.s));
+    HIPCHK(hipMemcpyAsync(c.Qc, Q, sizeof(Q), hipMemcpyHostToDevice, c.s));
 
     ALLOC(c.fixed, c.ndof); ALLOC(c.f, c.ndof); ALLOC(c.rlo, c.m); ALLOC(c.rhi, c.m);
-    HIPCHK(hipMemcpy(c.fixed, mask.data(), c.ndof, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c.f, f.data(), c.ndof * 8, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c.rlo, lo.data(), c.m * 8, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c.rhi, hi.data(), c.m * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(c.fixed, mask.data(), c.ndof, hipMemcpyHostToDevice, c.s));
+    HIPCHK(hipMemcpyAsync(c.f, f.data(), c.ndof * 8, hipMemcpyHostToDevice, c.s));
+    HIPCHK(hipMemcpyAsync(c.rlo, lo.data(), c.m * 8, hipMemcpyHostToDevice, c.s));
+    HIPCHK(hipMemcpyAsync(c.rhi, hi.data(), c.m * 8, hipMemcpyHostToDevice, c.s));
     ALLOC(c.u, c.ndof);
     ALLOC(c.nlo, c.m); ALLOC(c.nhi, c.m); ALLOC(c.rho, c.m); ALLOC(c.mlo, c.m);
     ALLOC(c.mhi, c.m); ALLOC(c.p, c.m); ALLOC(c.qlo, c.m); ALLOC(c.qhi, c.m);
@@ -665,6 +718,34 @@ bool prof_begin(Ctx& c, int cls) {
     return true;
 }
 
+vts_status check_problem(const vts_problem* pr, std::string& err) {
+    vts_status st = validate(pr, err);
+    if (st != VTS_OK) return st;
+    HostData hd;
+    return prepare_host(pr, hd, err);
+}
+
+vts_status create_in(const vts_problem* pr, const vts_options* opt, void* stream, void* arena,
+                     size_t arena_bytes, vts_ctx** out, std::string& err) {
+    if (!out) return VTS_EINVAL;
+    *out = nullptr;
+    vts_status st = validate(pr, err);
+    if (st != VTS_OK) return st;
+    vts_ctx* c = new (std::nothrow) vts_ctx();
+    if (!c) return VTS_ENOMEM;
+    c->arena = (char*)arena;
+    c->arena_size = arena ? arena_bytes : 0;
+    st = ctx_create(*c, pr, opt, stream);
+    if (st != VTS_OK) {
+        err = c->err;
+        ctx_free(*c);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return VTS_OK;
+}
+
 void prof_end(Ctx& c, double bytes, int launches) {
     hipEventRecord(c.prof_ev[2 * c.prof_n + 1], c.s);
     c.prof_n += 1;
@@ -700,26 +781,13 @@ void vts_default_options(vts_options* o) {
 }
 
 vts_status vts_create(const vts_problem* pr, const vts_options* opt, void* stream, vts_ctx** out) {
-    if (!out) return VTS_EINVAL;
-    *out = nullptr;
     std::string err;
-    vts_status st = validate(pr, err);
-    if (st != VTS_OK) {
-        g_create_err = err;
-        return st;
-    }
-    vts_ctx* c = new (std::nothrow) vts_ctx();
-    if (!c) return VTS_ENOMEM;
-    st = ctx_create(*c, pr, opt, stream);
-    if (st != VTS_OK) {
-        g_create_err = c->err;
-        ctx_free(*c);
-        delete c;
-        return st;
-    }
-    *out = c;
-    return VTS_OK;
+    vts_status st = create_in(pr, opt, stream, nullptr, 0, out, err);
+    if (st != VTS_OK) g_create_err = err;
+    return st;
 }
+
+size_t vts_allocated_bytes(const vts_ctx* c) { return c ? c->alloc_bytes : 0; }
 
 vts_status vts_reset(vts_ctx* cp) {
     if (!cp) return VTS_EINVAL;

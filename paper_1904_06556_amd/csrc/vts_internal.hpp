@@ -137,7 +137,10 @@ struct Ctx {
     bool converged = false;
     std::string err;
 
-    std::vector<void*> allocs;
+    std::vector<void*> allocs;   // hipMalloc'd buffers (contexts without an arena)
+    char* arena = nullptr;       // caller-owned device range (server slots), or null
+    size_t arena_size = 0, arena_used = 0;
+    size_t alloc_bytes = 0;      // device bytes taken, 256-byte granules
 
     // kernel-class profiling (vts_profile_start/stop): HIP events around
     // every launch of one class on this context's stream
@@ -147,6 +150,14 @@ struct Ctx {
     int64_t prof_launches = 0;
     double prof_bytes = 0.0;
 };
+
+// every check vts_create makes before touching the device (no HIP call)
+vts_status check_problem(const vts_problem* pr, std::string& err);
+
+// vts_create with an optional caller-owned device arena of arena_bytes (the
+// context then calls no hipMalloc; vts_destroy leaves the arena alone)
+vts_status create_in(const vts_problem* pr, const vts_options* opt, void* stream, void* arena,
+                     size_t arena_bytes, vts_ctx** out, std::string& err);
 
 // profiling hooks (capi.cpp); prof_begin returns true if this launch is timed
 bool prof_begin(Ctx& c, int cls);
@@ -210,3 +221,7 @@ enum Slot {
 };
 
 }  // namespace vts
+
+// the opaque handle of the C ABI is the context itself
+struct vts_ctx : public vts::Ctx {};
+

@@ -75,6 +75,14 @@ class Result_t(C.Structure):
                 ("minres", C.c_int32), ("status", C.c_int32)]
 
 
+class RequestInfo_t(C.Structure):
+    _fields_ = [("id", C.c_int64), ("status", C.c_int32), ("outer", C.c_int32),
+                ("newton", C.c_int32), ("minres", C.c_int32), ("compliance", C.c_double),
+                ("alpha", C.c_double), ("sum_rho", C.c_double), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("footprint", C.c_size_t),
+                ("n_dof", C.c_int64), ("m", C.c_int64)]
+
+
 def _struct_dict(s):
     return {k: getattr(s, k) for k, _ in s._fields_}
 
@@ -87,6 +95,7 @@ SIGNATURES = {
     "vts_destroy": (None, [_P]),
     "vts_reset": (C.c_int, [_P]),
     "vts_footprint_bytes": (C.c_size_t, [C.POINTER(Problem_t), C.POINTER(Options_t)]),
+    "vts_allocated_bytes": (C.c_size_t, [_P]),
     "vts_sizes": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                             C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "vts_set_rho": (C.c_int, [_P, _P]),
@@ -108,6 +117,15 @@ SIGNATURES = {
     "vts_profile_stop": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double)]),
     "vts_last_error": (C.c_char_p, [_P]),
+    "vts_server_create": (C.c_int, [C.c_int32, C.c_size_t, C.POINTER(_P)]),
+    "vts_server_submit": (C.c_int, [_P, C.POINTER(Problem_t), C.POINTER(Options_t),
+                                    C.POINTER(C.c_int64)]),
+    "vts_server_poll": (C.c_int32, [_P, C.POINTER(RequestInfo_t), C.c_int32, C.c_double]),
+    "vts_server_fetch": (C.c_int, [_P, C.c_int64, _P, _P]),
+    "vts_server_clock": (C.c_double, [_P]),
+    "vts_server_counts": (None, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32)]),
+    "vts_server_destroy": (None, [_P]),
 }
 
 _lib = None
@@ -154,6 +172,32 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
+def _problem_struct(nx, ny, nz, levels, fixed, f, V, rho_lo, rho_hi, E, nu, h, precision):
+    """vts_problem over host arrays; returns it with the arrays it points to."""
+    fixed = np.ascontiguousarray(fixed, dtype=np.uint8)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    pr = Problem_t()
+    pr.nx, pr.ny, pr.nz, pr.levels = nx, ny, nz, levels
+    pr.E, pr.nu, pr.h, pr.V = E, nu, h, V
+    pr.fixed_host = fixed.ctypes.data_as(C.POINTER(C.c_uint8))
+    pr.f_host = f.ctypes.data_as(C.POINTER(C.c_double))
+    keep = [fixed, f]
+    if np.ndim(rho_lo):
+        lo = np.ascontiguousarray(rho_lo, dtype=np.float64)
+        pr.rho_lo_host = lo.ctypes.data_as(_D)
+        keep.append(lo)
+    else:
+        pr.rho_lo_s = float(rho_lo)
+    if np.ndim(rho_hi):
+        hi = np.ascontiguousarray(rho_hi, dtype=np.float64)
+        pr.rho_hi_host = hi.ctypes.data_as(_D)
+        keep.append(hi)
+    else:
+        pr.rho_hi_s = float(rho_hi)
+    pr.precision = precision
+    return pr, keep
+
+
 class Context:
     """One problem's device state (vts_ctx)."""
 
@@ -161,25 +205,8 @@ class Context:
                  nu=0.3, h=1.0, precision=VTS_FP64, options: Optional[Options_t] = None,
                  stream=None):
         L = lib()
-        self._fixed = np.ascontiguousarray(fixed, dtype=np.uint8)
-        self._f = np.ascontiguousarray(f, dtype=np.float64)
-        pr = Problem_t()
-        pr.nx, pr.ny, pr.nz, pr.levels = nx, ny, nz, levels
-        pr.E, pr.nu, pr.h, pr.V = E, nu, h, V
-        pr.fixed_host = self._fixed.ctypes.data_as(C.POINTER(C.c_uint8))
-        pr.f_host = self._f.ctypes.data_as(C.POINTER(C.c_double))
-        self._lo = self._hi = None
-        if np.ndim(rho_lo):
-            self._lo = np.ascontiguousarray(rho_lo, dtype=np.float64)
-            pr.rho_lo_host = self._lo.ctypes.data_as(_D)
-        else:
-            pr.rho_lo_s = float(rho_lo)
-        if np.ndim(rho_hi):
-            self._hi = np.ascontiguousarray(rho_hi, dtype=np.float64)
-            pr.rho_hi_host = self._hi.ctypes.data_as(_D)
-        else:
-            pr.rho_hi_s = float(rho_hi)
-        pr.precision = precision
+        pr, self._keep = _problem_struct(nx, ny, nz, levels, fixed, f, V, rho_lo, rho_hi, E, nu,
+                                         h, precision)
         self._pr = pr
         self._opt = options if options is not None else default_options()
         self.stream = stream
@@ -210,6 +237,9 @@ class Context:
         pr.f_host = C.cast(dummy_d, _D)
         pr.precision = precision
         return int(lib().vts_footprint_bytes(C.byref(pr), None))
+
+    def allocated_bytes(self) -> int:
+        return int(lib().vts_allocated_bytes(self.h))
 
     def close(self):
         if getattr(self, "h", None):
@@ -349,3 +379,63 @@ class Context:
             parts.append(np.asarray(d[name], float))
         parts.append([d["eps_nwt"], d["eps_mr"]])
         return np.concatenate(parts)
+
+
+class Server:
+    """Request loop for independent VTS problems (vts_server): a device pool
+    of hbm_bytes, `slots` workers with one stream each, admission by
+    footprint."""
+
+    def __init__(self, slots: int, hbm_bytes: int):
+        h_ = C.c_void_p()
+        st = lib().vts_server_create(int(slots), int(hbm_bytes), C.byref(h_))
+        if st != VTS_OK:
+            raise VtsError(st, "vts_server_create")
+        self.h = h_
+
+    def submit(self, pr, precision=None, options: Optional[Options_t] = None) -> int:
+        if precision is None:
+            precision = VTS_MIXED if pr.extra.get("precision") == "mixed" else VTS_FP64
+        ps, keep = _problem_struct(pr.nx, pr.ny, pr.nz, pr.levels, pr.fixed, pr.f, pr.V,
+                                   pr.rho_lo, pr.rho_hi, pr.E, pr.nu, pr.h, precision)
+        rid = C.c_int64()
+        st = lib().vts_server_submit(self.h, C.byref(ps),
+                                     C.byref(options) if options is not None else None,
+                                     C.byref(rid))
+        del keep                                  # the server copied the arrays
+        if st != VTS_OK:
+            raise VtsError(st, "vts_server_submit")
+        return rid.value
+
+    def poll(self, timeout_s: float = 0.0, max_n: int = 64):
+        buf = (RequestInfo_t * max_n)()
+        n = lib().vts_server_poll(self.h, buf, max_n, float(timeout_s))
+        return [_struct_dict(buf[i]) for i in range(n)]
+
+    def fetch(self, rid: int, m: int, n_dof: int):
+        rho = np.empty(m)
+        u = np.empty(n_dof)
+        st = lib().vts_server_fetch(self.h, int(rid), rho.ctypes.data_as(C.c_void_p),
+                                    u.ctypes.data_as(C.c_void_p))
+        if st != VTS_OK:
+            raise VtsError(st, f"vts_server_fetch({rid})")
+        return rho, u
+
+    def clock(self) -> float:
+        return float(lib().vts_server_clock(self.h))
+
+    def counts(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        lib().vts_server_counts(self.h, C.byref(a), C.byref(b), C.byref(c))
+        return dict(pending=a.value, running=b.value, finished=c.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vts_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
