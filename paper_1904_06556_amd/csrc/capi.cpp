@@ -34,11 +34,6 @@ struct Dims {
 int64_t nodes_of(const Dims& d) { return (int64_t)(d.nx + 1) * (d.ny + 1) * (d.nz + 1); }
 
 // sizes of every device allocation of a problem (bytes), in allocation order
-// block partials of one fused V-cycle step on the finest level: the
-// first-colour kernel (256 nodes per block) plus the colour passes (64 nodes
-// per block each), or the prolongation (256 nodes per block)
-int64_t gspart_count(int64_t nn) { return nn / 256 + nn / 64 + 64; }
-
 struct Plan {
     std::vector<size_t> bytes;
     size_t total() const {
@@ -142,7 +137,6 @@ Plan make_plan(const vts_problem* pr) {
     for (int q = 0; q < 5; ++q) add(m * 8);                          // dnl dnh c1 c2 wt
     for (int q = 0; q < 8; ++q) add((ndof + 1) * 8);                 // MINRES
     add(kRedSlots * kRedBlocks * 8); add(kRedSlots * 8);             // partials, red
-    add(gspart_count(nn) * 8); add(4);                               // V-cycle partials, counter
     {
         Ctx t;                                                       // tiled S partials
         t.nx = d.nx; t.ny = d.ny; t.nz = d.nz;
@@ -663,9 +657,6 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
     ALLOC(c.dnl, c.m); ALLOC(c.dnh, c.m); ALLOC(c.c1, c.m); ALLOC(c.c2, c.m); ALLOC(c.wt, c.m);
     for (int q = 0; q < 8; ++q) ALLOC(c.mv[q], c.ndof + 1);
     ALLOC(c.partials, kRedSlots * kRedBlocks);
-    ALLOC(c.gspart, gspart_count(c.nn));
-    ALLOC(c.gcount, 1);
-    HIPCHK(hipMemsetAsync(c.gcount, 0, sizeof(unsigned), c.s));
     ALLOC(c.spart, apply_S_tile_blocks(c));
     ALLOC(c.red, kRedSlots);
     {

@@ -502,57 +502,11 @@ k_coarse_solve(const double* __restrict__ A, int nc, const int* __restrict__ cma
 
 
 // ---------------------------------------------------------------------------
-// fused multi-workgroup steps: each block stores one partial sum of acol . z;
-// the block that finishes last (counted with one device-scope atomic, reset
-// by that block) adds all partials in index order and applies the alpha step,
-// so the result does not depend on block scheduling
+// fused entry steps of a level: the level's right-hand side (conversion of
+// the finest input, or restriction of the parent's residual) together with
+// its first forward colour, which with z = 0 reduces to z = D^-1 r on the
+// colour-0 nodes and z = 0 elsewhere
 // ---------------------------------------------------------------------------
-// sum over the block of one double per thread; valid in thread 0
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += sh[q];
-    __syncthreads();
-    return s;
-}
-
-// call in every thread after thread 0 stored the block's partial: true in
-// the block that finished last
-__device__ __forceinline__ bool finished_last(unsigned* counter) {
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(counter, 1u);
-        last = prev == gridDim.x - 1;
-        if (last) atomicExch(counter, 0u);
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last != 0;
-}
-
-// in the last block: alpha step from the sum of n partials.
-// mode 0: z_a += (r_a - acol.z - d z_a) / d;  mode 1: res_a = r_a - acol.z - d z_a
-template <typename T>
-__device__ __forceinline__ void alpha_from_partials(const double* part, int n, int64_t nn,
-                                                    double d, const T* r, T* z, T* res, int mode,
-                                                    double* sh) {
-    double s = 0.0;
-    for (int q = threadIdx.x; q < n; q += blockDim.x) s += part[q];
-    const double dot = block_sum(s, sh);
-    if (threadIdx.x == 0) {
-        const T td = (T)d;
-        const T v = r[3 * nn] - (T)dot - td * z[3 * nn];
-        if (mode == 0)
-            z[3 * nn] += v / td;
-        else
-            res[3 * nn] = v;
-    }
-}
-
 // colour-major index of natural node (i, j, k)
 template <typename T>
 __device__ __forceinline__ int64_t cm_index(const Level<T>& L, int i, int j, int k) {
@@ -561,9 +515,9 @@ __device__ __forceinline__ int64_t cm_index(const Level<T>& L, int i, int j, int
 }
 
 // the first forward colour with z = 0: z = D^-1 r on colour-0 nodes, zero
-// elsewhere; returns this node's acol . z
+// elsewhere
 template <typename T>
-__device__ __forceinline__ double first_colour(const Level<T>& L, int64_t N, int i, int j, int k,
+__device__ __forceinline__ void first_colour(const Level<T>& L, int64_t N, int i, int j, int k,
                                                T r0, T r1, T r2) {
     T z0 = 0, z1 = 0, z2 = 0;
     if (((i | j | k) & 1) == 0) {
@@ -578,17 +532,13 @@ __device__ __forceinline__ double first_colour(const Level<T>& L, int64_t N, int
     L.z[3 * N] = z0;
     L.z[3 * N + 1] = z1;
     L.z[3 * N + 2] = z2;
-    return (double)L.acol[3 * N] * z0 + (double)L.acol[3 * N + 1] * z1 +
-           (double)L.acol[3 * N + 2] * z2;
 }
 
 // finest level: r (FP64 S-vector) into the level's precision, then the first colour
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_top_init(Level<T> L, const double* __restrict__ rin, double* part) {
-    __shared__ double sh[kThreads / 64];
+k_top_init(Level<T> L, const double* __restrict__ rin) {
     const int64_t N = gidx();
-    double acc = 0.0;
     if (N < L.nn) {
         const int i = (int)(N % L.NX);
         const int64_t tt = N / L.NX;
@@ -597,24 +547,20 @@ k_top_init(Level<T> L, const double* __restrict__ rin, double* part) {
         L.r[3 * N] = r0;
         L.r[3 * N + 1] = r1;
         L.r[3 * N + 2] = r2;
-        acc = first_colour(L, N, i, j, k, r0, r1, r2);
+        first_colour(L, N, i, j, k, r0, r1, r2);
     }
     if (N == 0) {
         L.r[3 * L.nn] = (T)rin[3 * L.nn];
         L.z[3 * L.nn] = T(0);
     }
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // restriction P^T of the parent's residual (alpha by identity), then the
 // child's first colour
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_restrict_init(Level<T> F, Level<T> C, const T* __restrict__ rf, double* part) {
-    __shared__ double sh[kThreads / 64];
+k_restrict_init(Level<T> F, Level<T> C, const T* __restrict__ rf) {
     const int64_t N = gidx();
-    double acc = 0.0;
     if (N < C.nn) {
         const int I = (int)(N % C.NX);
         const int64_t tt = N / C.NX;
@@ -645,68 +591,12 @@ k_restrict_init(Level<T> F, Level<T> C, const T* __restrict__ rf, double* part) 
         C.r[3 * N] = r0;
         C.r[3 * N + 1] = r1;
         C.r[3 * N + 2] = r2;
-        acc = first_colour(C, N, I, J, K, r0, r1, r2);
+        first_colour(C, N, I, J, K, r0, r1, r2);
     }
     if (N == 0) {
         C.r[3 * C.nn] = rf[3 * F.nn];
         C.z[3 * C.nn] = T(0);
     }
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-// z_f += P z_c (alpha by identity), then the alpha step that opens the
-// backward sweep
-template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_prolong_alpha(Level<T> C, Level<T> F, const T* __restrict__ zc, T* __restrict__ zf,
-                double* part, unsigned* counter, double d) {
-    __shared__ double sh[kThreads / 64];
-    const int64_t n = gidx();
-    double acc = 0.0;
-    if (n < F.nn) {
-        const int i = (int)(n % F.NX);
-        const int64_t tt = n / F.NX;
-        const int j = (int)(tt % F.NY), k = (int)(tt / F.NY);
-        const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1,
-                  k1 = (k + 1) >> 1;
-        const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1),
-                wk = (k & 1) ? T(0.5) : T(1);
-        T a0 = 0, a1 = 0, a2 = 0;
-        for (int b = 0; b < 8; ++b) {
-            const int I = (b & 1) ? i1 : i0, J = ((b >> 1) & 1) ? j1 : j0, K = (b >> 2) ? k1 : k0;
-            if ((b & 1) && !(i & 1)) continue;
-            if (((b >> 1) & 1) && !(j & 1)) continue;
-            if ((b >> 2) && !(k & 1)) continue;
-            const int64_t N = nat(I, J, K, C.NX, C.NY);
-            const T wgt = wi * wj * wk;
-            a0 += wgt * zc[3 * N];
-            a1 += wgt * zc[3 * N + 1];
-            a2 += wgt * zc[3 * N + 2];
-        }
-        T z0 = zf[3 * n], z1 = zf[3 * n + 1], z2 = zf[3 * n + 2];
-        if (!F.fixed[3 * n]) z0 += a0;
-        if (!F.fixed[3 * n + 1]) z1 += a1;
-        if (!F.fixed[3 * n + 2]) z2 += a2;
-        zf[3 * n] = z0;
-        zf[3 * n + 1] = z1;
-        zf[3 * n + 2] = z2;
-        acc = (double)F.acol[3 * n] * z0 + (double)F.acol[3 * n + 1] * z1 +
-              (double)F.acol[3 * n + 2] * z2;
-    }
-    if (n == 0) zf[3 * F.nn] += zc[3 * C.nn];
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-    if (finished_last(counter))
-        alpha_from_partials(part, (int)gridDim.x, F.nn, d, (const T*)F.r, zf, F.res, 0, sh);
-}
-
-// alpha step from partials alone (a forward sweep with no colour launch
-// after its first colour)
-template <typename T>
-__global__ void k_alpha_part(Level<T> L, const double* __restrict__ part, int n, double d) {
-    __shared__ double sh[kThreads / 64];
-    alpha_from_partials(part, n, L.nn, d, (const T*)L.r, L.z, L.res, 0, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -738,16 +628,11 @@ __device__ __forceinline__ void row_partial(const Level<T>& L, int64_t t, int i,
     }
 }
 
-// TOP = finest level (a separate instantiation so profiles tell them apart).
-// Forward-sweep passes (dot != 0) store the block's sum of acol . z over the
-// updated nodes at dpart[blockIdx.x]; with final != 0 the last block also
-// applies the alpha step from the nfinal partials at dpart - doff.
+// TOP = finest level (a separate instantiation so profiles tell them apart)
 template <typename T, bool TOP>
 __global__ void __launch_bounds__(kBlk9)
-k_gs_color9(Level<T> L, int col, const T* __restrict__ r, T* __restrict__ z, int dot,
-            double* dpart, int doff, int nfinal, unsigned* counter, double d) {
+k_gs_color9(Level<T> L, int col, const T* __restrict__ r, T* __restrict__ z) {
     __shared__ T part[kRowWaves][3][64];
-    __shared__ double sh[kBlk9 / 64];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int64_t cnt = L.coff[col + 1] - L.coff[col];
     const int64_t tl = (int64_t)blockIdx.x * 64 + lane;
@@ -795,29 +680,15 @@ k_gs_color9(Level<T> L, int col, const T* __restrict__ r, T* __restrict__ z, int
         z[3 * n + 1] = z1;
         z[3 * n + 2] = z2;
     }
-    if (!dot) return;
-    double acc = 0.0;
-    if (g == 0 && valid)
-        acc = (double)L.acol[3 * n] * z0 + (double)L.acol[3 * n + 1] * z1 +
-              (double)L.acol[3 * n + 2] * z2;
-    if (g == 0) {
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-        if (lane == 0) dpart[blockIdx.x] = acc;
-    }
-    if (nfinal > 0 && finished_last(counter))
-        alpha_from_partials(dpart - doff, nfinal, L.nn, d, r, z, L.res, 0, sh);
 }
 
 // res = r - S z (displacement part, masked) and per-block partial sums of acol . z
-// The block that finishes last also forms the alpha residual
-// res_a = r_a - acol . z - d z_a from the partials.
 template <typename T, bool TOP>
 __global__ void __launch_bounds__(kBlk9)
 k_resid9(Level<T> L, const T* __restrict__ r, const T* __restrict__ z, T* __restrict__ res,
-         double* partials, unsigned* counter, double d) {
+         double* partials) {
     __shared__ T part[kRowWaves][3][64];
     __shared__ double red[64];
-    __shared__ double sh[kBlk9 / 64];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
     const T za = z[3 * L.nn];
     double acc = 0.0;
@@ -856,9 +727,6 @@ k_resid9(Level<T> L, const T* __restrict__ r, const T* __restrict__ z, T* __rest
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
         if (lane == 0) partials[SL_AUX * kRedBlocks + blockIdx.x] = acc;
     }
-    if (finished_last(counter))
-        alpha_from_partials(partials + SL_AUX * kRedBlocks, (int)gridDim.x, L.nn, d, r,
-                            const_cast<T*>(z), res, 1, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1196,57 +1064,48 @@ void mg_build(Ctx& c, Hierarchy<T>& H) {
         hipLaunchKernelGGL(k_chol_inverse, dim3(H.nc), dim3(256), 0, c.s, H.A, H.nc, H.Ainv);
 }
 
-// Gauss-Seidel colour passes of one sweep.  Forward (colours 1..7; colour 0
-// was applied by the kernel that set up r and z, whose ninit block partials
-// of acol . z lead c.gspart): every pass adds its block partials, and the last
-// pass applies the alpha step from all of them.  Backward: colours 7..0.  On
-// the finest level the colour passes are optionally bracketed by the
-// profiling events of the context (kernel class VTS_PROF_GS_FINE), one event
-// pair per sweep.
+// Gauss-Seidel colour passes of one sweep: forward colours 1..7 (colour 0
+// was applied by the kernel that set up the level's r and z) followed by
+// the alpha update, or backward colours 7..0.  On the finest level the
+// colour passes are optionally bracketed by the profiling events of the
+// context (kernel class VTS_PROF_GS_FINE), one event pair per sweep.
 template <typename T>
-static void gs_sweep(Ctx& c, Level<T>& Lk, bool forward, bool top, int ninit) {
+static void gs_sweep(Ctx& c, Level<T>& Lk, bool forward, bool top) {
     const bool prof = top && prof_begin(c, VTS_PROF_GS_FINE);
     double bytes = 0.0;
     int launches = 0;
-    int last = -1, total = ninit;
-    if (forward) {
-        for (int col = 1; col < 8; ++col) {
-            const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
-            if (cnt == 0) continue;
-            last = col;
-            total += (int)((cnt + 63) / 64);
-        }
-    }
-    int off = ninit;
     for (int q = forward ? 1 : 0; q < 8; ++q) {
         const int col = forward ? q : 7 - q;
         const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
         if (cnt == 0) continue;
         const dim3 grid((unsigned)((cnt + 63) / 64));
-        const int dot = forward ? 1 : 0;
-        const int nfinal = (forward && col == last) ? total : 0;
         if (top)
             hipLaunchKernelGGL((k_gs_color9<T, true>), grid, dim3(kBlk9), 0, c.s, Lk, col,
-                               (const T*)Lk.r, Lk.z, dot, c.gspart + off, off, nfinal, c.gcount,
-                               c.sum_w);
+                               (const T*)Lk.r, Lk.z);
         else
             hipLaunchKernelGGL((k_gs_color9<T, false>), grid, dim3(kBlk9), 0, c.s, Lk, col,
-                               (const T*)Lk.r, Lk.z, dot, c.gspart + off, off, nfinal, c.gcount,
-                               c.sum_w);
-        off += (int)grid.x;
+                               (const T*)Lk.r, Lk.z);
         bytes += gs_color_bytes(Lk, col, sizeof(T));
         ++launches;
     }
     if (prof) prof_end(c, bytes, launches);
-    if (forward && last < 0)
-        hipLaunchKernelGGL(k_alpha_part<T>, dim3(1), dim3(kThreads), 0, c.s, Lk,
-                           (const double*)c.gspart, ninit, c.sum_w);
+    if (forward) alpha_update(c, Lk);
 }
 
-// V-cycle below level k; on entry a multi-workgroup level (k > ksmall) holds
-// r and z after its first colour, with ninit leading partials in c.gspart
+// z_a += (r_a - acol . z - d z_a) / d
 template <typename T>
-static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k, int ninit) {
+static void alpha_update(Ctx& c, Level<T>& Lk) {
+    const int gr = red_grid_of(3 * Lk.nn);
+    hipLaunchKernelGGL(k_acol_dot<T>, dim3(gr), dim3(kThreads), 0, c.s, Lk, (const T*)Lk.z,
+                       c.partials);
+    hipLaunchKernelGGL(k_alpha_fin<T>, dim3(1), dim3(kThreads), 0, c.s, c.partials, gr, Lk.nn,
+                       c.sum_w, (const T*)Lk.r, Lk.z, Lk.res, 0);
+}
+
+// V-cycle below level k.  On entry a multi-workgroup level (k > ksmall,
+// k > 0) holds its r and z after the first forward colour.
+template <typename T>
+static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
     Level<T>& Lk = H.lev[k];
     const bool top = k == (int)H.lev.size() - 1;
     if (k <= H.ksmall) {
@@ -1255,8 +1114,8 @@ static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k, int ninit) {
         a.ks = k;
         a.d = c.sum_w;
         a.Ainv = H.Ainv;
-        a.cinv = H.cinv;
         a.nc = H.nc;
+        a.cinv = H.cinv;
         hipLaunchKernelGGL(k_vcycle_small<T>, dim3(1), dim3(1024), 0, c.s, a);
         return;
     }
@@ -1267,31 +1126,31 @@ static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k, int ninit) {
     }
     const double d = c.sum_w;
     // forward sweep (colours 1..7, then alpha)
-    gs_sweep(c, Lk, true, top, ninit);
-    // residual (and alpha residual), restriction, coarse correction
+    gs_sweep(c, Lk, true, top);
+    // residual, alpha residual, restriction, coarse correction, prolongation
     int64_t chunks = (Lk.nn + 63) / 64;
     const int grr = (int)(chunks < kRedBlocks ? chunks : kRedBlocks);
     if (top)
         hipLaunchKernelGGL((k_resid9<T, true>), dim3(grr), dim3(kBlk9), 0, c.s, Lk, (const T*)Lk.r,
-                           (const T*)Lk.z, Lk.res, c.partials, c.gcount, d);
+                           (const T*)Lk.z, Lk.res, c.partials);
     else
         hipLaunchKernelGGL((k_resid9<T, false>), dim3(grr), dim3(kBlk9), 0, c.s, Lk, (const T*)Lk.r,
-                           (const T*)Lk.z, Lk.res, c.partials, c.gcount, d);
+                           (const T*)Lk.z, Lk.res, c.partials);
+    hipLaunchKernelGGL(k_alpha_fin<T>, dim3(1), dim3(kThreads), 0, c.s, c.partials, grr, Lk.nn, d,
+                       (const T*)Lk.r, Lk.z, Lk.res, 1);
     Level<T>& Lc = H.lev[k - 1];
-    int ninit_c = 0;
-    if (k - 1 <= H.ksmall || k - 1 == 0) {
+    if (k - 1 <= H.ksmall || k - 1 == 0)
         hipLaunchKernelGGL(k_restrict<T>, dim3(grid_of(Lc.nn)), dim3(kThreads), 0, c.s, Lk, Lc,
                            (const T*)Lk.res, Lc.r, 1);
-    } else {
-        ninit_c = grid_of(Lc.nn);
-        hipLaunchKernelGGL(k_restrict_init<T>, dim3(ninit_c), dim3(kThreads), 0, c.s, Lk, Lc,
-                           (const T*)Lk.res, c.gspart);
-    }
-    vcycle_level(c, H, k - 1, ninit_c);
-    // prolongation and the alpha step that opens the backward sweep
-    hipLaunchKernelGGL(k_prolong_alpha<T>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s, Lc, Lk,
-                       (const T*)Lc.z, Lk.z, c.gspart, c.gcount, d);
-    gs_sweep(c, Lk, false, top, 0);
+    else
+        hipLaunchKernelGGL(k_restrict_init<T>, dim3(grid_of(Lc.nn)), dim3(kThreads), 0, c.s, Lk,
+                           Lc, (const T*)Lk.res);
+    vcycle_level(c, H, k - 1);
+    hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s, Lc, Lk,
+                       (const T*)Lc.z, Lk.z);
+    // backward sweep: alpha, then colours 7..0
+    alpha_update(c, Lk);
+    gs_sweep(c, Lk, false, top);
 }
 
 template <typename T>
@@ -1299,16 +1158,13 @@ void mg_vcycle(Ctx& c, Hierarchy<T>& H, const double* r, double* z) {
     const int L = (int)H.lev.size();
     Level<T>& fine = H.lev[L - 1];
     const int64_t nv = 3 * fine.nn + 1;
-    if (L - 1 <= H.ksmall || L == 1) {
+    if (L - 1 <= H.ksmall || L == 1)
         hipLaunchKernelGGL((k_convert<double, T>), dim3(grid_of(nv)), dim3(kThreads), 0, c.s, r,
                            fine.r, nv);
-        vcycle_level(c, H, L - 1, 0);
-    } else {
-        const int ninit = grid_of(fine.nn);
-        hipLaunchKernelGGL(k_top_init<T>, dim3(ninit), dim3(kThreads), 0, c.s, fine, r,
-                           c.gspart);
-        vcycle_level(c, H, L - 1, ninit);
-    }
+    else
+        hipLaunchKernelGGL(k_top_init<T>, dim3(grid_of(fine.nn)), dim3(kThreads), 0, c.s, fine,
+                           r);
+    vcycle_level(c, H, L - 1);
     hipLaunchKernelGGL((k_convert<T, double>), dim3(grid_of(nv)), dim3(kThreads), 0, c.s,
                        (const T*)fine.z, z, nv);
 }

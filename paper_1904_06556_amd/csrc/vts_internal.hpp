@@ -137,9 +137,6 @@ struct Ctx {
     bool converged = false;
     std::string err;
 
-    double* gspart = nullptr;    // block partials of the fused V-cycle steps
-    unsigned* gcount = nullptr;  // finished-block counter of those steps (returns to 0)
-
     std::vector<void*> allocs;   // hipMalloc'd buffers (contexts without an arena)
     char* arena = nullptr;       // caller-owned device range (server slots), or null
     size_t arena_size = 0, arena_used = 0;
