@@ -372,15 +372,16 @@ vts_status minres(Ctx& c, double eps, vts_linstats* out) {
             launch_scale(c, v, y, 1.0 / beta, n);
             launch_apply_S(c, v, y);
             if (it >= 2) launch_axpy(c, y, -beta / beta_old, r1, n);
-            launch_dot(c, v, y, n, SL_DOT);
-            if ((st = sync_red(c)) != VTS_OK) return st;
-            const double alpha = c.red_host[SL_DOT];
-            launch_axpy(c, y, -alpha / beta, r2, n);
+            // alpha = v . S v stays on the device for the next update; the
+            // host reads it with beta^2 after one synchronization
+            launch_dot(c, v, y, n, SL_MRALPHA);
+            launch_axpy_red(c, y, SL_MRALPHA, beta, r2, n);
             std::swap(r1, r2);
             std::swap(r2, y);
             precond(c, r2, y);
             launch_dot(c, r2, y, n, SL_DOT);
             if ((st = sync_red(c)) != VTS_OK) return st;
+            const double alpha = c.red_host[SL_MRALPHA];
             const double bsq = c.red_host[SL_DOT];
             if (!(bsq >= 0) || !std::isfinite(bsq)) {
                 c.err = "MINRES: preconditioner not positive definite";

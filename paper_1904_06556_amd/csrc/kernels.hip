@@ -708,6 +708,17 @@ void launch_axpy(Ctx& c, double* y, double a, const double* x, int64_t n) {
     hipLaunchKernelGGL(k_axpy, dim3(grid1d(n)), dim3(kThreads), 0, c.s, y, a, x, n);
 }
 
+__global__ void k_axpy_red(double* __restrict__ y, const double* __restrict__ red, int slot,
+                           double div, const double* __restrict__ x, int64_t n) {
+    const int64_t t = gid();
+    const double a = -(red[slot] / div);
+    if (t < n) y[t] += a * x[t];
+}
+void launch_axpy_red(Ctx& c, double* y, int slot, double div, const double* x, int64_t n) {
+    hipLaunchKernelGGL(k_axpy_red, dim3(grid1d(n)), dim3(kThreads), 0, c.s, y, c.red, slot, div,
+                       x, n);
+}
+
 // w = (v - eps_old w1 - delta w2) / gamma ; x += phi w
 __global__ void k_minres_w(double* __restrict__ w, const double* __restrict__ v,
                            const double* __restrict__ w1, const double* __restrict__ w2,

@@ -13,7 +13,7 @@ namespace vts {
 
 constexpr int kThreads = 256;          // block size of every 1D launch
 constexpr int kRedBlocks = 1024;       // max blocks of a reduction launch
-constexpr int kRedSlots = 16;          // quantities per reduction buffer
+constexpr int kRedSlots = 17;          // quantities per reduction buffer
 constexpr int kMaxCoarse = 4096;       // largest dense coarsest system
 
 // Block of 27 neighbours: offset (dx,dy,dz) in {-1,0,1}^3 -> s = (dx+1) + 3(dy+1) + 9(dz+1).
@@ -196,6 +196,8 @@ void launch_set(Ctx& c, double* dst, double v);
 void launch_fill(Ctx& c, double* dst, double v, int64_t n);
 void launch_scale(Ctx& c, double* dst, const double* src, double a, int64_t n);
 void launch_axpy(Ctx& c, double* y, double a, const double* x, int64_t n);
+// y -= (red[slot] / div) x, the scalar read on the device
+void launch_axpy_red(Ctx& c, double* y, int slot, double div, const double* x, int64_t n);
 void launch_minres_w(Ctx& c, double* w, const double* v, const double* w1, const double* w2,
                      double eps_old, double delta, double inv_gamma, double* x, double phi,
                      int64_t n);
@@ -217,7 +219,7 @@ template <typename T> int mg_check_factor(Ctx& c, Hierarchy<T>& H);
 enum Slot {
     SL_SUM_R1 = 0, SL_SUM_Z, SL_SUM_W, SL_G3SQ, SL_G4SQ, SL_G1SQ,
     SL_DOT = 6, SL_SLOPE_NU = 7, SL_LS = 8, SL_GAP = 9, SL_NLO = 10, SL_NHI = 11,
-    SL_STAT = 12, SL_SUM_RHO = 13, SL_WT = 14, SL_AUX = 15
+    SL_STAT = 12, SL_SUM_RHO = 13, SL_WT = 14, SL_AUX = 15, SL_MRALPHA = 16
 };
 
 }  // namespace vts
