@@ -83,16 +83,15 @@ typedef struct {
  * vts_default_options() fills the values used by this library: the paper's
  * beta = gamma = 0.3, eps_NWT = 1 and eps_MR rule; tighter eps_PBM = 1e-8,
  * eps_NWT_min = 1e-5, final eps_NWT = 5e-7 and a stationarity test so that
- * results meet a KKT residual of 1e-6; q_min = 1e-8 (the paper's value) for
- * the penalties q of nu >= 0; and a floor for the penalties p of the energy
- * constraints that is relative to the problem's energy scale,
- * p >= p_min |alpha| with p_min = 1e-3 (p_min_relative = 1; the volume
- * multiplier alpha equals the common element energy at the optimum).  The
- * constraint values scale with the square of the load, so the paper's
- * absolute p_min = 1e-8 ties the method's behaviour to that scale; the Schur
- * weights grow like rho/p, and a moderate relative floor keeps the Newton
- * systems within reach of the Gauss-Seidel multigrid.  PBM converges for
- * any positive floor. */
+ * results meet a KKT residual of 1e-6; and floors of the penalties that are
+ * relative to the problem's energy scale (p_min_relative = 1): p >= p_min
+ * |alpha| with p_min = 1e-3 for the energy constraints and q >= q_min |alpha|
+ * with the paper's q_min = 1e-8 for nu >= 0 (the volume multiplier alpha
+ * equals the common element energy at the optimum).  The constraint values
+ * scale with the square of the load, so the paper's absolute floors tie the
+ * method's behaviour to that scale; the Schur weights grow like rho/p, and a
+ * moderate relative p floor keeps the Newton systems within reach of the
+ * Gauss-Seidel multigrid.  PBM converges for any positive floors. */
 typedef struct {
     double beta, gamma, p_min, q_min;
     double eps_pbm, eps_nwt0, eps_nwt_min, eps_nwt_final;
@@ -103,7 +102,7 @@ typedef struct {
     double armijo_c1, armijo_min; /* Armijo constant and smallest step */
     int32_t max_outer, max_newton, max_minres;
     int32_t final_res4;           /* final Newton also requires the res_4 term */
-    int32_t p_min_relative;       /* 1: floor of p is p_min |alpha|; 0: p_min */
+    int32_t p_min_relative;       /* 1: floors p_min |alpha|, q_min |alpha|; 0: p_min, q_min */
 } vts_options;
 
 typedef struct {

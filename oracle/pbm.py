@@ -40,8 +40,8 @@ class Options:
     1e-6.  The floor of the energy-constraint penalties p is relative to the
     energy scale of the problem: p >= p_min |alpha| (alpha, the volume
     multiplier, equals the common element energy of the optimum), instead of
-    the paper's absolute 1e-8 (the floor q_min of q_lo, q_hi keeps the
-    paper's absolute 1e-8).  The constraint functions e_i - alpha + nu_lo -
+    the paper's absolute 1e-8; the floor of q_lo, q_hi is q_min |alpha| with
+    the paper's q_min = 1e-8.  The constraint functions e_i - alpha + nu_lo -
     nu_hi scale with the square of the load, and an absolute floor makes
     the method's behaviour depend on that scale; the multiplier method
     converges for any positive floor, the Schur weights grow like rho/p, so a
@@ -51,7 +51,7 @@ class Options:
     beta: float = 0.3
     gamma: float = 0.3
     p_min: float = 1e-3                       # floor of p / |alpha|; paper: 1e-8 absolute
-    p_min_relative: bool = True               # False: p_min is an absolute floor
+    p_min_relative: bool = True               # False: p_min, q_min are absolute floors
     q_min: float = 1e-8                       # floor of q_lo, q_hi (the paper's value)
     eps_pbm: float = 1e-8
     eps_nwt0: float = 1.0
@@ -63,7 +63,7 @@ class Options:
     eps_mr_min: float = 1e-9
     armijo_c1: float = 1e-4
     armijo_min: float = 2.0 ** -30
-    max_outer: int = 100
+    max_outer: int = 500
     max_newton: int = 100
     max_minres: int = 500
     final_res4: bool = True                   # final Newton also tests res_4
@@ -74,6 +74,14 @@ def p_floor(o: "Options", alpha: float) -> float:
     if o.p_min_relative and alpha != 0.0:
         return o.p_min * abs(alpha)
     return o.p_min
+
+
+def q_floor(o: "Options", alpha: float) -> float:
+    """Floor of the penalty parameters q_lo, q_hi after an outer iteration
+    (relative to the same energy scale as p when p_min_relative is set)."""
+    if o.p_min_relative and alpha != 0.0:
+        return o.q_min * abs(alpha)
+    return o.q_min
 
 
 def paper_options(eps_pbm: float = 1e-5) -> "Options":
@@ -468,8 +476,8 @@ class Solver:
                 break
             st.rho, st.mu_lo, st.mu_hi = rho_n, mul_n, muh_n
             st.p = np.maximum(o.gamma * st.p, p_floor(o, st.alpha))
-            st.q_lo = np.maximum(o.gamma * st.q_lo, o.q_min)
-            st.q_hi = np.maximum(o.gamma * st.q_hi, o.q_min)
+            st.q_lo = np.maximum(o.gamma * st.q_lo, q_floor(o, st.alpha))
+            st.q_hi = np.maximum(o.gamma * st.q_hi, q_floor(o, st.alpha))
             eps_nwt = max(min(100.0 * ratio, eps_nwt), o.eps_nwt_min)
         eps_final = o.eps_nwt_final if o.eps_nwt_final is not None else 10.0 * o.eps_pbm
         if self.status == "ok":

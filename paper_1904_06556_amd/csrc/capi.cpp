@@ -774,7 +774,7 @@ void vts_default_options(vts_options* o) {
     o->eps_mr_min = 1e-9;
     o->armijo_c1 = 1e-4;
     o->armijo_min = 9.313225746154785e-10;   // 2^-30
-    o->max_outer = 100;
+    o->max_outer = 500;
     o->max_newton = 100;
     o->max_minres = 500;
     o->final_res4 = 1;

@@ -617,11 +617,12 @@ __global__ void k_penalty(int64_t m, double gamma, double pmin, double qmin,
 }
 
 void launch_penalty_update(Ctx& c) {
-    // floor of p relative to the energy scale |alpha| unless asked otherwise
-    const double pfloor =
-        (c.opt.p_min_relative && c.alpha != 0.0) ? c.opt.p_min * fabs(c.alpha) : c.opt.p_min;
+    // floors of p and q relative to the energy scale |alpha| unless asked otherwise
+    const bool rel = c.opt.p_min_relative && c.alpha != 0.0;
+    const double pfloor = rel ? c.opt.p_min * fabs(c.alpha) : c.opt.p_min;
+    const double qfloor = rel ? c.opt.q_min * fabs(c.alpha) : c.opt.q_min;
     hipLaunchKernelGGL(k_penalty, dim3(grid1d(c.m)), dim3(kThreads), 0, c.s, c.m, c.opt.gamma,
-                       pfloor, c.opt.q_min, c.p, c.qlo, c.qhi);
+                       pfloor, qfloor, c.p, c.qlo, c.qhi);
 }
 
 __global__ void k_init(int64_t ndof, int64_t m, double rho0, double* u, double* nlo,
