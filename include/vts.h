@@ -274,6 +274,15 @@ vts_status vts_set_state(vts_ctx* ctx, const void* host_buf, size_t bytes);
 /* Message of the last failure on this context (static storage of ctx). */
 const char* vts_last_error(const vts_ctx* ctx);
 
+/* Advances each of the k contexts by one outer iteration of Algorithm 1
+ * (as vts_pbm_iterate), their device work overlapping: one host thread per
+ * context, each driving its own context's stream (the contexts should be
+ * created on different streams).  stats (NULL, or k entries) receives each
+ * context's statistics.  Returns VTS_OK, or the status of the first context
+ * (in index order) that failed; the others still complete their iteration.
+ * Each context's result is the same as with vts_pbm_iterate alone. */
+vts_status vts_group_step(vts_ctx** ctxs, int32_t k, vts_pbmstats* stats);
+
 /* ---------------------------------------------------------------------
  * Serving: a request loop for streams of independent VTS problems (the
  * problem (1.1) of each request solved by Algorithm 1 to the options'

@@ -267,6 +267,25 @@ vts_status vts_server_fetch(vts_server* S, int64_t id, double* rho_host, double*
     return VTS_OK;
 }
 
+vts_status vts_group_step(vts_ctx** ctxs, int32_t k, vts_pbmstats* stats) {
+    if (!ctxs || k < 0) return VTS_EINVAL;
+    for (int32_t q = 0; q < k; ++q)
+        if (!ctxs[q]) return VTS_EINVAL;
+    std::vector<vts_status> st(k, VTS_OK);
+    std::vector<std::thread> th;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return VTS_EDEVICE;
+    for (int32_t q = 0; q < k; ++q)
+        th.emplace_back([&, q] {
+            hipSetDevice(dev);
+            st[q] = vts_pbm_iterate(ctxs[q], stats ? &stats[q] : nullptr);
+        });
+    for (std::thread& t : th) t.join();
+    for (int32_t q = 0; q < k; ++q)
+        if (st[q] != VTS_OK) return st[q];
+    return VTS_OK;
+}
+
 double vts_server_clock(const vts_server* S) { return S ? S->now() : 0.0; }
 
 void vts_server_counts(const vts_server* S, int32_t* pending, int32_t* running,

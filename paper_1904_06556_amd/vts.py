@@ -117,6 +117,7 @@ SIGNATURES = {
     "vts_profile_stop": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double)]),
     "vts_last_error": (C.c_char_p, [_P]),
+    "vts_group_step": (C.c_int, [C.POINTER(_P), C.c_int32, C.POINTER(PbmStats_t)]),
     "vts_server_create": (C.c_int, [C.c_int32, C.c_size_t, C.POINTER(_P)]),
     "vts_server_submit": (C.c_int, [_P, C.POINTER(Problem_t), C.POINTER(Options_t),
                                     C.POINTER(C.c_int64)]),
@@ -379,6 +380,18 @@ class Context:
             parts.append(np.asarray(d[name], float))
         parts.append([d["eps_nwt"], d["eps_mr"]])
         return np.concatenate(parts)
+
+
+def group_step(contexts):
+    """One outer PBM iteration of each context, overlapping on the device
+    (vts_group_step); returns the per-context statistics."""
+    k = len(contexts)
+    hs = (_P * k)(*[c.h for c in contexts])
+    st = (PbmStats_t * k)()
+    code = lib().vts_group_step(hs, k, st)
+    if code != VTS_OK:
+        raise VtsError(code, "vts_group_step")
+    return [_struct_dict(st[i]) for i in range(k)]
 
 
 class Server:

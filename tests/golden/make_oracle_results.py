@@ -37,7 +37,8 @@ def main(idx: int):
                certificate_lower=float(lb), certificate_upper=float(ub), certificate_rel=float(cert),
                alpha=float(st.alpha), sum_rho=float(st.rho.sum()), V=P.V,
                outer=len(s.log.outer), newton=len(s.log.newton),
-               minres=int(sum(d["minres"] for d in s.log.newton)), **r)
+               minres=int(sum(d["minres"] for d in s.log.newton)),
+               options={k: getattr(opts, k) for k in vars(opts)}, **r)
     path = os.path.join(HERE, f"oracle_{pr.name}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)

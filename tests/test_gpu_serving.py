@@ -93,3 +93,21 @@ def test_submit_rejects():
     with pytest.raises(V.VtsError):
         srv.submit(bad)
     srv.close()
+
+
+def test_group_step_equals_single_steps():
+    probs = _mix()[:3]
+    streams = [torch.cuda.Stream() for _ in probs]
+    grouped = [V.Context.from_problem(p, precision=V.VTS_MIXED, stream=s)
+               for p, s in zip(probs, streams)]
+    single = [V.Context.from_problem(p, precision=V.VTS_MIXED) for p in probs]
+    for it in range(3):
+        say("group step", it)
+        gs = V.group_step(grouped)
+        for k, c in enumerate(single):
+            a = c.pbm_iterate()
+            assert a == gs[k]
+    for g, c in zip(grouped, single):
+        assert np.array_equal(g.get_state(), c.get_state())
+        g.close()
+        c.close()
