@@ -4,6 +4,8 @@ density by a sparse direct solve, KKT terms, duality certificate, iteration
 counts).  Calls only oracle/ and workloads/; the GPU path is not involved.
 
     python tests/golden/make_oracle_results.py 1        # the 64x32x32 cantilever
+
+Takes about half an hour on one core for the 64x32x32 cantilever.
 """
 import json
 import os
@@ -13,7 +15,6 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-import numpy as np  # noqa: E402
 
 import workloads as W  # noqa: E402
 from oracle import kkt, pbm  # noqa: E402
@@ -42,7 +43,6 @@ def main(idx: int):
     path = os.path.join(HERE, f"oracle_{pr.name}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
-    np.save(os.path.join(HERE, f"oracle_{pr.name}_rho.npy"), st.rho)
     print(json.dumps(out, indent=1))
 
 

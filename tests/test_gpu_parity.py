@@ -284,3 +284,30 @@ def test_checkpoint_roundtrip():
     assert np.array_equal(ctx.get_state(), s2)
     assert a["gap"] == b["gap"]
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", [V.VTS_FP64, V.VTS_MIXED])
+def test_benchmark_workload_matches_stored_oracle(precision):
+    """The 64x32x32 cantilever in the benchmark's configuration against the
+    stored FP64 oracle run (tests/golden/oracle_cant-64x32x32.json, written by
+    make_oracle_results.py from oracle/ alone): compliance within 1e-6, inside
+    the oracle's weak-duality bracket, KKT <= 1e-6."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "oracle_cant-64x32x32.json")))
+    pr = W.config(1)
+    say("benchmark workload vs stored oracle", pr.name, "precision", precision)
+    opts = V.default_options(eps_mr0=pr.extra["eps_mr0"])
+    ctx = V.Context.from_problem(pr, precision=precision, options=opts)
+    res = ctx.pbm_solve()
+    c_or = gold["compliance_half_fu"]
+    assert abs(res["compliance"] - c_or) <= 1e-6 * c_or
+    lo, hi = gold["certificate_lower"], gold["certificate_upper"]
+    assert lo * (1 - 1e-6) <= res["compliance"] <= hi * (1 + 1e-6)
+    d = ctx.state_dict()
+    P = pbm.VTS(pr)
+    r = kkt.kkt_residual(P.grid, P.Ke, P.f, P.V, P.rho_lo, P.rho_hi, d["rho"], d["u"], d["alpha"])
+    assert r["kkt"] <= 1e-6, r
+    assert abs(res["alpha"] - gold["alpha"]) <= 1e-5 * abs(gold["alpha"])
+    ctx.close()

@@ -96,3 +96,19 @@ def test_bridge_small_kkt():
     pr = W.bridge_top(8, 4, 4, 2, vol_frac=0.15)
     s, st = _solve(pr)
     assert _check(s, st)["kkt"] <= 1e-6
+
+
+def test_stored_benchmark_oracle_run_is_certified():
+    """The stored oracle run of the 64x32x32 cantilever: its compliance sits
+    inside its own weak-duality bracket, the bracket is tight, and the run met
+    the KKT target (values written by make_oracle_results.py)."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "oracle_cant-64x32x32.json")))
+    assert g["status"] == "ok" and g["workload"] == "cant-64x32x32"
+    assert g["certificate_lower"] <= g["compliance_exact"] <= g["certificate_upper"]
+    assert g["certificate_rel"] <= 1e-7
+    assert abs(g["compliance_half_fu"] - g["compliance_exact"]) <= 1e-6 * g["compliance_exact"]
+    assert g["kkt"] <= 1e-6
+    assert abs(g["sum_rho"] - g["V"]) <= 1e-6 * g["V"]
