@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--serve", action="store_true",
                     help="serving stream: Poisson arrivals of mixed VTS requests against the "
                          "request loop; prints one JSON line with p50/p99 latency per rate")
+    ap.add_argument("--doc", action="store_true",
+                    help="the damped optimality-criteria method (the paper's comparison "
+                         "method) on the same workload and device: time to its stopping "
+                         "test, beside PBM's time-to-KKT; prints one JSON line")
     ap.add_argument("--requests", type=int, default=20, help="requests per rate (--serve)")
     ap.add_argument("--slots", type=int, default=4, help="concurrent requests (--serve)")
     ap.add_argument("--pool-gb", type=float, default=16.0, help="device pool (--serve)")
@@ -208,6 +212,64 @@ def kernels_only(a, torch, W, V):
     return 0
 
 
+def doc_compare(a, torch, W, V):
+    """DOC (Algorithm 4, q = 0.5, eps_DOC = 1e-3, bisection tolerance
+    1e-4) and PBM on the same workload, both on the GPU."""
+    pr = W.config(a.workload)
+    prec = V.VTS_MIXED if pr.extra.get("precision") == "mixed" else V.VTS_FP64
+    eps_mr0 = pr.extra.get("eps_mr0")
+    opts = V.default_options()
+    if eps_mr0:
+        opts.eps_mr0 = eps_mr0
+    ctx = V.Context.from_problem(pr, precision=prec, options=opts)
+    ctx.reset()
+    ctx.pbm_solve()
+    torch.cuda.synchronize()
+    ctx.reset()
+    t0 = time.perf_counter()
+    r = ctx.pbm_solve()
+    torch.cuda.synchronize()
+    t_pbm = time.perf_counter() - t0
+    print(f"PBM: {t_pbm:.2f} s, {r['outer']} outer, {r['newton']} Newton", file=sys.stderr,
+          flush=True)
+    # DOC iterations one call at a time, so that progress is visible
+    ctx.reset()
+    t0 = time.perf_counter()
+    d = dict(iterations=0, minres_its=0, status=V.VTS_ENOTCONV)
+    for k in range(5000):
+        s = ctx.doc_step(q=0.5, tau=1e-4, eps_doc=1e-3, eps_mr=1e-6)
+        d["iterations"] = k + 1
+        d["minres_its"] += s["minres_its"]
+        if (k + 1) % 20 == 0:
+            print(f"DOC iteration {k + 1}: change {s['change']:.2e} compliance "
+                  f"{s['compliance']:.6f} minres {s['minres_its']}", file=sys.stderr, flush=True)
+        if s["converged"]:
+            d["status"] = V.VTS_OK
+            break
+    torch.cuda.synchronize()
+    t_doc = time.perf_counter() - t0
+    # 1/2 f^T u of the last iteration: at convergence rho is kept, so this is
+    # the compliance of the returned design (to the MINRES tolerance)
+    c_doc = s["compliance"]
+    line = {
+        "metric": METRIC, "value": 1.0 / t_doc, "unit": "DOC solves/s (eps_DOC 1e-3)",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": t_doc * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == V.VTS_FP64 else "f64+f32mg", "data": "synthetic",
+        "config": {"workload": pr.name, "method": "DOC (Algorithm 4)", "q": 0.5,
+                   "eps_doc": 1e-3, "eps_mr": 1e-6},
+        "doc": {"seconds": t_doc, "iterations": d["iterations"], "minres": d["minres_its"],
+                "status": d["status"], "compliance": c_doc},
+        "pbm": {"seconds": t_pbm, "outer": r["outer"], "newton": r["newton"],
+                "minres": r["minres"], "compliance": r["compliance"]},
+        "doc_over_pbm_time": t_doc / t_pbm,
+        "doc_compliance_excess": (c_doc - r["compliance"]) / r["compliance"],
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
+
+
 def serving(a, torch, W, V):
     """Latency of a Poisson stream of mixed requests (grids 16x8x8 .. 96x48x48,
     cantilever edge / bridge face loads, V/m ~ U[0.1, 0.4]) at three arrival
@@ -273,6 +335,8 @@ def main():
         return kernels_only(a, torch, W, V)
     if a.serve:
         return serving(a, torch, W, V)
+    if a.doc:
+        return doc_compare(a, torch, W, V)
     pr = W.config(a.workload)
     eps_mr0 = pr.extra.get("eps_mr0")
     opts = V.default_options()

@@ -274,6 +274,37 @@ vts_status vts_set_state(vts_ctx* ctx, const void* host_buf, size_t bytes);
 /* Message of the last failure on this context (static storage of ctx). */
 const char* vts_last_error(const vts_ctx* ctx);
 
+/* ---------------------------------------------------------------------
+ * Damped optimality criteria (Section 5, Algorithm 4), the paper's
+ * comparison method, on the same device data: the state equation
+ * K(rho) u = f is solved by the same MINRES with one multigrid V-cycle
+ * (the Schur operator with rho' = rho, no rank-one terms and a decoupled
+ * alpha), followed by the bisection on alpha of Algorithm 4.  It overwrites
+ * the PBM working data of the context (u, the operator, the hierarchy).
+ * --------------------------------------------------------------------- */
+typedef struct {
+    double change;                /* ||rho+ - rho||_inf */
+    double alpha;                 /* bisection midpoint defining rho+ */
+    double compliance;            /* 1/2 f^T u at the iteration's rho */
+    double volume;                /* sum rho+ */
+    int32_t bisection_steps, minres_its;
+    int32_t converged;            /* change <= eps_doc: rho kept, as Algorithm 4 stops */
+    int32_t iterations;           /* DOC iterations taken (vts_doc_solve) */
+} vts_docstats;
+
+/* One iteration of Algorithm 4 at the context's rho with exponent q,
+ * bisection tolerance tau (the paper: 0.1 eps_doc, bracket [0, 10000]) and
+ * MINRES tolerance eps_mr.  If eps_doc > 0 and ||rho+ - rho||_inf <= eps_doc
+ * the iteration reports convergence and keeps rho; otherwise rho becomes
+ * rho+.  VTS_EINVAL for q <= 0 or tau <= 0. */
+vts_status vts_doc_step(vts_ctx* ctx, double q, double tau, double eps_doc, double eps_mr,
+                        vts_docstats* out);
+
+/* Algorithm 4 from the context's rho until convergence (tau = 0.1 eps_doc)
+ * or max_iter iterations (VTS_ENOTCONV). */
+vts_status vts_doc_solve(vts_ctx* ctx, double q, double eps_doc, double eps_mr, int32_t max_iter,
+                         vts_docstats* out);
+
 /* Advances each of the k contexts by one outer iteration of Algorithm 1
  * (as vts_pbm_iterate), their device work overlapping: one host thread per
  * context, each driving its own context's stream (the contexts should be

@@ -955,6 +955,75 @@ vts_status vts_pbm_solve(vts_ctx* cp, vts_result* res) {
     return st;
 }
 
+vts_status vts_doc_step(vts_ctx* cp, double q, double tau, double eps_doc, double eps_mr,
+                        vts_docstats* out) {
+    if (!cp || !(q > 0) || !(tau > 0)) return VTS_EINVAL;
+    Ctx& c = *cp;
+    // the state equation: MINRES with the V-cycle on blockdiag(K(rho), 1)
+    c.eval_valid = false;
+    c.setup_valid = false;
+    launch_doc_setup(c);
+    c.sum_w = 1.0;
+    vts_status st = build_mg(c);
+    if (st != VTS_OK) return st;
+    vts_linstats ls{0, 0.0};
+    if ((st = minres(c, eps_mr, &ls)) != VTS_OK) return st;
+    HIPCHK(hipMemcpyAsync(c.u, c.dy, c.ndof * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+    launch_energy(c, c.u, c.e);
+    launch_dot(c, c.f, c.u, c.ndof, SL_DOT);
+    // bisection on alpha (Algorithm 4)
+    double lo = 0.0, hi = 1e4, alpha = 0.5 * (lo + hi);
+    int steps = 0;
+    while ((hi - lo) / (hi + lo) > tau) {
+        alpha = 0.5 * (hi + lo);
+        launch_doc_volume(c, q, alpha);
+        if ((st = sync_red(c)) != VTS_OK) return st;
+        if (c.red_host[SL_SUM_RHO] > c.V)
+            lo = alpha;
+        else
+            hi = alpha;
+        ++steps;
+    }
+    launch_doc_candidate(c, q, alpha, c.c1);
+    launch_doc_volume(c, q, alpha);
+    if ((st = sync_red(c)) != VTS_OK) return st;
+    const double change = c.red_host[SL_STAT];
+    const bool conv = eps_doc > 0 && change <= eps_doc;
+    if (!conv)
+        HIPCHK(hipMemcpyAsync(c.rho, c.c1, c.m * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c.s));
+    c.minres_total += ls.iterations;
+    if (out) {
+        out->change = change;
+        out->alpha = alpha;
+        out->compliance = 0.5 * c.red_host[SL_DOT];
+        out->volume = c.red_host[SL_SUM_RHO];
+        out->bisection_steps = steps;
+        out->minres_its = ls.iterations;
+        out->converged = conv ? 1 : 0;
+        out->iterations = 1;
+    }
+    return VTS_OK;
+}
+
+vts_status vts_doc_solve(vts_ctx* cp, double q, double eps_doc, double eps_mr, int32_t max_iter,
+                         vts_docstats* out) {
+    if (!cp || !(eps_doc > 0) || max_iter < 1) return VTS_EINVAL;
+    vts_docstats s{};
+    int32_t minres = 0;
+    for (int32_t k = 0; k < max_iter; ++k) {
+        vts_status st = vts_doc_step(cp, q, 0.1 * eps_doc, eps_doc, eps_mr, &s);
+        if (st != VTS_OK) return st;
+        minres += s.minres_its;
+        s.iterations = k + 1;
+        if (s.converged) break;
+    }
+    s.minres_its = minres;
+    if (out) *out = s;
+    return s.converged ? VTS_OK : VTS_ENOTCONV;
+}
+
 vts_status vts_get_vector(const vts_ctx* cp, int32_t which, double* dst) {
     if (!cp || !dst) return VTS_EINVAL;
     Ctx& c = const_cast<vts_ctx&>(*cp);

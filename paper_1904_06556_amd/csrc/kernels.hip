@@ -5,6 +5,8 @@
 // component-major ([j][e]) so that a wave reads them coalesced.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cfloat>
 #include <cmath>
 
@@ -718,6 +720,74 @@ __global__ void k_axpy_red(double* __restrict__ y, const double* __restrict__ re
 void launch_axpy_red(Ctx& c, double* y, int slot, double div, const double* x, int64_t n) {
     hipLaunchKernelGGL(k_axpy_red, dim3(grid1d(n)), dim3(kThreads), 0, c.s, y, c.red, slot, div,
                        x, n);
+}
+
+// ---------------------------------------------------------------------------
+// damped optimality criteria (Algorithm 4)
+// ---------------------------------------------------------------------------
+// K(rho) as the Schur operator with rho' = rho, w = 0 (no rank-one terms, no
+// alpha coupling) and right-hand side [f; 0]
+__global__ void k_doc_setup(int64_t m, int64_t ndof, const double* __restrict__ rho,
+                            const double* __restrict__ f, double* __restrict__ r1,
+                            double* __restrict__ w, double* __restrict__ be,
+                            double* __restrict__ rhs) {
+    const int64_t t = gid();
+    if (t < m) {
+        r1[t] = rho[t];
+        w[t] = 0.0;
+    }
+    if (t < 24 * m) be[t] = 0.0;
+    if (t < ndof) rhs[t] = f[t];
+    if (t == 0) rhs[ndof] = 0.0;
+}
+void launch_doc_setup(Ctx& c) {
+    hipLaunchKernelGGL(k_doc_setup, dim3(grid1d(std::max<int64_t>(24 * c.m, c.ndof + 1))),
+                       dim3(kThreads), 0, c.s, c.m, c.ndof, c.rho, c.f, c.r1, c.w, c.be, c.rhs);
+}
+
+__device__ __forceinline__ double doc_candidate(double rho, double e, double lo, double hi,
+                                                double q, double alpha) {
+    // rho (u^T K_i u)^q / alpha, clamped to the bounds
+    return fmin(fmax(rho * pow(2.0 * e, q) / alpha, lo), hi);
+}
+
+// partial sums of the candidate volume sum_i rho+_i(alpha)
+__global__ void __launch_bounds__(kThreads)
+k_doc_volume(int64_t m, double q, double alpha, const double* __restrict__ rho,
+             const double* __restrict__ e, const double* __restrict__ lo,
+             const double* __restrict__ hi, double* partials) {
+    double acc[1] = {0.0};
+    for (int64_t t = gid(); t < m; t += (int64_t)gridDim.x * blockDim.x)
+        acc[0] += doc_candidate(rho[t], e[t], lo[t], hi[t], q, alpha);
+    block_sum_store<1>(acc, partials, SL_SUM_RHO);
+}
+void launch_doc_volume(Ctx& c, double q, double alpha) {
+    const int g = red_grid(c.m);
+    hipLaunchKernelGGL(k_doc_volume, dim3(g), dim3(kThreads), 0, c.s, c.m, q, alpha, c.rho, c.e,
+                       c.rlo, c.rhi, c.partials);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c.s, c.partials, g,
+                       (int)SL_SUM_RHO, 0u, c.red);
+}
+
+// rho+ (alpha) into out and the partial maxima of |rho+ - rho|
+__global__ void __launch_bounds__(kThreads)
+k_doc_candidate(int64_t m, double q, double alpha, const double* __restrict__ rho,
+                const double* __restrict__ e, const double* __restrict__ lo,
+                const double* __restrict__ hi, double* __restrict__ out, double* partials) {
+    double acc[1] = {0.0};
+    for (int64_t t = gid(); t < m; t += (int64_t)gridDim.x * blockDim.x) {
+        const double r = doc_candidate(rho[t], e[t], lo[t], hi[t], q, alpha);
+        out[t] = r;
+        acc[0] = fmax(acc[0], fabs(r - rho[t]));
+    }
+    block_sum_store<1>(acc, partials, SL_STAT, 1u);
+}
+void launch_doc_candidate(Ctx& c, double q, double alpha, double* out) {
+    const int g = red_grid(c.m);
+    hipLaunchKernelGGL(k_doc_candidate, dim3(g), dim3(kThreads), 0, c.s, c.m, q, alpha, c.rho,
+                       c.e, c.rlo, c.rhi, out, c.partials);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c.s, c.partials, g,
+                       (int)SL_STAT, 1u, c.red);
 }
 
 // w = (v - eps_old w1 - delta w2) / gamma ; x += phi w

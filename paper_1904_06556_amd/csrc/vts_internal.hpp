@@ -198,6 +198,10 @@ void launch_scale(Ctx& c, double* dst, const double* src, double a, int64_t n);
 void launch_axpy(Ctx& c, double* y, double a, const double* x, int64_t n);
 // y -= (red[slot] / div) x, the scalar read on the device
 void launch_axpy_red(Ctx& c, double* y, int slot, double div, const double* x, int64_t n);
+// damped optimality criteria (Algorithm 4)
+void launch_doc_setup(Ctx& c);                               // r1 = rho, w = 0, rhs = [f; 0]
+void launch_doc_volume(Ctx& c, double q, double alpha);     // sum rho+(alpha) -> red[SL_SUM_RHO]
+void launch_doc_candidate(Ctx& c, double q, double alpha, double* out); // max |drho| -> red[SL_STAT]
 void launch_minres_w(Ctx& c, double* w, const double* v, const double* w1, const double* w2,
                      double eps_old, double delta, double inv_gamma, double* x, double phi,
                      int64_t n);

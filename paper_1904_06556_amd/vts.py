@@ -75,6 +75,12 @@ class Result_t(C.Structure):
                 ("minres", C.c_int32), ("status", C.c_int32)]
 
 
+class DocStats_t(C.Structure):
+    _fields_ = [("change", C.c_double), ("alpha", C.c_double), ("compliance", C.c_double),
+                ("volume", C.c_double), ("bisection_steps", C.c_int32),
+                ("minres_its", C.c_int32), ("converged", C.c_int32), ("iterations", C.c_int32)]
+
+
 class RequestInfo_t(C.Structure):
     _fields_ = [("id", C.c_int64), ("status", C.c_int32), ("outer", C.c_int32),
                 ("newton", C.c_int32), ("minres", C.c_int32), ("compliance", C.c_double),
@@ -118,6 +124,10 @@ SIGNATURES = {
                                    C.POINTER(C.c_double)]),
     "vts_last_error": (C.c_char_p, [_P]),
     "vts_group_step": (C.c_int, [C.POINTER(_P), C.c_int32, C.POINTER(PbmStats_t)]),
+    "vts_doc_step": (C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_double,
+                               C.POINTER(DocStats_t)]),
+    "vts_doc_solve": (C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                C.POINTER(DocStats_t)]),
     "vts_server_create": (C.c_int, [C.c_int32, C.c_size_t, C.POINTER(_P)]),
     "vts_server_submit": (C.c_int, [_P, C.POINTER(Problem_t), C.POINTER(Options_t),
                                     C.POINTER(C.c_int64)]),
@@ -320,6 +330,19 @@ class Context:
         if check:
             self._check(st)
         return _struct_dict(r)
+
+    # --- damped optimality criteria (Algorithm 4) -------------------------
+    def doc_step(self, q=0.5, tau=1e-4, eps_doc=-1.0, eps_mr=1e-6):
+        s = DocStats_t()
+        self._check(lib().vts_doc_step(self.h, q, tau, eps_doc, eps_mr, C.byref(s)))
+        return _struct_dict(s)
+
+    def doc_solve(self, q=0.5, eps_doc=1e-3, eps_mr=1e-6, max_iter=1000, check=True):
+        s = DocStats_t()
+        st = lib().vts_doc_solve(self.h, q, eps_doc, eps_mr, max_iter, C.byref(s))
+        if check:
+            self._check(st)
+        return dict(_struct_dict(s), status=st)
 
     # --- profiling -------------------------------------------------------
     def profile_start(self, kernel_class):

@@ -1,0 +1,61 @@
+"""Damped optimality criteria (Algorithm 4) on the GPU against the oracle:
+the iterates after a fixed number of steps and the converged design."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import doc, kkt, pbm
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_1904_06556_amd import vts as V  # noqa: E402
+
+
+def say(*a):
+    print("[doc]", *a, flush=True)
+
+
+CASES = {
+    "cant-8x4x4-l3": lambda: W.config(0),
+    "bridge-16x8x8-l3-h": lambda: W.bridge_top(16, 8, 8, 3, vol_frac=0.2, h=0.25),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_doc_iterates_match_oracle(case):
+    pr = CASES[case]()
+    eps = 1e-4
+    steps = 6
+    say("iterates", case)
+    ref = doc.doc_solve(pr, eps=eps, iterations=steps)
+    ctx = V.Context.from_problem(pr, precision=V.VTS_FP64)
+    for k in range(steps):
+        s = ctx.doc_step(q=0.5, tau=0.1 * eps, eps_doc=-1.0, eps_mr=1e-12)
+        h = ref.history[k]
+        assert s["bisection_steps"] == h["bisection"]
+        assert abs(s["alpha"] - h["alpha"]) <= 1e-9 * h["alpha"]
+        assert abs(s["compliance"] - h["compliance"]) <= 1e-9 * h["compliance"]
+        assert abs(s["change"] - h["change"]) <= 1e-8
+    rho = ctx.vector("rho").cpu().numpy()
+    assert np.max(np.abs(rho - ref.rho)) <= 1e-8
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [V.VTS_FP64, V.VTS_MIXED])
+def test_doc_converges_like_oracle(precision):
+    pr = W.config(0)
+    say("solve", pr.name, precision)
+    ref = doc.doc_solve(pr, eps=1e-4)
+    ctx = V.Context.from_problem(pr, precision=precision)
+    s = ctx.doc_solve(q=0.5, eps_doc=1e-4, eps_mr=1e-10, max_iter=2000)
+    assert s["converged"] == 1
+    assert abs(s["iterations"] - ref.iterations) <= 2
+    P = pbm.VTS(pr)
+    rho = ctx.vector("rho").cpu().numpy()
+    c_gpu = kkt.compliance(P.grid, P.Ke, rho, P.f)
+    c_ref = kkt.compliance(P.grid, P.Ke, ref.rho, P.f)
+    assert abs(c_gpu - c_ref) <= 1e-6 * c_ref
+    # volume to the bisection tolerance tau = 0.1 eps_doc
+    assert abs(rho.sum() - P.V) <= 3e-5 * P.V
+    ctx.close()
