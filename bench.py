@@ -96,11 +96,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pmc_cant-64x32x32_fp64.md
 
 
 def kernel_source_hash():
+    """Hash of the multigrid kernels' source and of the level structure they
+    read (the counters stay valid while both are unchanged)."""
     import hashlib
+    csrc = os.path.join(ROOT, "paper_1904_06556_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("mg.hip", "vts_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_1904_06556_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(csrc, "mg.hip"), "rb") as fh:
+        h.update(fh.read())
+    with open(os.path.join(csrc, "vts_internal.hpp")) as fh:
+        hdr = fh.read()
+    a = hdr.index("struct Level {")
+    h.update(hdr[a:hdr.index("};", a)].encode())
     return h.hexdigest()[:16]
 
 
