@@ -331,7 +331,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {a.gpus} is not supported "
-              f"(this build has no multi-GPU path; see DESIGN.md)", file=sys.stderr)
+              f"(the path runs on one GPU; there is no multi-GPU code)", file=sys.stderr)
         return 2
     import torch
     import workloads as W

@@ -5,7 +5,7 @@ penalties (p, q_lo, q_hi).  All displacement-sized vectors live in the
 all-DOF layout with zeros at fixed DOFs; the linear algebra of the reduced
 system runs on the free DOFs plus the scalar alpha (size n+1).
 
-Readings of the paper used here (each also listed in the design doc):
+Readings of the paper used here:
   * the constant term of res_3 in eq. (3.10) is taken as -rho_lo (the sign
     that differentiating eq. (3.9) gives; it is printed as +rho_lo);
   * the mu_lo update of Algorithm 1 uses phi'(-nu_lo/q_lo), as eq. (3.4)

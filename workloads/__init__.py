@@ -17,8 +17,10 @@ Boundary conditions (Section 7, the cantilever and bridge descriptions):
   * cantilever: every node of the face x = 0 is fixed in all directions;
   * bridge: the four corner nodes of the bottom face z = 0 are fixed in all
     directions.
-The load magnitudes and patch shapes are not given in the paper; the readings
-used here are listed in the design doc.
+The load magnitudes and patch shapes are not given in the paper; the
+readings used here: unit nodal loads on the cantilever edge, a unit pressure
+on the whole bridge top face (consistent bilinear nodal forces), and seeded
+unit point loads for the three-load cantilever.
 """
 from __future__ import annotations
 
@@ -220,7 +222,7 @@ def paper_bridge(mx, my, mz, l) -> Problem:
 
 
 def config(idx: int) -> Problem:
-    """The benchmark workloads (1-based numbering in the design doc):
+    """The benchmark workloads:
     0: cantilever 8x4x4, 3 levels, V = 0.3 m, FP64
     1: cantilever 64x32x32, 5 levels, V = 0.2 m, FP64, MINRES tol 1e-2
     2: bridge 128x64x64, 6 levels, V = 0.15 m, mixed precision
