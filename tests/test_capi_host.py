@@ -91,3 +91,11 @@ def test_state_layout_roundtrip_pack():
              mu_hi=[5.0], p=[6.0], q_lo=[7.0], q_hi=[8.0], eps_nwt=0.5, eps_mr=1e-3)
     b = V.Context.pack_state(d, 6, 1)
     assert b.size == 6 + 1 + 8 + 2 and b[6] == 2.0 and b[-1] == 1e-3
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys as _sys
+    r = subprocess.run([_sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr

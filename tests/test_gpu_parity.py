@@ -311,3 +311,39 @@ def test_benchmark_workload_matches_stored_oracle(precision):
     assert r["kkt"] <= 1e-6, r
     assert abs(res["alpha"] - gold["alpha"]) <= 1e-5 * abs(gold["alpha"])
     ctx.close()
+
+
+def test_pbm_solve_is_bitwise_repeatable():
+    pr = W.config(0)
+    say("repeatability", pr.name)
+    ctx = V.Context.from_problem(pr, precision=V.VTS_MIXED)
+    a = ctx.pbm_solve()
+    sa = ctx.get_state()
+    ctx.reset()
+    b = ctx.pbm_solve()
+    assert a == b
+    assert np.array_equal(sa, ctx.get_state())
+    ctx.close()
+
+
+def test_profile_hook_counts_launches():
+    pr = W.config(1)
+    say("profile hook", pr.name)
+    ctx = V.Context.from_problem(pr, precision=V.VTS_FP64)
+    ctx.newton_setup()
+    n = ctx.n_dof + 1
+    r = torch.rand(n, dtype=torch.float64, device="cuda")
+    z = torch.empty_like(r)
+    ctx.profile_start("gs_fine")
+    for _ in range(3):
+        ctx.precondition(r, z)
+    p = ctx.profile_stop()
+    # 7 forward passes (colour 0 is fused into the input step) + 8 backward
+    assert p["launches"] == 3 * 15 and p["total_ms"] > 0 and p["bytes"] > 0
+    ctx.profile_start("apply_K")
+    x = torch.rand(ctx.n_dof, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    ctx.apply_K(x, y)
+    p = ctx.profile_stop()
+    assert p["launches"] == 1 and p["bytes"] == 16.0 * ctx.n_dof + 8.0 * ctx.m + ctx.n_dof
+    ctx.close()
