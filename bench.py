@@ -55,6 +55,9 @@ def parse():
                     help="the damped optimality-criteria method (the paper's comparison "
                          "method) on the same workload and device: time to its stopping "
                          "test, beside PBM's time-to-KKT; prints one JSON line")
+    ap.add_argument("--paper", action="store_true",
+                    help="the paper's CANT/BRIDGE-4-2-2-{5,6} problems with the paper's "
+                         "parameters (Section 7), iteration counts beside Tables 3 and 4")
     ap.add_argument("--requests", type=int, default=20, help="requests per rate (--serve)")
     ap.add_argument("--slots", type=int, default=4, help="concurrent requests (--serve)")
     ap.add_argument("--pool-gb", type=float, default=16.0, help="device pool (--serve)")
@@ -218,6 +221,60 @@ def kernels_only(a, torch, W, V):
     return 0
 
 
+# PBM iterations / Newton steps / MINRES iterations printed in Tables 3 and 4
+# (Section 7.2) for these problems, with the paper's parameters
+PAPER_COUNTS = {"CANT-4-2-2-5": (15, 57, 153), "CANT-4-2-2-6": (17, 59, 118),
+                "BRIDGE-4-2-2-5": (14, 45, 155), "BRIDGE-4-2-2-6": (15, 57, 317)}
+
+
+def paper_problems(a, torch, W, V):
+    """PBM with the parameter values stated after Algorithm 1 and in Section
+    7 (eps_PBM = 1e-5, eps_NWT_min = 1e-3, final eps_NWT = 10 eps_PBM,
+    absolute floors p_min = q_min = 1e-8, eps_MR0 = 1e-4 sqrt(n), rho_lo = 0)
+    on the CANT and BRIDGE 4-2-2-l problems, FP64."""
+    out = {}
+    for name in PAPER_COUNTS:
+        kind, mx, my, mz, l = name.split("-")
+        gen = W.paper_cantilever if kind == "CANT" else W.paper_bridge
+        pr = gen(int(mx), int(my), int(mz), int(l))
+        opts = V.default_options(eps_pbm=1e-5, eps_nwt_min=1e-3, eps_nwt_final=1e-4,
+                                 final_res4=0, eps_stat=0.0, accept_stall=0.0, p_min=1e-8,
+                                 q_min=1e-8, p_min_relative=0, eps_mr0=0.0, max_outer=100)
+        ctx = V.Context.from_problem(pr, precision=V.VTS_FP64, options=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status = V.VTS_OK
+        for k in range(opts.max_outer):
+            try:
+                s = ctx.pbm_iterate()
+            except V.VtsError as e:
+                status = e.status
+                break
+            print(f"{name}: outer {k + 1} ratio {s['ratio']:.2e} newton {s['newton_its']} "
+                  f"minres {s['minres_its']} t {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+            if s["converged"]:
+                break
+        r = ctx.pbm_solve(check=False) if status == V.VTS_OK else None
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = dict(m=pr.m, n=pr.n, seconds=dt, status=int(r["status"] if r else status))
+        if r:
+            res.update(outer=r["outer"], newton=r["newton"], minres=r["minres"],
+                       compliance=r["compliance"])
+        res["paper_pbm_nwt_mr"] = PAPER_COUNTS[name]
+        out[name] = res
+        print(f"{name}: {json.dumps(res)}", file=sys.stderr, flush=True)
+        ctx.close()
+    line = {"metric": METRIC, "value": None, "unit": "see problems", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "paper problems (Section 7) with the paper's parameters"},
+            "problems": out}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def doc_compare(a, torch, W, V):
     """DOC (Algorithm 4, q = 0.5, eps_DOC = 1e-3, bisection tolerance
     1e-4) and PBM on the same workload, both on the GPU."""
@@ -343,6 +400,8 @@ def main():
         return serving(a, torch, W, V)
     if a.doc:
         return doc_compare(a, torch, W, V)
+    if a.paper:
+        return paper_problems(a, torch, W, V)
     pr = W.config(a.workload)
     eps_mr0 = pr.extra.get("eps_mr0")
     opts = V.default_options()

@@ -216,7 +216,7 @@ def paper_bridge(mx, my, mz, l) -> Problem:
     """BRIDGE-mx-my-mz-l of Section 7 (mesh and supports as in the paper;
     load as in `bridge_top`)."""
     s = 2 ** (l - 1)
-    pr = bridge_top(mx * s, my * s, mz * s, l, rho_lo=0.0)
+    pr = bridge_top(mx * s, my * s, mz * s, l, rho_lo=0.0, h=1.0 / s)
     pr.name = f"BRIDGE-{mx}-{my}-{mz}-{l}"
     return pr
 
