@@ -112,3 +112,19 @@ def test_stored_benchmark_oracle_run_is_certified():
     assert abs(g["compliance_half_fu"] - g["compliance_exact"]) <= 1e-6 * g["compliance_exact"]
     assert g["kkt"] <= 1e-6
     assert abs(g["sum_rho"] - g["V"]) <= 1e-6 * g["V"]
+
+
+def test_paper_parameters_reach_the_paper_accuracy():
+    """With the parameter values of Section 7 (absolute penalty floors 1e-8,
+    eps_PBM = 1e-5) the oracle stops with the gap ratio below 1e-5 and a
+    compliance within that accuracy of the certified optimum."""
+    pr = W.config(0)
+    s = pbm.Solver(pr, pbm.paper_options())
+    st = s.solve()
+    assert s.status == "ok"
+    assert s.log.outer[-1]["ratio"] < 1e-5
+    P = s.P
+    ref = pbm.Solver(pr).solve()
+    lb, ub, rel = kkt.certificate(P.grid, P.Ke, P.f, P.V, P.rho_lo, P.rho_hi, ref.rho, ref.u)
+    c = kkt.compliance(P.grid, P.Ke, kkt.project_feasible(st.rho, P.V, P.rho_lo, P.rho_hi), P.f)
+    assert lb * (1 - 1e-12) <= c <= ub * (1 + 1e-4)
