@@ -103,6 +103,10 @@ typedef struct {
     int32_t max_outer, max_newton, max_minres;
     int32_t final_res4;           /* final Newton also requires the res_4 term */
     int32_t p_min_relative;       /* 1: floors p_min |alpha|, q_min |alpha|; 0: p_min, q_min */
+    int32_t stall_steps;          /* final Newton stops after this many steps without a new best
+                                     criterion below 0.9 x the best (0: never); then the
+                                     accept_stall rule decides (the paper accepts stalled
+                                     near-optimal points, Section 7.2) */
 } vts_options;
 
 typedef struct {

@@ -67,6 +67,7 @@ class Options:
     max_newton: int = 100
     max_minres: int = 500
     final_res4: bool = True                   # final Newton also tests res_4
+    stall_steps: int = 10                     # final Newton: stop after this many steps without progress
 
 
 def p_floor(o: "Options", alpha: float) -> float:
@@ -406,10 +407,14 @@ class Solver:
 
     def newton(self, st: State, eps_nwt: float, final=False):
         """Algorithm 2.  The MINRES tolerance rule of Section 6.2 compares
-        res_PBM of consecutive steps of this call."""
+        res_PBM of consecutive steps of this call.  Status "newton_limit" if
+        max_newton steps do not meet eps_nwt; in the final call also
+        "stalled" once stall_steps steps in a row bring no new best value
+        below 0.9 times the best so far."""
         P, o = self.P, self.opts
         ev = evaluate(P, st)
         self.res_prev = None
+        best, since = np.inf, 0
         for it in range(o.max_newton):
             S = schur_matrix(P, ev)
             rhs = reduced_rhs(P, ev)
@@ -455,6 +460,15 @@ class Solver:
             crit = res + r4 if (final and o.final_res4) else res
             if crit < eps_nwt:
                 break
+            if crit < 0.9 * best:
+                best, since = crit, 0
+            else:
+                since += 1
+            if final and o.stall_steps > 0 and since >= o.stall_steps:
+                self.status = "stalled"
+                return st, ev
+        else:
+            self.status = "newton_limit"
         return st, ev
 
     def solve(self, st: Optional[State] = None):

@@ -486,14 +486,31 @@ vts_status newton(Ctx& c, double eps_nwt, bool final_call, vts_newtonstats* last
     vts_newtonstats ns{};
     int k = 0;
     vts_status st = VTS_OK;
+    double best = HUGE_VAL;
+    int since = 0;
+    bool stalled = false;
     for (k = 0; k < c.opt.max_newton; ++k) {
         st = newton_step(c, &ns, final_call);
         if (st != VTS_OK) break;
         const double crit = (final_call && c.opt.final_res4) ? ns.res_pbm + ns.res4 : ns.res_pbm;
         if (crit < eps_nwt) break;
+        if (crit < 0.9 * best) {
+            best = crit;
+            since = 0;
+        } else {
+            ++since;
+        }
+        if (final_call && c.opt.stall_steps > 0 && since >= c.opt.stall_steps) {
+            stalled = true;
+            break;
+        }
     }
     if (last) *last = ns;
     if (its) *its = k + (st == VTS_OK ? 1 : 0);
+    if (st == VTS_OK && stalled) {
+        c.err = "Newton stalled";
+        return VTS_ENOTCONV;
+    }
     if (st == VTS_OK && k >= c.opt.max_newton) {
         c.err = "Newton iteration limit";
         return VTS_ENOTCONV;
@@ -779,6 +796,7 @@ void vts_default_options(vts_options* o) {
     o->max_minres = 500;
     o->final_res4 = 1;
     o->p_min_relative = 1;
+    o->stall_steps = 10;
 }
 
 vts_status vts_create(const vts_problem* pr, const vts_options* opt, void* stream, vts_ctx** out) {

@@ -51,7 +51,8 @@ class Options_t(C.Structure):
                 ("eps_mr_min", C.c_double), ("armijo_c1", C.c_double),
                 ("armijo_min", C.c_double), ("max_outer", C.c_int32),
                 ("max_newton", C.c_int32), ("max_minres", C.c_int32),
-                ("final_res4", C.c_int32), ("p_min_relative", C.c_int32)]
+                ("final_res4", C.c_int32), ("p_min_relative", C.c_int32),
+                ("stall_steps", C.c_int32)]
 
 
 class LinStats_t(C.Structure):

@@ -38,6 +38,7 @@ def test_default_options_match_oracle_defaults():
         assert getattr(o, k) == pytest.approx(getattr(p, k), rel=0, abs=0), k
     assert bool(o.final_res4) == p.final_res4
     assert bool(o.p_min_relative) == p.p_min_relative
+    assert o.stall_steps == p.stall_steps
 
 
 def test_footprint_grows_with_problem():
