@@ -48,7 +48,7 @@ typedef enum {
     VTS_ENOMEM = 2,       /* device allocation failed */
     VTS_EDEVICE = 3,      /* a HIP runtime call failed */
     VTS_ESTATE = 4,       /* call out of order (e.g. apply_S before newton_setup) */
-    VTS_ENOTCONV = 5,     /* iteration limit reached */
+    VTS_ENOTCONV = 5,     /* iteration limit reached, or the final Newton stalled */
     VTS_ENONDESCENT = 6,  /* Newton direction not a descent direction / line search stalled */
     VTS_ENONSPD = 7       /* preconditioner or coarse matrix not positive definite */
 } vts_status;
