@@ -19,6 +19,10 @@ Modules
            block Gauss-Seidel, the V-cycle (Section 6.1)
   minres   preconditioned MINRES (Section 6.1)
   kkt      compliance, KKT residual and the duality certificate (Section 2)
+  doc      damped optimality criteria, the comparison method (Section 5,
+           Algorithm 4)
+  ip       primal-dual interior point method, the other comparison method
+           (Section 4, Algorithm 3)
 
 Parity status: every function is pinned by a `-m "not gpu"` test except where
 its docstring says "parity unpinned".

@@ -5,6 +5,12 @@ tridiagonal least-squares problem solved by Givens rotations, and the
 residual-norm estimate phi_bar = ||r_k||_{M^{-1}}.  Stopping test eq. (6.2)
 ||r|| <= eps ||b|| read in that same norm: phi_bar <= eps * beta_1 with
 beta_1 = sqrt(b^T M^{-1} b).
+
+A negative M-norm (r^T M^{-1} r < 0) means that the preconditioner is not
+positive definite in floating point.  By default this raises NotSPD; with
+stop_on_indefinite the iteration ends there and returns the iterate reached
+before that Lanczos step (used by the interior point method, whose systems
+become ill-conditioned enough for the V-cycle to lose definiteness).
 """
 from __future__ import annotations
 
@@ -17,7 +23,7 @@ class NotSPD(RuntimeError):
     pass
 
 
-def minres(A, b, Minv, eps, maxit):
+def minres(A, b, Minv, eps, maxit, stop_on_indefinite=False):
     """Returns (x, iterations, phi_bar/beta_1)."""
     n = b.size
     x = np.zeros(n)
@@ -25,6 +31,8 @@ def minres(A, b, Minv, eps, maxit):
     y = Minv(r1)
     beta1sq = float(r1 @ y)
     if beta1sq < 0:
+        if stop_on_indefinite:
+            return x, 0, 1.0
         raise NotSPD("preconditioner not positive definite")
     if beta1sq == 0:
         return x, 0, 0.0
@@ -50,6 +58,8 @@ def minres(A, b, Minv, eps, maxit):
         beta_old = beta
         bsq = float(r2 @ y)
         if bsq < 0:
+            if stop_on_indefinite:
+                return x, it, phibar / beta1
             raise NotSPD("preconditioner not positive definite")
         beta = math.sqrt(bsq)
         # apply the previous rotation, then build the new one
