@@ -55,6 +55,9 @@ def parse():
                     help="the damped optimality-criteria method (the paper's comparison "
                          "method) on the same workload and device: time to its stopping "
                          "test, beside PBM's time-to-KKT; prints one JSON line")
+    ap.add_argument("--ip", action="store_true",
+                    help="the primal-dual interior point method (the paper's other comparison "
+                         "method) on the same workload in FP64, beside PBM; one JSON line")
     ap.add_argument("--paper", action="store_true",
                     help="the paper's CANT/BRIDGE-4-2-2-{5,6} problems with the paper's "
                          "parameters (Section 7), iteration counts beside Tables 3 and 4")
@@ -275,6 +278,96 @@ def paper_problems(a, torch, W, V):
     return 0
 
 
+def device_kkt(torch, ctx, pr, lam):
+    """KKT residual of the context's (rho, u) with volume multiplier lam, by
+    its definition: r_eq = ||K(rho)u - f||/||f||, r_vol = |sum rho - V|/V,
+    r_box, and r_stat = max_i |rho_i - clip(rho_i + (e_i - lam)/lam)|/hi_i,
+    with K(rho)u and e_i from vts_apply_K and vts_element_energy."""
+    dev = "cuda"
+    u = ctx.vector("u")
+    rho = ctx.vector("rho")
+    fixed = torch.as_tensor(np.asarray(pr.fixed, dtype=bool), device=dev)
+    f = torch.as_tensor(np.asarray(pr.f, dtype=np.float64), device=dev).masked_fill(fixed, 0.0)
+    m = rho.numel()
+    lo = torch.as_tensor(np.broadcast_to(np.asarray(pr.rho_lo, float), (m,)).copy(), device=dev)
+    hi = torch.as_tensor(np.broadcast_to(np.asarray(pr.rho_hi, float), (m,)).copy(), device=dev)
+    y = torch.empty_like(u)
+    ctx.apply_K(u, y)
+    e = torch.empty_like(rho)
+    ctx.element_energy(u, e)
+    torch.cuda.synchronize()
+    r_eq = float(torch.linalg.norm(y - f) / torch.linalg.norm(f))
+    r_vol = float(abs(rho.sum() - pr.V) / pr.V)
+    r_box = float(torch.clamp(torch.maximum(lo - rho, rho - hi), min=0.0).max() / hi.max())
+    proj = torch.minimum(torch.maximum(rho + (e - lam) / lam, lo), hi)
+    r_stat = float(((rho - proj).abs() / hi).max())
+    return dict(r_eq=r_eq, r_vol=r_vol, r_box=r_box, r_stat=r_stat,
+                kkt=max(r_eq, r_vol, r_box, r_stat))
+
+
+def ip_compare(a, torch, W, V):
+    """The primal-dual interior point method (Algorithm 3, the paper's
+    parameters: eps_IP 1e-5, sigma 0.2, r = s = 1e-2 initially) and PBM on
+    the same workload, both on the GPU in FP64."""
+    pr = W.config(a.workload)
+    eps_mr0 = pr.extra.get("eps_mr0")
+    opts = V.default_options()
+    if eps_mr0:
+        opts.eps_mr0 = eps_mr0
+    ctx = V.Context.from_problem(pr, precision=V.VTS_FP64, options=opts)
+    ctx.reset()
+    ctx.pbm_solve()
+    torch.cuda.synchronize()
+    ctx.reset()
+    t0 = time.perf_counter()
+    r = ctx.pbm_solve()
+    torch.cuda.synchronize()
+    t_pbm = time.perf_counter() - t0
+    k_pbm = device_kkt(torch, ctx, pr, ctx.state_dict()["alpha"])
+    print(f"PBM: {t_pbm:.2f} s, {r['outer']} outer, {r['newton']} Newton, {r['minres']} MINRES",
+          file=sys.stderr, flush=True)
+    # IP iterations one call at a time, so that progress is visible
+    t0 = time.perf_counter()
+    ctx.ip_init()
+    its, mr, status, hist = 0, 0, V.VTS_ENOTCONV, []
+    s = {}
+    for k in range(300):
+        s = ctx.ip_step(check=False)
+        its, mr = k + 1, mr + s["minres_its"]
+        hist.append(s["minres_its"])
+        print(f"IP iteration {its}: minres {s['minres_its']} gap ratio {s['gap_ratio']:.2e} "
+              f"res_IP {s['res_ip']:.2e} eps_MR {s['eps_mr']:.1e}", file=sys.stderr, flush=True)
+        if s["status"] != V.VTS_OK:
+            status = s["status"]
+            break
+        if s["converged"]:
+            status = V.VTS_OK
+            break
+    torch.cuda.synchronize()
+    t_ip = time.perf_counter() - t0
+    k_ip = device_kkt(torch, ctx, pr, -ctx.state_dict()["alpha"])
+    line = {
+        "metric": METRIC, "value": 1.0 / t_ip, "unit": "IP solves/s (eps_IP 1e-5)",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": t_ip * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": pr.name, "method": "primal-dual IP (Algorithm 3)",
+                   "eps_ip": 1e-5, "sigma": 0.2, "max_minres": 3000},
+        "ip": {"seconds": t_ip, "iterations": its, "minres": mr, "status": status,
+               "compliance": s.get("compliance"), "gap_ratio": s.get("gap_ratio"),
+               "res_ip": s.get("res_ip"), "kkt": k_ip["kkt"], "kkt_terms": k_ip,
+               "minres_per_iteration": hist},
+        "pbm": {"seconds": t_pbm, "outer": r["outer"], "newton": r["newton"],
+                "minres": r["minres"], "compliance": r["compliance"], "kkt": k_pbm["kkt"]},
+        "ip_over_pbm_time": t_ip / t_pbm,
+        "ip_compliance_excess": ((s["compliance"] - r["compliance"]) / r["compliance"]
+                                 if s.get("compliance") else None),
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
+
+
 def doc_compare(a, torch, W, V):
     """DOC (Algorithm 4, q = 0.5, eps_DOC = 1e-3, bisection tolerance
     1e-4) and PBM on the same workload, both on the GPU."""
@@ -400,6 +493,8 @@ def main():
         return serving(a, torch, W, V)
     if a.doc:
         return doc_compare(a, torch, W, V)
+    if a.ip:
+        return ip_compare(a, torch, W, V)
     if a.paper:
         return paper_problems(a, torch, W, V)
     pr = W.config(a.workload)
@@ -429,11 +524,9 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / a.steps
     last = results[-1]
 
-    # KKT of the last result by the definition (oracle checker, host)
-    from oracle import pbm as opbm, kkt
-    d = ctx.state_dict()
-    P = opbm.VTS(pr)
-    k = kkt.kkt_residual(P.grid, P.Ke, P.f, P.V, P.rho_lo, P.rho_hi, d["rho"], d["u"], d["alpha"])
+    # KKT of the last result by its definition, from the library's own
+    # operators on the device
+    k = device_kkt(torch, ctx, pr, ctx.state_dict()["alpha"])
     gold = os.path.join(ROOT, "tests", "golden", f"oracle_{pr.name}.json")
     c_err = None
     if os.path.exists(gold):

@@ -309,6 +309,64 @@ vts_status vts_doc_step(vts_ctx* ctx, double q, double tau, double eps_doc, doub
 vts_status vts_doc_solve(vts_ctx* ctx, double q, double eps_doc, double eps_mr, int32_t max_iter,
                          vts_docstats* out);
 
+/* ---------------------------------------------------------------------
+ * Primal-dual interior point method (Section 4, Algorithm 3), the paper's
+ * second comparison method, on the same device data.  Variables
+ * (u, alpha, rho, nu_lo, nu_hi) live in the context's state vectors (it
+ * overwrites the PBM state and working data); each iteration solves the
+ * reduced system (eq. S_IP) by the same MINRES with one V-cycle: S_IP has
+ * the structure of the PBM Schur operator with rho' = rho and the weights
+ * W = ((rho - rho_lo)^-1 nu_lo + (rho_hi - rho)^-1 nu_hi)^-1.
+ * Readings: the residual's nu_hi term belongs to res_5; the reduced
+ * right-hand side and the increments are those of the Newton step of the
+ * residual with the Jacobian (eq. gradres); in eq. (Delta_onu) the term
+ * (N_lo - N_hi) rho is (N_lo - N_hi) Delta rho; alpha tends to minus the
+ * volume multiplier, so the gap (2.6) is evaluated at (u, -alpha); the
+ * multiplier step lengths are capped at 1; MINRES stops, keeping its
+ * iterate, if the V-cycle loses definiteness in floating point.
+ * --------------------------------------------------------------------- */
+typedef struct {
+    double eps_ip;                /* stopping tolerance (paper: 1e-5) */
+    double sigma_r, sigma_s;      /* barrier reduction factors (0.2) */
+    double r0, s0;                /* initial barrier parameters (1e-2) */
+    double step_frac;             /* fraction of the step to the boundary (0.9) */
+    double eps_mr0, eps_mr_min;   /* MINRES tolerance rule of Section 6.2 (1e-2, 1e-9) */
+    int32_t max_iter;             /* iterations of Algorithm 3 (300) */
+    int32_t max_minres;           /* MINRES iterations per system (3000) */
+} vts_ip_options;
+
+typedef struct {
+    double gap_ratio;             /* delta(u, -alpha) / (1/2 f^T u) after the step */
+    double res_ip;                /* feasibility measure eq. (ip_res) after the step */
+    double compliance;            /* 1/2 f^T u after the step */
+    double alpha;                 /* after the step (tends to minus the multiplier) */
+    double r, s;                  /* barrier parameters of this iteration's system */
+    double kappa_u, kappa_nu_lo, kappa_nu_hi;  /* step lengths taken */
+    double eps_mr;                /* MINRES tolerance of this iteration's solve */
+    int32_t minres_its;           /* this iteration (vts_ip_solve: all iterations) */
+    int32_t converged;            /* the stopping test of Algorithm 3 holds */
+    int32_t iterations;           /* iterations taken (vts_ip_solve) */
+} vts_ipstats;
+
+void vts_ip_default_options(vts_ip_options* o);
+
+/* Sets the initial point stated before Algorithm 3 (u = 0, alpha = 1,
+ * rho = V/m, nu_lo = nu_hi = e), the barrier parameters r0, s0 and their
+ * first shifted update, and the MINRES tolerance.  opt NULL: defaults.
+ * VTS_EINVAL for options out of range. */
+vts_status vts_ip_init(vts_ctx* ctx, const vts_ip_options* opt);
+
+/* One iteration of Algorithm 3 from the context's current point: reduced
+ * system, MINRES, increments, barrier shift, step lengths, update, gap,
+ * objective and res_IP, the next shifted barrier parameters and the MINRES
+ * tolerance rule.  VTS_ESTATE before vts_ip_init; VTS_ENOTCONV if rounding
+ * put a variable on its bound (the iterate is kept, the method cannot go on). */
+vts_status vts_ip_step(vts_ctx* ctx, vts_ipstats* stats);
+
+/* vts_ip_init followed by vts_ip_step until the stopping test holds
+ * (VTS_OK) or max_iter iterations (VTS_ENOTCONV).  stats may be NULL. */
+vts_status vts_ip_solve(vts_ctx* ctx, const vts_ip_options* opt, vts_ipstats* stats);
+
 /* Advances each of the k contexts by one outer iteration of Algorithm 1
  * (as vts_pbm_iterate), their device work overlapping: one host thread per
  * context, each driving its own context's stream (the contexts should be

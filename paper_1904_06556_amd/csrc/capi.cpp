@@ -341,8 +341,12 @@ void precond(Ctx& c, const double* r, double* z) {
 
 // Preconditioned MINRES (Paige-Saunders), x0 = 0: Lanczos in the M-inner
 // product with M^{-1} one V-cycle, Givens QR of the tridiagonal, stop when the
-// M^{-1}-norm estimate phi_bar of the residual is <= eps * beta_1.
-vts_status minres(Ctx& c, double eps, vts_linstats* out) {
+// M^{-1}-norm estimate phi_bar of the residual is <= eps * beta_1.  A
+// negative M^{-1}-norm means the V-cycle is not positive definite in floating
+// point: VTS_ENONSPD, or with stop_indef the iterate reached so far is kept.
+vts_status minres(Ctx& c, double eps, vts_linstats* out, int maxit = -1,
+                  bool stop_indef = false) {
+    if (maxit < 0) maxit = c.opt.max_minres;
     const int64_t n = c.ndof + 1;
     double *x = c.mv[0], *r1 = c.mv[1], *r2 = c.mv[2], *y = c.mv[3], *v = c.mv[4];
     double* wb[3] = {c.mv[5], c.mv[6], c.mv[7]};   // w, w1(k-2), w2(k-1) rotate
@@ -353,12 +357,13 @@ vts_status minres(Ctx& c, double eps, vts_linstats* out) {
     vts_status st = sync_red(c);
     if (st != VTS_OK) return st;
     const double b1sq = c.red_host[SL_DOT];
-    if (!(b1sq >= 0) || !std::isfinite(b1sq)) {
+    const bool indef0 = stop_indef && b1sq < 0;
+    if (!indef0 && (!(b1sq >= 0) || !std::isfinite(b1sq))) {
         c.err = "MINRES: preconditioner not positive definite";
         return VTS_ENONSPD;
     }
     int it = 0;
-    double rel = 0.0;
+    double rel = indef0 ? 1.0 : 0.0;
     if (b1sq > 0) {
         const double beta1 = std::sqrt(b1sq);
         double beta = beta1, beta_old = 0.0;
@@ -368,7 +373,7 @@ vts_status minres(Ctx& c, double eps, vts_linstats* out) {
         launch_fill(c, wb[2], 0.0, n);
         int iw = 0, iw1 = 1, iw2 = 2;                 // buffers holding w_k-1 ... as in the recurrence
         double cs = -1.0, sn = 0.0, dbar = 0.0, eps_l = 0.0, phibar = beta1;
-        for (it = 1; it <= c.opt.max_minres; ++it) {
+        for (it = 1; it <= maxit; ++it) {
             launch_scale(c, v, y, 1.0 / beta, n);
             launch_apply_S(c, v, y);
             if (it >= 2) launch_axpy(c, y, -beta / beta_old, r1, n);
@@ -383,6 +388,10 @@ vts_status minres(Ctx& c, double eps, vts_linstats* out) {
             if ((st = sync_red(c)) != VTS_OK) return st;
             const double alpha = c.red_host[SL_MRALPHA];
             const double bsq = c.red_host[SL_DOT];
+            if (stop_indef && bsq < 0) {
+                rel = phibar / beta1;
+                break;
+            }
             if (!(bsq >= 0) || !std::isfinite(bsq)) {
                 c.err = "MINRES: preconditioner not positive definite";
                 return VTS_ENONSPD;
@@ -409,7 +418,7 @@ vts_status minres(Ctx& c, double eps, vts_linstats* out) {
             rel = phibar / beta1;
             if (phibar <= eps * beta1) break;
         }
-        if (it > c.opt.max_minres) it = c.opt.max_minres;
+        if (it > maxit) it = maxit;
     }
     HIPCHK(hipMemcpyAsync(c.dy, x, n * sizeof(double), hipMemcpyDeviceToDevice, c.s));
     // keep the rotated buffers consistent for the next call
@@ -556,6 +565,145 @@ vts_status pbm_iterate(Ctx& c, vts_pbmstats* out) {
     c.eval_valid = false;
     c.setup_valid = false;
     HIPCHK(hipGetLastError());
+    return VTS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// primal-dual interior point method (Section 4, Algorithm 3)
+// ---------------------------------------------------------------------------
+// evaluation at the current point with the current barrier parameters: the
+// reduced system's weights and right-hand side (alpha row negated, see
+// kernels.hip), the gap and feasibility sums, the complementarity measures
+vts_status ip_evaluate(Ctx& c) {
+    launch_ip_eval(c, c.ip.r, c.ip.s);
+    launch_grad(c);                           // res_1 = K(rho) u - f, rhs_u, ||res_1||^2
+    launch_dot(c, c.f, c.u, c.ndof, SL_SUM_R1);
+    vts_status st = sync_red(c);
+    if (st != VTS_OK) return st;
+    const double* q = c.red_host + kIpEvalSlot;
+    c.ip.sum_rho = q[0];
+    c.sum_z = q[1];
+    c.sum_w = q[2];
+    c.ip.n_res3 = std::sqrt(q[3]);
+    c.ip.gap_sum = q[4];
+    c.ip.cl = q[5];
+    c.ip.ch = q[6];
+    c.ip.n_nl = std::sqrt(q[7]);
+    c.ip.n_nh = std::sqrt(q[8]);
+    c.ip.dmax = q[9];
+    c.ip.viol = q[10];
+    c.n_g1 = std::sqrt(c.red_host[SL_G1SQ]);
+    c.ip.fu = c.red_host[SL_SUM_R1];
+    c.g2 = c.V - c.ip.sum_rho;
+    launch_set(c, c.rhs + c.ndof, -c.g2 - c.sum_z);
+    // the PBM evaluation buffers now hold the IP system
+    c.eval_valid = false;
+    c.setup_valid = false;
+    if (!(c.ip.viol < 0)) {
+        c.err = "interior point iterate reached a bound";
+        return VTS_ENOTCONV;
+    }
+    if (!std::isfinite(c.n_g1) || !std::isfinite(c.sum_w) || !std::isfinite(c.ip.n_res3)) {
+        c.err = "non-finite value in the interior point residual";
+        return VTS_EINVAL;
+    }
+    return VTS_OK;
+}
+
+vts_status ip_init(Ctx& c, const vts_ip_options* opt) {
+    vts_ip_options o;
+    vts_ip_default_options(&o);
+    if (opt) o = *opt;
+    if (!(o.eps_ip > 0) || !(o.sigma_r > 0 && o.sigma_r < 1) || !(o.sigma_s > 0 && o.sigma_s < 1) ||
+        !(o.r0 > 0) || !(o.s0 > 0) || !(o.step_frac > 0 && o.step_frac < 1) || !(o.eps_mr0 > 0) ||
+        !(o.eps_mr_min > 0) || o.max_iter < 1 || o.max_minres < 1) {
+        c.err = "invalid interior point options";
+        return VTS_EINVAL;
+    }
+    c.ip = Ctx::Ip{};
+    c.ip.o = o;
+    launch_init_state(c);
+    launch_round_rho(c);
+    c.alpha = 1.0;
+    c.ip.r = o.r0;
+    c.ip.s = o.s0;
+    c.ip.eps_mr = o.eps_mr0;
+    c.converged = false;
+    vts_status st = ip_evaluate(c);
+    if (st != VTS_OK) return st;
+    // the first shifted update, from the initial point
+    c.ip.r_plus = o.sigma_r * c.ip.cl / (double)c.m;
+    c.ip.s_plus = o.sigma_s * c.ip.ch / (double)c.m;
+    c.ip.ready = true;
+    return VTS_OK;
+}
+
+vts_status ip_step(Ctx& c, vts_ipstats* out) {
+    if (!c.ip.ready) {
+        c.err = "vts_ip_step before vts_ip_init";
+        return VTS_ESTATE;
+    }
+    const vts_ip_options& o = c.ip.o;
+    // the system at the current point (the same values as the evaluation
+    // that ended the previous iteration; repeated because other calls on the
+    // context may have used the evaluation buffers since)
+    vts_status st = ip_evaluate(c);
+    if (st != VTS_OK) return st;
+    if ((st = build_mg(c)) != VTS_OK) return st;
+    vts_linstats ls{0, 0.0};
+    const double eps_mr = c.ip.eps_mr;
+    if ((st = minres(c, eps_mr, &ls, o.max_minres, true)) != VTS_OK) return st;
+    const double r_used = c.ip.r, s_used = c.ip.s;
+    launch_ip_dir(c, r_used, s_used);
+    launch_copy1(c, c.dy + c.ndof, c.red + SL_AUX);
+    if ((st = sync_red(c)) != VTS_OK) return st;
+    const double dalpha = -c.red_host[SL_AUX];
+    // step lengths: maxima of -(step to the boundary), -DBL_MAX where no
+    // component moves towards a bound
+    const double k_u = std::min(o.step_frac * -c.red_host[SL_SUM_R1], 1.0);
+    const double k_l = std::min(o.step_frac * -c.red_host[SL_SUM_R1 + 1], 1.0);
+    const double k_h = std::min(o.step_frac * -c.red_host[SL_SUM_R1 + 2], 1.0);
+    // the barrier shift: this iteration's update values become current
+    c.ip.r = c.ip.r_plus;
+    c.ip.s = c.ip.s_plus;
+    launch_ip_update(c, k_u, k_l, k_h);
+    c.alpha += dalpha;
+    HIPCHK(hipGetLastError());
+    st = ip_evaluate(c);
+    c.newton_total += 1;
+    if (out) {
+        *out = vts_ipstats{};
+        out->r = r_used;
+        out->s = s_used;
+        out->kappa_u = k_u;
+        out->kappa_nu_lo = k_l;
+        out->kappa_nu_hi = k_h;
+        out->eps_mr = eps_mr;
+        out->minres_its = ls.iterations;
+        out->alpha = c.alpha;
+        out->iterations = 1;
+    }
+    if (st != VTS_OK) return st;
+    const double m = (double)c.m;
+    const double obj = 0.5 * c.ip.fu;
+    const double gap = -0.5 * c.ip.fu + (-c.alpha) * c.V - c.ip.gap_sum;
+    const double res_ip = c.n_g1 / c.norm_f + std::fabs(c.ip.sum_rho - c.V) / c.V +
+                          c.ip.n_res3 / (c.ip.n_nl + c.ip.n_nh) +
+                          std::fabs(c.ip.cl - m * c.ip.r) / m + std::fabs(c.ip.ch - m * c.ip.s) / m;
+    const double ratio = obj != 0.0 ? gap / obj : HUGE_VAL;
+    const bool conv = (o.eps_ip > ratio && ratio > -0.1 * o.eps_ip) && res_ip < 10.0 * o.eps_ip;
+    c.converged = conv;
+    // shifted barrier update values and the MINRES tolerance rule
+    c.ip.r_plus = o.sigma_r * c.ip.cl / m;
+    c.ip.s_plus = o.sigma_s * c.ip.ch / m;
+    const double cand = std::max(100.0 * c.ip.dmax, o.eps_mr_min);
+    if (cand < c.ip.eps_mr) c.ip.eps_mr = cand;
+    if (out) {
+        out->gap_ratio = ratio;
+        out->res_ip = res_ip;
+        out->compliance = obj;
+        out->converged = conv ? 1 : 0;
+    }
     return VTS_OK;
 }
 
@@ -1039,6 +1187,49 @@ vts_status vts_doc_solve(vts_ctx* cp, double q, double eps_doc, double eps_mr, i
     }
     s.minres_its = minres;
     if (out) *out = s;
+    return s.converged ? VTS_OK : VTS_ENOTCONV;
+}
+
+void vts_ip_default_options(vts_ip_options* o) {
+    if (!o) return;
+    o->eps_ip = 1e-5;
+    o->sigma_r = 0.2;
+    o->sigma_s = 0.2;
+    o->r0 = 1e-2;
+    o->s0 = 1e-2;
+    o->step_frac = 0.9;
+    o->eps_mr0 = 1e-2;
+    o->eps_mr_min = 1e-9;
+    o->max_iter = 300;
+    o->max_minres = 3000;
+}
+
+vts_status vts_ip_init(vts_ctx* cp, const vts_ip_options* opt) {
+    if (!cp) return VTS_EINVAL;
+    return ip_init(*cp, opt);
+}
+
+vts_status vts_ip_step(vts_ctx* cp, vts_ipstats* stats) {
+    if (!cp) return VTS_EINVAL;
+    return ip_step(*cp, stats);
+}
+
+vts_status vts_ip_solve(vts_ctx* cp, const vts_ip_options* opt, vts_ipstats* stats) {
+    if (!cp) return VTS_EINVAL;
+    Ctx& c = *cp;
+    vts_status st = ip_init(c, opt);
+    if (st != VTS_OK) return st;
+    vts_ipstats s{};
+    int32_t minres = 0, k = 0;
+    for (k = 0; k < c.ip.o.max_iter; ++k) {
+        st = ip_step(c, &s);
+        minres += s.minres_its;
+        if (st != VTS_OK || s.converged) break;
+    }
+    s.iterations = std::min(k + 1, c.ip.o.max_iter);
+    s.minres_its = minres;
+    if (stats) *stats = s;
+    if (st != VTS_OK) return st;
     return s.converged ? VTS_OK : VTS_ENOTCONV;
 }
 

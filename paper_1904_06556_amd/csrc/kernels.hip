@@ -790,6 +790,164 @@ void launch_doc_candidate(Ctx& c, double q, double alpha, double* out) {
                        (int)SL_STAT, 1u, c.red);
 }
 
+// ---------------------------------------------------------------------------
+// primal-dual interior point method (Section 4, Algorithm 3)
+//
+// The reduced system (eq. S_IP) is solved in the form of the PBM Schur
+// operator with rho' = rho, w = W and the alpha unknown negated
+// (beta = -dalpha): that turns the coupling vector [b_i; 1] of S_IP into the
+// [b_i; -1] of the S-apply and the V-cycle.  With dlo = rho - rho_lo,
+// dhi = rho_hi - rho:
+//   W = (nu_lo/dlo + nu_hi/dhi)^-1 = dlo dhi / (nu_lo dhi + nu_hi dlo)
+//   X = res_3 - res_4/dlo + res_5/dhi = e + alpha + r/dlo - s/dhi
+//   rhs = [-res_1 - sum W X b_i ; res_2 + sum W X]    (alpha row negated)
+// so the PBM right-hand side kernel applies with z = -W X.
+// ---------------------------------------------------------------------------
+struct IpEvalArgs {
+    int nx, ny, nz;
+    double alpha, r, s;
+    const double *Ke, *u, *nlo, *nhi, *rho, *rlo, *rhi;
+    const uint8_t* fixed;
+    double *e, *be, *r1, *w, *zc, *g3, *g4, *partials;
+};
+
+// reduction (kIpEvalQ quantities from slot kIpEvalSlot): sums of rho, z, W,
+// res_3^2, the gap term, nu_lo dlo, nu_hi dhi, nu_lo^2, nu_hi^2; maxima of
+// the complementarity products and of max(-dlo, -dhi, -nu_lo, -nu_hi)
+// (>= 0 once a variable has reached its bound)
+__global__ void __launch_bounds__(kThreads) k_ip_eval(IpEvalArgs a) {
+    const int64_t m = (int64_t)a.nx * a.ny * a.nz;
+    double acc[kIpEvalQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0, -DBL_MAX, -DBL_MAX};
+    const double lam = -a.alpha;
+    for (int64_t e = gid(); e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        elem_ijk(e, a.nx, a.ny, i, j, k);
+        double ue[24];
+        gather_elem(a.u, a.fixed, i, j, k, a.nx + 1, a.ny + 1, ue);
+        double en = 0.0;
+        for (int r = 0; r < 24; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < 24; ++q) s += a.Ke[r * 24 + q] * ue[q];
+            a.be[r * m + e] = s;
+            en += ue[r] * s;
+        }
+        en *= 0.5;
+        a.e[e] = en;
+        const double rh = a.rho[e], nl = a.nlo[e], nh = a.nhi[e];
+        const double lo = a.rlo[e], hi = a.rhi[e];
+        const double dlo = rh - lo, dhi = hi - rh;
+        const double res3 = en + a.alpha + nl - nh;
+        const double W = dlo * dhi / (nl * dhi + nh * dlo);
+        const double X = en + a.alpha + a.r / dlo - a.s / dhi;
+        const double z = -W * X;
+        a.r1[e] = rh;
+        a.w[e] = W;
+        a.zc[e] = z;
+        a.g3[e] = res3;
+        a.g4[e] = X;
+        const double gl = lam - en;                       // gap (2.6) at lambda = -alpha
+        const double cl = nl * dlo, ch = nh * dhi;
+        acc[0] += rh;
+        acc[1] += z;
+        acc[2] += W;
+        acc[3] += res3 * res3;
+        acc[4] += gl >= 0.0 ? lo * gl : hi * gl;
+        acc[5] += cl;
+        acc[6] += ch;
+        acc[7] += nl * nl;
+        acc[8] += nh * nh;
+        acc[9] = fmax(acc[9], fmax(fabs(cl), fabs(ch)));
+        acc[10] = fmax(acc[10], fmax(fmax(-dlo, -dhi), fmax(-nl, -nh)));
+    }
+    block_sum_store<kIpEvalQ>(acc, a.partials, kIpEvalSlot, kIpEvalMax);
+}
+
+void launch_ip_eval(Ctx& c, double r, double s) {
+    IpEvalArgs a{c.nx, c.ny, c.nz, c.alpha, r, s, c.Ke, c.u, c.nlo, c.nhi, c.rho, c.rlo, c.rhi,
+                 c.fixed, c.e, c.be, c.r1, c.w, c.zc, c.g3, c.g4, c.partials};
+    const int g = red_grid(c.m);
+    hipLaunchKernelGGL(k_ip_eval, dim3(g), dim3(kThreads), 0, c.s, a);
+    hipLaunchKernelGGL(k_finalize, dim3(kIpEvalQ), dim3(kThreads), 0, c.s, c.partials, g,
+                       kIpEvalSlot, kIpEvalMax, c.red);
+}
+
+// Increments from the solution dy = [du; -dalpha] of the reduced system:
+//   t = b_i^T du + dalpha,  drho = W (t + X)                      (eq. Delta_rho)
+//   dnu_hi = (dlo t - (nu_lo - nu_hi) drho - (res_4 + res_5 - dlo res_3))
+//            / (rho_hi - rho_lo)                                    (eq. Delta_onu)
+//   dnu_lo = dnu_hi - t - res_3                                     (eq. Delta_unu)
+// and the partial maxima of -(step to the boundary) for rho, nu_lo, nu_hi.
+struct IpDirArgs {
+    int nx, ny, nz;
+    int64_t ndof;
+    double r, s;
+    const double *be, *dy, *w, *g3, *g4, *rho, *nlo, *nhi, *rlo, *rhi;
+    const uint8_t* fixed;
+    double *drho, *dnl, *dnh, *partials;
+};
+
+__global__ void __launch_bounds__(kThreads) k_ip_dir(IpDirArgs a) {
+    const int64_t m = (int64_t)a.nx * a.ny * a.nz;
+    const double dalpha = -a.dy[a.ndof];
+    double acc[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    for (int64_t e = gid(); e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        elem_ijk(e, a.nx, a.ny, i, j, k);
+        double de[24];
+        gather_elem(a.dy, a.fixed, i, j, k, a.nx + 1, a.ny + 1, de);
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < 24; ++q) t += a.be[q * m + e] * de[q];
+        t += dalpha;
+        const double rh = a.rho[e], nl = a.nlo[e], nh = a.nhi[e];
+        const double lo = a.rlo[e], hi = a.rhi[e];
+        const double dlo = rh - lo, dhi = hi - rh;
+        const double res3 = a.g3[e];
+        const double res4 = nl * dlo - a.r, res5 = nh * dhi - a.s;
+        const double dr = a.w[e] * (t + a.g4[e]);
+        const double dh = (dlo * t - (nl - nh) * dr - (res4 + res5 - dlo * res3)) / (hi - lo);
+        const double dl = dh - t - res3;
+        a.drho[e] = dr;
+        a.dnl[e] = dl;
+        a.dnh[e] = dh;
+        if (dr > 0.0) acc[0] = fmax(acc[0], -(dhi / dr));
+        if (dr < 0.0) acc[0] = fmax(acc[0], -((lo - rh) / dr));
+        if (dl < 0.0) acc[1] = fmax(acc[1], -(-nl / dl));
+        if (dh < 0.0) acc[2] = fmax(acc[2], -(-nh / dh));
+    }
+    block_sum_store<3>(acc, a.partials, SL_SUM_R1, 0x7u);
+}
+
+void launch_ip_dir(Ctx& c, double r, double s) {
+    IpDirArgs a{c.nx, c.ny, c.nz, c.ndof, r, s, c.be, c.dy, c.w, c.g3, c.g4, c.rho, c.nlo,
+                c.nhi, c.rlo, c.rhi, c.fixed, c.c1, c.dnl, c.dnh, c.partials};
+    const int g = red_grid(c.m);
+    hipLaunchKernelGGL(k_ip_dir, dim3(g), dim3(kThreads), 0, c.s, a);
+    hipLaunchKernelGGL(k_finalize, dim3(3), dim3(kThreads), 0, c.s, c.partials, g,
+                       (int)SL_SUM_R1, 0x7u, c.red);
+}
+
+__global__ void k_ip_update(int64_t ndof, int64_t m, double ku, double kl, double kh,
+                            double* __restrict__ u, const double* __restrict__ dy,
+                            double* __restrict__ rho, const double* __restrict__ drho,
+                            double* __restrict__ nlo, const double* __restrict__ dnl,
+                            double* __restrict__ nhi, const double* __restrict__ dnh) {
+    const int64_t t = gid();
+    if (t < ndof) u[t] += ku * dy[t];
+    if (t < m) {
+        rho[t] += ku * drho[t];
+        nlo[t] += kl * dnl[t];
+        nhi[t] += kh * dnh[t];
+    }
+}
+
+void launch_ip_update(Ctx& c, double ku, double kl, double kh) {
+    const int64_t n = c.ndof > c.m ? c.ndof : c.m;
+    hipLaunchKernelGGL(k_ip_update, dim3(grid1d(n)), dim3(kThreads), 0, c.s, c.ndof, c.m, ku, kl,
+                       kh, c.u, c.dy, c.rho, c.c1, c.nlo, c.dnl, c.nhi, c.dnh);
+}
+
 // w = (v - eps_old w1 - delta w2) / gamma ; x += phi w
 __global__ void k_minres_w(double* __restrict__ w, const double* __restrict__ v,
                            const double* __restrict__ w1, const double* __restrict__ w2,

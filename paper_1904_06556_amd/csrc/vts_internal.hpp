@@ -137,6 +137,16 @@ struct Ctx {
     bool converged = false;
     std::string err;
 
+    // interior point method (Algorithm 3): options, barrier parameters and
+    // the scalars of the last evaluation
+    struct Ip {
+        vts_ip_options o{};
+        double r = 0, s = 0, r_plus = 0, s_plus = 0, eps_mr = 0;
+        double sum_rho = 0, n_res3 = 0, gap_sum = 0, cl = 0, ch = 0, n_nl = 0, n_nh = 0;
+        double dmax = 0, viol = 0, fu = 0;
+        bool ready = false;
+    } ip;
+
     std::vector<void*> allocs;   // hipMalloc'd buffers (contexts without an arena)
     char* arena = nullptr;       // caller-owned device range (server slots), or null
     size_t arena_size = 0, arena_used = 0;
@@ -202,6 +212,10 @@ void launch_axpy_red(Ctx& c, double* y, int slot, double div, const double* x, i
 void launch_doc_setup(Ctx& c);                               // r1 = rho, w = 0, rhs = [f; 0]
 void launch_doc_volume(Ctx& c, double q, double alpha);     // sum rho+(alpha) -> red[SL_SUM_RHO]
 void launch_doc_candidate(Ctx& c, double q, double alpha, double* out); // max |drho| -> red[SL_STAT]
+// primal-dual interior point method (Algorithm 3)
+void launch_ip_eval(Ctx& c, double r, double s);     // e, be, W, z, res_3, X; sums -> red[6..16]
+void launch_ip_dir(Ctx& c, double r, double s);      // drho (c1), dnl, dnh; step maxima -> red[0..2]
+void launch_ip_update(Ctx& c, double ku, double kl, double kh);
 void launch_minres_w(Ctx& c, double* w, const double* v, const double* w1, const double* w2,
                      double eps_old, double delta, double inv_gamma, double* x, double phi,
                      int64_t n);
@@ -225,6 +239,14 @@ enum Slot {
     SL_DOT = 6, SL_SLOPE_NU = 7, SL_LS = 8, SL_GAP = 9, SL_NLO = 10, SL_NHI = 11,
     SL_STAT = 12, SL_SUM_RHO = 13, SL_WT = 14, SL_AUX = 15, SL_MRALPHA = 16
 };
+
+// the interior point evaluation's reduction: kIpEvalQ quantities in slots
+// kIpEvalSlot.. (sums of rho, z, W, res_3^2, the gap term, nu_lo dlo,
+// nu_hi dhi, nu_lo^2, nu_hi^2; maxima of the complementarity products and of
+// the bound violation)
+constexpr int kIpEvalQ = 11;
+constexpr int kIpEvalSlot = SL_DOT;
+constexpr uint32_t kIpEvalMax = 0x600u;
 
 }  // namespace vts
 

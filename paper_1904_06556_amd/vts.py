@@ -82,6 +82,21 @@ class DocStats_t(C.Structure):
                 ("minres_its", C.c_int32), ("converged", C.c_int32), ("iterations", C.c_int32)]
 
 
+class IpOptions_t(C.Structure):
+    _fields_ = [("eps_ip", C.c_double), ("sigma_r", C.c_double), ("sigma_s", C.c_double),
+                ("r0", C.c_double), ("s0", C.c_double), ("step_frac", C.c_double),
+                ("eps_mr0", C.c_double), ("eps_mr_min", C.c_double),
+                ("max_iter", C.c_int32), ("max_minres", C.c_int32)]
+
+
+class IpStats_t(C.Structure):
+    _fields_ = [("gap_ratio", C.c_double), ("res_ip", C.c_double), ("compliance", C.c_double),
+                ("alpha", C.c_double), ("r", C.c_double), ("s", C.c_double),
+                ("kappa_u", C.c_double), ("kappa_nu_lo", C.c_double),
+                ("kappa_nu_hi", C.c_double), ("eps_mr", C.c_double),
+                ("minres_its", C.c_int32), ("converged", C.c_int32), ("iterations", C.c_int32)]
+
+
 class RequestInfo_t(C.Structure):
     _fields_ = [("id", C.c_int64), ("status", C.c_int32), ("outer", C.c_int32),
                 ("newton", C.c_int32), ("minres", C.c_int32), ("compliance", C.c_double),
@@ -129,6 +144,10 @@ SIGNATURES = {
                                C.POINTER(DocStats_t)]),
     "vts_doc_solve": (C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_int32,
                                 C.POINTER(DocStats_t)]),
+    "vts_ip_default_options": (None, [C.POINTER(IpOptions_t)]),
+    "vts_ip_init": (C.c_int, [_P, C.POINTER(IpOptions_t)]),
+    "vts_ip_step": (C.c_int, [_P, C.POINTER(IpStats_t)]),
+    "vts_ip_solve": (C.c_int, [_P, C.POINTER(IpOptions_t), C.POINTER(IpStats_t)]),
     "vts_server_create": (C.c_int, [C.c_int32, C.c_size_t, C.POINTER(_P)]),
     "vts_server_submit": (C.c_int, [_P, C.POINTER(Problem_t), C.POINTER(Options_t),
                                     C.POINTER(C.c_int64)]),
@@ -341,6 +360,32 @@ class Context:
     def doc_solve(self, q=0.5, eps_doc=1e-3, eps_mr=1e-6, max_iter=1000, check=True):
         s = DocStats_t()
         st = lib().vts_doc_solve(self.h, q, eps_doc, eps_mr, max_iter, C.byref(s))
+        if check:
+            self._check(st)
+        return dict(_struct_dict(s), status=st)
+
+    # --- primal-dual interior point method (Algorithm 3) -----------------
+    @staticmethod
+    def ip_options(**kw):
+        o = IpOptions_t()
+        lib().vts_ip_default_options(C.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def ip_init(self, **kw):
+        self._check(lib().vts_ip_init(self.h, C.byref(self.ip_options(**kw))))
+
+    def ip_step(self, check=True):
+        s = IpStats_t()
+        st = lib().vts_ip_step(self.h, C.byref(s))
+        if check:
+            self._check(st)
+        return dict(_struct_dict(s), status=st)
+
+    def ip_solve(self, check=True, **kw):
+        s = IpStats_t()
+        st = lib().vts_ip_solve(self.h, C.byref(self.ip_options(**kw)), C.byref(s))
         if check:
             self._check(st)
         return dict(_struct_dict(s), status=st)
