@@ -60,7 +60,8 @@ def parse():
                          "method) on the same workload in FP64, beside PBM; one JSON line")
     ap.add_argument("--paper", action="store_true",
                     help="the paper's CANT/BRIDGE-4-2-2-{5,6} problems with the paper's "
-                         "parameters (Section 7), iteration counts beside Tables 3 and 4")
+                         "parameters (Section 7), iteration counts beside Tables 3 and 4 "
+                         "(with --ip: the interior point method)")
     ap.add_argument("--requests", type=int, default=20, help="requests per rate (--serve)")
     ap.add_argument("--slots", type=int, default=4, help="concurrent requests (--serve)")
     ap.add_argument("--pool-gb", type=float, default=16.0, help="device pool (--serve)")
@@ -228,6 +229,55 @@ def kernels_only(a, torch, W, V):
 # (Section 7.2) for these problems, with the paper's parameters
 PAPER_COUNTS = {"CANT-4-2-2-5": (15, 57, 153), "CANT-4-2-2-6": (17, 59, 118),
                 "BRIDGE-4-2-2-5": (14, 45, 155), "BRIDGE-4-2-2-6": (15, 57, 317)}
+
+
+# Tables 3 and 4, IP columns (IP iterations, MINRES), rho_lo = 1e-3
+PAPER_IP_COUNTS = {"CANT-4-2-2-5": (28, 570), "CANT-4-2-2-6": (42, 2465),
+                   "BRIDGE-4-2-2-5": (25, 590), "BRIDGE-4-2-2-6": (50, 2965)}
+
+
+def paper_problems_ip(a, torch, W, V):
+    """The interior point method with the paper's parameters (Algorithm 3:
+    eps_IP = 1e-5, sigma = 0.2, r = s = 1e-2 initially; rho_lo = 1e-3 as in
+    Section 7 for IP) on the CANT and BRIDGE 4-2-2-l problems, FP64."""
+    out = {}
+    for name in PAPER_IP_COUNTS:
+        kind, mx, my, mz, l = name.split("-")
+        gen = W.paper_cantilever if kind == "CANT" else W.paper_bridge
+        pr = gen(int(mx), int(my), int(mz), int(l))
+        pr.rho_lo = 1e-3
+        ctx = V.Context.from_problem(pr, precision=V.VTS_FP64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.ip_init()
+        its, mr, status, s = 0, 0, V.VTS_ENOTCONV, {}
+        for k in range(150):
+            s = ctx.ip_step(check=False)
+            its, mr = k + 1, mr + s["minres_its"]
+            print(f"{name} IP: iteration {its} minres {s['minres_its']} gap ratio "
+                  f"{s['gap_ratio']:.2e} res_IP {s['res_ip']:.2e} t {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+            if s["status"] != V.VTS_OK:
+                status = s["status"]
+                break
+            if s["converged"]:
+                status = V.VTS_OK
+                break
+        torch.cuda.synchronize()
+        res = dict(m=pr.m, n=pr.n, seconds=time.perf_counter() - t0, status=int(status),
+                   iterations=its, minres=mr, compliance=s.get("compliance"),
+                   paper_ip_mr=PAPER_IP_COUNTS[name])
+        out[name] = res
+        print(f"{name}: {json.dumps(res)}", file=sys.stderr, flush=True)
+        ctx.close()
+    line = {"metric": METRIC, "value": None, "unit": "see problems", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "paper problems (Section 7), interior point method with "
+                                   "the paper's parameters"},
+            "problems": out}
+    print(json.dumps(line), flush=True)
+    return 0
 
 
 def paper_problems(a, torch, W, V):
@@ -493,6 +543,8 @@ def main():
         return serving(a, torch, W, V)
     if a.doc:
         return doc_compare(a, torch, W, V)
+    if a.paper and a.ip:
+        return paper_problems_ip(a, torch, W, V)
     if a.ip:
         return ip_compare(a, torch, W, V)
     if a.paper:
