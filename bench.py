@@ -62,6 +62,10 @@ def parse():
                     help="the paper's CANT/BRIDGE-4-2-2-{5,6} problems with the paper's "
                          "parameters (Section 7), iteration counts beside Tables 3 and 4 "
                          "(with --ip: the interior point method)")
+    ap.add_argument("--scale", action="store_true",
+                    help="time-to-KKT of the benchmark cantilever family at refinement levels "
+                         "--levels (n up to 12.8 M DOFs); one JSON line")
+    ap.add_argument("--levels", type=int, nargs="+", default=[5, 6, 7])
     ap.add_argument("--requests", type=int, default=20, help="requests per rate (--serve)")
     ap.add_argument("--slots", type=int, default=4, help="concurrent requests (--serve)")
     ap.add_argument("--pool-gb", type=float, default=16.0, help="device pool (--serve)")
@@ -240,23 +244,20 @@ def paper_problems_ip(a, torch, W, V):
     """The interior point method with the paper's parameters (Algorithm 3:
     eps_IP = 1e-5, sigma = 0.2, r = s = 1e-2 initially; rho_lo = 1e-3 as in
     Section 7 for IP) on the CANT and BRIDGE 4-2-2-l problems, FP64."""
-    out = {}
-    for name in PAPER_IP_COUNTS:
-        kind, mx, my, mz, l = name.split("-")
-        gen = W.paper_cantilever if kind == "CANT" else W.paper_bridge
-        pr = gen(int(mx), int(my), int(mz), int(l))
-        pr.rho_lo = 1e-3
+    def run(pr, name, eps_mr0):
         ctx = V.Context.from_problem(pr, precision=V.VTS_FP64)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ctx.ip_init()
+        ctx.ip_init(eps_mr0=eps_mr0)
         its, mr, status, s = 0, 0, V.VTS_ENOTCONV, {}
         for k in range(150):
             s = ctx.ip_step(check=False)
             its, mr = k + 1, mr + s["minres_its"]
-            print(f"{name} IP: iteration {its} minres {s['minres_its']} gap ratio "
-                  f"{s['gap_ratio']:.2e} res_IP {s['res_ip']:.2e} t {time.perf_counter() - t0:.1f} s",
-                  file=sys.stderr, flush=True)
+            if its % 10 == 0 or s["converged"] or s["status"] != V.VTS_OK:
+                print(f"{name} IP (eps_MR0 {eps_mr0:g}): iteration {its} minres "
+                      f"{s['minres_its']} gap ratio {s['gap_ratio']:.2e} res_IP "
+                      f"{s['res_ip']:.2e} t {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
             if s["status"] != V.VTS_OK:
                 status = s["status"]
                 break
@@ -264,12 +265,25 @@ def paper_problems_ip(a, torch, W, V):
                 status = V.VTS_OK
                 break
         torch.cuda.synchronize()
-        res = dict(m=pr.m, n=pr.n, seconds=time.perf_counter() - t0, status=int(status),
-                   iterations=its, minres=mr, compliance=s.get("compliance"),
-                   paper_ip_mr=PAPER_IP_COUNTS[name])
+        res = dict(seconds=time.perf_counter() - t0, status=int(status), iterations=its,
+                   minres=mr, compliance=s.get("compliance"), eps_mr0=eps_mr0)
+        ctx.close()
+        return res
+
+    out = {}
+    for name in PAPER_IP_COUNTS:
+        kind, mx, my, mz, l = name.split("-")
+        gen = W.paper_cantilever if kind == "CANT" else W.paper_bridge
+        pr = gen(int(mx), int(my), int(mz), int(l))
+        pr.rho_lo = 1e-3
+        res = dict(m=pr.m, n=pr.n, paper_ip_mr=PAPER_IP_COUNTS[name])
+        res["paper_eps_mr0"] = run(pr, name, 1e-2)
+        if res["paper_eps_mr0"]["status"] != V.VTS_OK:
+            # the paper's start value leaves the first directions too inexact
+            # for this load; the same method with a tighter start
+            res["eps_mr0_1e-4"] = run(pr, name, 1e-4)
         out[name] = res
         print(f"{name}: {json.dumps(res)}", file=sys.stderr, flush=True)
-        ctx.close()
     line = {"metric": METRIC, "value": None, "unit": "see problems", "n_gpus": 1,
             "steps": 1, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -324,6 +338,57 @@ def paper_problems(a, torch, W, V):
             "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": "paper problems (Section 7) with the paper's parameters"},
             "problems": out}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def scaling_run(a, torch, W, V):
+    """Time-to-KKT of the benchmark cantilever family (the CANT-4-2-2-l
+    geometry with the edge load of the 64x32x32 workload, V = 0.2 m) at
+    refinement levels 5, 6 and 7 on one GPU, with the library's default
+    options: how the solve scales with n up to 12.8 M DOFs."""
+    prec = V.VTS_FP64 if a.precision == "fp64" else V.VTS_MIXED
+    out = {}
+    for l in a.levels:
+        s2 = 2 ** (l - 1)
+        pr = W.cantilever_edge(4 * s2, 2 * s2, 2 * s2, l, vol_frac=0.2)
+        opts = V.default_options(eps_mr0=1e-2)
+        ctx = V.Context.from_problem(pr, precision=prec, options=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status = V.VTS_OK
+        for k in range(opts.max_outer):
+            try:
+                st = ctx.pbm_iterate()
+            except V.VtsError as e:
+                status = e.status
+                break
+            if (k + 1) % 5 == 0 or st["converged"]:
+                print(f"l={l} n={pr.n}: outer {k + 1} ratio {st['ratio']:.2e} stat "
+                      f"{st['stat']:.2e} t {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                      flush=True)
+            if st["converged"]:
+                break
+        r = ctx.pbm_solve(check=False) if status == V.VTS_OK else None
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = dict(m=pr.m, n=pr.n, seconds=dt, status=int(r["status"] if r else status),
+                   device_gb=ctx.allocated_bytes() / 1e9)
+        if r:
+            k = device_kkt(torch, ctx, pr, ctx.state_dict()["alpha"])
+            res.update(outer=r["outer"], newton=r["newton"], minres=r["minres"],
+                       compliance=r["compliance"], kkt=k["kkt"],
+                       ms_per_minres=dt * 1e3 / max(r["minres"], 1))
+        out[f"l{l}"] = res
+        print(f"l={l}: {json.dumps(res)}", file=sys.stderr, flush=True)
+        ctx.close()
+    line = {"metric": METRIC, "value": None, "unit": "see levels", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+            "scaling": "strong", "vs_baseline": None,
+            "dtype": "f64" if prec == V.VTS_FP64 else "f64+f32mg", "data": "synthetic",
+            "config": {"workload": "cantilever 4*2^(l-1) x 2^l x 2^l, edge load, V = 0.2 m",
+                       "levels": a.levels},
+            "levels": out}
     print(json.dumps(line), flush=True)
     return 0
 
@@ -543,6 +608,8 @@ def main():
         return serving(a, torch, W, V)
     if a.doc:
         return doc_compare(a, torch, W, V)
+    if a.scale:
+        return scaling_run(a, torch, W, V)
     if a.paper and a.ip:
         return paper_problems_ip(a, torch, W, V)
     if a.ip:
