@@ -100,3 +100,28 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([_sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def test_product_code_does_not_use_the_oracle():
+    """The package never imports oracle/; in bench.py only the cpu_baseline
+    leg does."""
+    import ast
+    import glob
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+    def oracle_imports(tree):
+        for node in ast.walk(tree):
+            if isinstance(node, ast.Import) and any(a.name.split(".")[0] == "oracle"
+                                                   for a in node.names):
+                yield node
+            if isinstance(node, ast.ImportFrom) and (node.module or "").split(".")[0] == "oracle":
+                yield node
+
+    for path in glob.glob(os.path.join(root, "paper_1904_06556_amd", "*.py")):
+        assert not list(oracle_imports(ast.parse(open(path).read()))), path
+    tree = ast.parse(open(os.path.join(root, "bench.py")).read())
+    for fn in tree.body:
+        if isinstance(fn, ast.FunctionDef) and fn.name != "cpu_baseline":
+            assert not list(oracle_imports(fn)), fn.name
+    assert not [n for n in tree.body if isinstance(n, (ast.Import, ast.ImportFrom))
+                and list(oracle_imports(n))]
