@@ -107,6 +107,13 @@ typedef struct {
                                      criterion below 0.9 x the best (0: never); then the
                                      accept_stall rule decides (the paper accepts stalled
                                      near-optimal points, Section 7.2) */
+    int32_t use_graphs;           /* 1: replay each V-cycle from a captured HIP graph (the
+                                     same kernels and arguments, bitwise equal results;
+                                     recaptured after every multigrid setup; contexts built
+                                     inside a server pool never do, so serving allocates
+                                     nothing).  Default 0: measured no faster on MI355X,
+                                     the V-cycle waits on dependent-kernel latency on the
+                                     device, not on host launch cost */
 } vts_options;
 
 typedef struct {

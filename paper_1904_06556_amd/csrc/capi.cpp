@@ -305,6 +305,12 @@ double res_pbm(const Ctx& c) {
 }
 double res4_term(const Ctx& c) { return c.n_g4 / c.norm_bounds; }
 
+// drop the captured V-cycles (the stream must be idle: build_mg has synchronized)
+void drop_graphs(Ctx& c) {
+    for (auto& g : c.vgraphs) hipGraphExecDestroy(g.exec);
+    c.vgraphs.clear();
+}
+
 vts_status build_mg(Ctx& c) {
     int flag = 0;
     if (c.h64) {
@@ -314,6 +320,8 @@ vts_status build_mg(Ctx& c) {
         mg_build(c, *c.h32);
         flag = mg_check_factor(c, *c.h32);
     }
+    // mg_check_factor synchronized the stream: no captured V-cycle is in flight
+    drop_graphs(c);
     HIPCHK(hipGetLastError());
     if (flag) {
         c.err = "coarsest multigrid matrix is not positive definite";
@@ -332,11 +340,56 @@ vts_status setup(Ctx& c) {
     return VTS_OK;
 }
 
-void precond(Ctx& c, const double* r, double* z) {
+void vcycle_launches(Ctx& c, const double* r, double* z) {
     if (c.h64)
         mg_vcycle(c, *c.h64, r, z);
     else
         mg_vcycle(c, *c.h32, r, z);
+}
+
+// One V-cycle from a captured graph; false if graphs are unavailable (the
+// caller then launches the kernels directly).  The capture records the same
+// launches on a private stream; nothing runs during the capture.
+bool precond_graph(Ctx& c, const double* r, double* z) {
+    for (const auto& g : c.vgraphs)
+        if (g.r == r && g.z == z && g.d == c.sum_w) return hipGraphLaunch(g.exec, c.s) == hipSuccess;
+    if (!c.cap_stream && hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        c.cap_stream = nullptr;
+        c.opt.use_graphs = 0;
+        return false;
+    }
+    hipStream_t s0 = c.s;
+    c.s = c.cap_stream;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        vcycle_launches(c, r, z);
+        e = hipStreamEndCapture(c.s, &graph);
+    }
+    c.s = s0;
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c.opt.use_graphs = 0;
+        return false;
+    }
+    if (c.vgraphs.size() >= 4) {
+        // the oldest entry may still be in flight on s: finish it first
+        hipStreamSynchronize(c.s);
+        hipGraphExecDestroy(c.vgraphs.front().exec);
+        c.vgraphs.erase(c.vgraphs.begin());
+    }
+    c.vgraphs.push_back({r, z, c.sum_w, exec});
+    return hipGraphLaunch(exec, c.s) == hipSuccess;
+}
+
+void precond(Ctx& c, const double* r, double* z) {
+    // graphs only outside server pools (instantiation may allocate) and
+    // while no kernel class is being timed
+    if (c.opt.use_graphs && !c.arena && c.prof_class == 0 && precond_graph(c, r, z)) return;
+    vcycle_launches(c, r, z);
 }
 
 // Preconditioned MINRES (Paige-Saunders), x0 = 0: Lanczos in the M-inner
@@ -854,6 +907,9 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
 void ctx_free(Ctx& c) {
     if (c.s) hipStreamSynchronize(c.s);
     else hipDeviceSynchronize();
+    drop_graphs(c);
+    if (c.cap_stream) hipStreamDestroy(c.cap_stream);
+    c.cap_stream = nullptr;
     for (hipEvent_t e : c.prof_ev) hipEventDestroy(e);
     c.prof_ev.clear();
     for (void* p : c.allocs) hipFree(p);
@@ -945,6 +1001,7 @@ void vts_default_options(vts_options* o) {
     o->final_res4 = 1;
     o->p_min_relative = 1;
     o->stall_steps = 10;
+    o->use_graphs = 0;
 }
 
 vts_status vts_create(const vts_problem* pr, const vts_options* opt, void* stream, vts_ctx** out) {

@@ -147,6 +147,18 @@ struct Ctx {
         bool ready = false;
     } ip;
 
+    // V-cycles replayed from captured HIP graphs, keyed by the arguments that
+    // vary between calls (r, z and the alpha diagonal); dropped whenever the
+    // hierarchy is rebuilt.  Captured on a private stream, launched on s.
+    struct VGraph {
+        const double* r;
+        double* z;
+        double d;
+        hipGraphExec_t exec;
+    };
+    std::vector<VGraph> vgraphs;
+    hipStream_t cap_stream = nullptr;
+
     std::vector<void*> allocs;   // hipMalloc'd buffers (contexts without an arena)
     char* arena = nullptr;       // caller-owned device range (server slots), or null
     size_t arena_size = 0, arena_used = 0;

@@ -52,7 +52,7 @@ class Options_t(C.Structure):
                 ("armijo_min", C.c_double), ("max_outer", C.c_int32),
                 ("max_newton", C.c_int32), ("max_minres", C.c_int32),
                 ("final_res4", C.c_int32), ("p_min_relative", C.c_int32),
-                ("stall_steps", C.c_int32)]
+                ("stall_steps", C.c_int32), ("use_graphs", C.c_int32)]
 
 
 class LinStats_t(C.Structure):
