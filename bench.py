@@ -66,6 +66,9 @@ def parse():
                     help="time-to-KKT of the benchmark cantilever family at refinement levels "
                          "--levels (n up to 12.8 M DOFs); one JSON line")
     ap.add_argument("--levels", type=int, nargs="+", default=[5, 6, 7])
+    ap.add_argument("--scale-kernels", action="store_true",
+                    help="the dominant kernels (finest Gauss-Seidel pass, K(rho)x, S-apply) "
+                         "timed at each of --levels, FP64 and mixed; one JSON line")
     ap.add_argument("--requests", type=int, default=20, help="requests per rate (--serve)")
     ap.add_argument("--slots", type=int, default=4, help="concurrent requests (--serve)")
     ap.add_argument("--pool-gb", type=float, default=16.0, help="device pool (--serve)")
@@ -393,6 +396,55 @@ def scaling_run(a, torch, W, V):
     return 0
 
 
+def scaling_kernels(a, torch, W, V):
+    """The dominant kernels at the initial Newton point of the cantilever
+    family at levels --levels, FP64 and mixed: the finest-level Gauss-Seidel
+    pass, K(rho)x and the S-apply, each timed with HIP events over every
+    launch of repeated calls; bandwidth from the algorithmic bytes."""
+    out = {}
+    for l in a.levels:
+        s2 = 2 ** (l - 1)
+        pr = W.cantilever_edge(4 * s2, 2 * s2, 2 * s2, l, vol_frac=0.2)
+        for prec in (V.VTS_FP64, V.VTS_MIXED):
+            ctx = V.Context.from_problem(pr, precision=prec)
+            ctx.reset()
+            ctx.newton_setup()
+            g = torch.Generator(device="cpu").manual_seed(1)
+            r = (torch.rand(ctx.n_dof + 1, generator=g, dtype=torch.float64) - 0.5).cuda()
+            z = torch.empty_like(r)
+            x = (torch.rand(ctx.n_dof, generator=g, dtype=torch.float64) - 0.5).cuda()
+            y = torch.empty_like(x)
+            # one untimed call of each (first use loads code and warms caches)
+            ctx.precondition(r, z)
+            ctx.apply_K(x, y)
+            ctx.apply_S(r, z)
+            torch.cuda.synchronize()
+            gs = profiled(ctx, "gs_fine", lambda: [ctx.precondition(r, z) for _ in range(a.reps)])
+            ka = profiled(ctx, "apply_K", lambda: [ctx.apply_K(x, y) for _ in range(a.reps)])
+            sa = profiled(ctx, "apply_S", lambda: [ctx.apply_S(r, z) for _ in range(a.reps)])
+            key = f"l{l}_{'fp64' if prec == V.VTS_FP64 else 'mixed'}"
+            out[key] = {
+                "n": pr.n, "m": pr.m,
+                "gs_fine": {"avg_launch_us": gs["avg_launch_ms"] * 1e3, "gbs": gs["gbs"],
+                            "frac": gs["gbs"] / HBM_PEAK_GBS,
+                            "bytes_per_launch": gs["bytes_per_launch"]},
+                "apply_K_f64": {"avg_launch_us": ka["avg_launch_ms"] * 1e3, "gbs": ka["gbs"],
+                                "frac": ka["gbs"] / HBM_PEAK_GBS},
+                "apply_S": {"avg_launch_us": sa["avg_launch_ms"] * 1e3, "gbs": sa["gbs"],
+                            "frac": sa["gbs"] / HBM_PEAK_GBS},
+            }
+            print(f"{key}: {json.dumps(out[key])}", file=sys.stderr, flush=True)
+            ctx.close()
+    line = {"metric": METRIC, "value": None, "unit": "see levels", "n_gpus": 1, "steps": 1,
+            "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "strong",
+            "vs_baseline": None, "dtype": "f64 / f64+f32mg", "data": "synthetic",
+            "config": {"workload": "cantilever 4*2^(l-1) x 2^l x 2^l, initial Newton point",
+                       "levels": a.levels, "reps": a.reps},
+            "kernels_by_level": out}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def device_kkt(torch, ctx, pr, lam):
     """KKT residual of the context's (rho, u) with volume multiplier lam, by
     its definition: r_eq = ||K(rho)u - f||/||f||, r_vol = |sum rho - V|/V,
@@ -608,6 +660,8 @@ def main():
         return serving(a, torch, W, V)
     if a.doc:
         return doc_compare(a, torch, W, V)
+    if a.scale_kernels:
+        return scaling_kernels(a, torch, W, V)
     if a.scale:
         return scaling_run(a, torch, W, V)
     if a.paper and a.ip:
