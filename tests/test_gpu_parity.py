@@ -385,3 +385,50 @@ def test_graph_vcycle_equals_direct_launches(prec):
     assert g.pbm_solve() == e.pbm_solve() == ra
     g.close()
     e.close()
+
+
+DEGENERATE = {
+    "one-element-1x1x1-l1": lambda: W.cantilever_edge(1, 1, 1, 1, vol_frac=0.3),
+    "two-elements-2x1x1-l1": lambda: W.cantilever_edge(2, 1, 1, 1, vol_frac=0.6),
+    "ragged-7x3x5-l1": lambda: W.cantilever_edge(7, 3, 5, 1, vol_frac=0.25),
+}
+
+
+@pytest.mark.parametrize("precision", [V.VTS_FP64, V.VTS_MIXED])
+@pytest.mark.parametrize("case", list(DEGENERATE))
+def test_degenerate_grids_solve(case, precision):
+    """One level (the multigrid is the coarse solve alone), one and two
+    elements, and a grid of odd sizes, against what fixes their optimum:
+    m = 1 has rho = V; m = 2 a convex one-dimensional compliance (golden
+    section); otherwise the weak-duality bracket."""
+    pr = DEGENERATE[case]()
+    say("degenerate", case, precision)
+    ctx = V.Context.from_problem(pr, precision=precision)
+    r = ctx.pbm_solve()
+    d = ctx.state_dict()
+    ctx.close()
+    P = pbm.VTS(pr)
+    k = kkt.kkt_residual(P.grid, P.Ke, P.f, P.V, P.rho_lo, P.rho_hi, d["rho"], d["u"], d["alpha"])
+    assert k["kkt"] <= 1e-6, k
+    c = kkt.compliance(P.grid, P.Ke, d["rho"], P.f)
+    assert abs(r["compliance"] - c) <= 1e-6 * c
+    if P.grid.m == 1:
+        assert abs(d["rho"][0] - P.V) <= 1e-9 * P.V
+        assert abs(c - kkt.compliance(P.grid, P.Ke, np.array([P.V]), P.f)) <= 1e-9 * c
+    elif P.grid.m == 2:
+        lo = max(P.rho_lo[0], P.V - P.rho_hi[1])
+        hi = min(P.rho_hi[0], P.V - P.rho_lo[1])
+        cf = lambda t: kkt.compliance(P.grid, P.Ke, np.array([t, P.V - t]), P.f)
+        gr = (np.sqrt(5.0) - 1.0) / 2.0
+        a, b = lo, hi
+        for _ in range(200):
+            x1, x2 = b - gr * (b - a), a + gr * (b - a)
+            if cf(x1) < cf(x2):
+                b = x2
+            else:
+                a = x1
+        assert abs(c - cf(0.5 * (a + b))) <= 1e-7 * c
+    else:
+        lb, ub, rel_gap = kkt.certificate(P.grid, P.Ke, P.f, P.V, P.rho_lo, P.rho_hi, d["rho"],
+                                          d["u"])
+        assert rel_gap <= 1e-6 and lb <= c * (1 + 1e-9)
