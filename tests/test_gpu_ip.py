@@ -20,6 +20,8 @@ def say(*a):
 CASES = {
     "cant-8x4x4-l3": (lambda: W.config(0), 8),
     "cant-16x8x8-l3": (lambda: W.cantilever_edge(16, 8, 8, 3, vol_frac=0.3), 8),
+    # the size and launch configuration that bench.py --ip times
+    "cant-64x32x32-l5": (lambda: W.config(1), 3),
 }
 
 
