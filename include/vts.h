@@ -330,7 +330,10 @@ vts_status vts_doc_solve(vts_ctx* ctx, double q, double eps_doc, double eps_mr, 
  * (N_lo - N_hi) rho is (N_lo - N_hi) Delta rho; alpha tends to minus the
  * volume multiplier, so the gap (2.6) is evaluated at (u, -alpha); the
  * multiplier step lengths are capped at 1; MINRES stops, keeping its
- * iterate, if the V-cycle loses definiteness in floating point.
+ * iterate, if the V-cycle loses definiteness in floating point.  Use FP64
+ * contexts: with VTS_MIXED the FP32 V-cycle cannot resolve the late,
+ * ill-conditioned IP systems (the 8x4x4 cantilever does not meet the
+ * stopping test in 300 iterations).
  * --------------------------------------------------------------------- */
 typedef struct {
     double eps_ip;                /* stopping tolerance (paper: 1e-5) */
