@@ -300,6 +300,30 @@ k_acol_dot(Level<T> L, const T* __restrict__ z, double* partials) {
     if (threadIdx.x == 0) partials[SL_AUX * kRedBlocks + blockIdx.x] = sh[0];
 }
 
+// The alpha step of k_alpha_fin inside another kernel, by the first kThreads
+// threads of the block (every thread of the block must call it: it holds
+// barriers).  Same partial-sum order and the same operations as k_alpha_fin,
+// so the result is bitwise the same: returns v = r_a - (T)(sum partials) - d z_a.
+template <typename T>
+__device__ __forceinline__ T alpha_residual(const double* __restrict__ partials, int slot, int nb,
+                                            double d, T ra, T za, double* sh) {
+    if ((int)threadIdx.x < kThreads) {
+        double x = 0.0;
+        for (int b = threadIdx.x; b < nb; b += kThreads) x += partials[slot * kRedBlocks + b];
+        sh[threadIdx.x] = x;
+    }
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const T td = (T)d;
+    const T dot = (T)sh[0];
+    const T v = ra - dot - td * za;
+    __syncthreads();
+    return v;
+}
+
 // Sum the partials, then either the Gauss-Seidel update of alpha
 // (mode 0: z_a += (r_a - acol.z - d z_a)/d) or the alpha residual
 // (mode 1: res_a = r_a - acol.z - d z_a).
@@ -331,9 +355,22 @@ __global__ void k_alpha_fin(const double* __restrict__ partials, int nb, int64_t
 // transfers (Section 6.2): trilinear prolongation P, restriction P^T,
 // identity on alpha
 // ---------------------------------------------------------------------------
+// restriction P^T; with_alpha: the alpha entry by identity.  With nb > 0 the
+// parent's alpha residual res_a = r_a - acol.z - d z_a is formed here first
+// (block 0, from the nb partial sums of the residual kernel in SL_STAT) and
+// becomes the coarse alpha entry.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_restrict(Level<T> F, Level<T> C, const T* __restrict__ rf, T* __restrict__ rc, int with_alpha) {
+k_restrict(Level<T> F, Level<T> C, const T* __restrict__ rf, T* __restrict__ rc, int with_alpha,
+           const double* __restrict__ partials, int nb, double d) {
+    __shared__ double sh[kThreads];
+    if (nb > 0 && blockIdx.x == 0) {
+        const T v = alpha_residual<T>(partials, SL_STAT, nb, d, F.r[3 * F.nn], F.z[3 * F.nn], sh);
+        if (threadIdx.x == 0) {
+            F.res[3 * F.nn] = v;
+            rc[3 * C.nn] = v;
+        }
+    }
     const int64_t N = gidx();
     if (N >= C.nn) return;
     const int I = (int)(N % C.NX);
@@ -362,7 +399,7 @@ k_restrict(Level<T> F, Level<T> C, const T* __restrict__ rf, T* __restrict__ rc,
     rc[3 * N] = C.fixed[3 * N] ? T(0) : a0;
     rc[3 * N + 1] = C.fixed[3 * N + 1] ? T(0) : a1;
     rc[3 * N + 2] = C.fixed[3 * N + 2] ? T(0) : a2;
-    if (with_alpha && N == 0) rc[3 * C.nn] = rf[3 * F.nn];
+    if (with_alpha && nb <= 0 && N == 0) rc[3 * C.nn] = rf[3 * F.nn];
 }
 
 template <typename T>
@@ -559,7 +596,12 @@ k_top_init(Level<T> L, const double* __restrict__ rin) {
 // child's first colour
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_restrict_init(Level<T> F, Level<T> C, const T* __restrict__ rf) {
+k_restrict_init(Level<T> F, Level<T> C, const T* __restrict__ rf,
+                const double* __restrict__ partials, int nb, double d) {
+    __shared__ double sh[kThreads];
+    T va = T(0);
+    if (blockIdx.x == 0)
+        va = alpha_residual<T>(partials, SL_STAT, nb, d, F.r[3 * F.nn], F.z[3 * F.nn], sh);
     const int64_t N = gidx();
     if (N < C.nn) {
         const int I = (int)(N % C.NX);
@@ -594,7 +636,8 @@ k_restrict_init(Level<T> F, Level<T> C, const T* __restrict__ rf) {
         first_colour(C, N, I, J, K, r0, r1, r2);
     }
     if (N == 0) {
-        C.r[3 * C.nn] = rf[3 * F.nn];
+        F.res[3 * F.nn] = va;
+        C.r[3 * C.nn] = va;
         C.z[3 * C.nn] = T(0);
     }
 }
@@ -682,15 +725,23 @@ k_gs_color9(Level<T> L, int col, const T* __restrict__ r, T* __restrict__ z) {
     }
 }
 
-// res = r - S z (displacement part, masked) and per-block partial sums of acol . z
+// res = r - S z (displacement part, masked) and per-block partial sums of
+// acol . z (slot SL_STAT).  First the alpha step that ends the forward sweep,
+// z_a += (r_a - acol.z - d z_a)/d from the nb partial sums of k_acol_dot
+// (slot SL_AUX): every block forms it (identical value, fixed order) and
+// block 0 stores it.  The level entered the sweep with z = 0 and the colour
+// passes leave z_a alone, so z_a is 0 before this step and the blocks never
+// read the location block 0 writes.
 template <typename T, bool TOP>
 __global__ void __launch_bounds__(kBlk9)
-k_resid9(Level<T> L, const T* __restrict__ r, const T* __restrict__ z, T* __restrict__ res,
-         double* partials) {
+k_resid9(Level<T> L, const T* __restrict__ r, T* __restrict__ z, T* __restrict__ res,
+         double* partials, int nb, double d) {
     __shared__ T part[kRowWaves][3][64];
     __shared__ double red[64];
+    __shared__ double sh[kThreads];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const T za = z[3 * L.nn];
+    const T za = T(0) + alpha_residual<T>(partials, SL_AUX, nb, d, r[3 * L.nn], T(0), sh) / (T)d;
+    if (blockIdx.x == 0 && threadIdx.x == 0) z[3 * L.nn] = za;
     double acc = 0.0;
     for (int64_t base = (int64_t)blockIdx.x * 64; base < L.nn; base += (int64_t)gridDim.x * 64) {
         const int64_t t = base + lane;
@@ -725,7 +776,7 @@ k_resid9(Level<T> L, const T* __restrict__ r, const T* __restrict__ z, T* __rest
     }
     if (g == 0) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-        if (lane == 0) partials[SL_AUX * kRedBlocks + blockIdx.x] = acc;
+        if (lane == 0) partials[SL_STAT * kRedBlocks + blockIdx.x] = acc;
     }
 }
 
@@ -1051,7 +1102,8 @@ void mg_build(Ctx& c, Hierarchy<T>& H) {
             Level<T>& Lk = H.lev[k];
             hipLaunchKernelGGL(k_elem_stencil<T>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s, Lk);
             hipLaunchKernelGGL(k_restrict<T>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s,
-                               H.lev[k + 1], Lk, H.lev[k + 1].acol, Lk.acol, 0);
+                               H.lev[k + 1], Lk, H.lev[k + 1].acol, Lk.acol, 0,
+                               (const double*)nullptr, 0, 0.0);
         }
     }
     Level<T>& L0 = H.lev[0];
@@ -1065,10 +1117,11 @@ void mg_build(Ctx& c, Hierarchy<T>& H) {
 }
 
 // Gauss-Seidel colour passes of one sweep: forward colours 1..7 (colour 0
-// was applied by the kernel that set up the level's r and z) followed by
-// the alpha update, or backward colours 7..0.  On the finest level the
-// colour passes are optionally bracketed by the profiling events of the
-// context (kernel class VTS_PROF_GS_FINE), one event pair per sweep.
+// was applied by the kernel that set up the level's r and z; the alpha
+// update that follows is fused into the residual kernel), or backward
+// colours 7..0.  On the finest level the colour passes are optionally
+// bracketed by the profiling events of the context (kernel class
+// VTS_PROF_GS_FINE), one event pair per sweep.
 template <typename T>
 static void gs_sweep(Ctx& c, Level<T>& Lk, bool forward, bool top) {
     const bool prof = top && prof_begin(c, VTS_PROF_GS_FINE);
@@ -1089,15 +1142,21 @@ static void gs_sweep(Ctx& c, Level<T>& Lk, bool forward, bool top) {
         ++launches;
     }
     if (prof) prof_end(c, bytes, launches);
-    if (forward) alpha_update(c, Lk);
+}
+
+// per-block partial sums of acol . z into SL_AUX; returns the block count
+template <typename T>
+static int acol_partials(Ctx& c, Level<T>& Lk) {
+    const int gr = red_grid_of(3 * Lk.nn);
+    hipLaunchKernelGGL(k_acol_dot<T>, dim3(gr), dim3(kThreads), 0, c.s, Lk, (const T*)Lk.z,
+                       c.partials);
+    return gr;
 }
 
 // z_a += (r_a - acol . z - d z_a) / d
 template <typename T>
 static void alpha_update(Ctx& c, Level<T>& Lk) {
-    const int gr = red_grid_of(3 * Lk.nn);
-    hipLaunchKernelGGL(k_acol_dot<T>, dim3(gr), dim3(kThreads), 0, c.s, Lk, (const T*)Lk.z,
-                       c.partials);
+    const int gr = acol_partials(c, Lk);
     hipLaunchKernelGGL(k_alpha_fin<T>, dim3(1), dim3(kThreads), 0, c.s, c.partials, gr, Lk.nn,
                        c.sum_w, (const T*)Lk.r, Lk.z, Lk.res, 0);
 }
@@ -1125,26 +1184,26 @@ static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
         return;
     }
     const double d = c.sum_w;
-    // forward sweep (colours 1..7, then alpha)
+    // forward sweep (colours 1..7) and the partial sums for its alpha update
     gs_sweep(c, Lk, true, top);
-    // residual, alpha residual, restriction, coarse correction, prolongation
+    const int gr = acol_partials(c, Lk);
+    // alpha update and residual; alpha residual and restriction; coarse
+    // correction; prolongation
     int64_t chunks = (Lk.nn + 63) / 64;
     const int grr = (int)(chunks < kRedBlocks ? chunks : kRedBlocks);
     if (top)
         hipLaunchKernelGGL((k_resid9<T, true>), dim3(grr), dim3(kBlk9), 0, c.s, Lk, (const T*)Lk.r,
-                           (const T*)Lk.z, Lk.res, c.partials);
+                           Lk.z, Lk.res, c.partials, gr, d);
     else
         hipLaunchKernelGGL((k_resid9<T, false>), dim3(grr), dim3(kBlk9), 0, c.s, Lk, (const T*)Lk.r,
-                           (const T*)Lk.z, Lk.res, c.partials);
-    hipLaunchKernelGGL(k_alpha_fin<T>, dim3(1), dim3(kThreads), 0, c.s, c.partials, grr, Lk.nn, d,
-                       (const T*)Lk.r, Lk.z, Lk.res, 1);
+                           Lk.z, Lk.res, c.partials, gr, d);
     Level<T>& Lc = H.lev[k - 1];
     if (k - 1 <= H.ksmall || k - 1 == 0)
         hipLaunchKernelGGL(k_restrict<T>, dim3(grid_of(Lc.nn)), dim3(kThreads), 0, c.s, Lk, Lc,
-                           (const T*)Lk.res, Lc.r, 1);
+                           (const T*)Lk.res, Lc.r, 1, (const double*)c.partials, grr, d);
     else
         hipLaunchKernelGGL(k_restrict_init<T>, dim3(grid_of(Lc.nn)), dim3(kThreads), 0, c.s, Lk,
-                           Lc, (const T*)Lk.res);
+                           Lc, (const T*)Lk.res, (const double*)c.partials, grr, d);
     vcycle_level(c, H, k - 1);
     hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s, Lc, Lk,
                        (const T*)Lc.z, Lk.z);
