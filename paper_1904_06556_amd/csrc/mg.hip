@@ -736,35 +736,43 @@ template <typename T, bool TOP>
 __global__ void __launch_bounds__(kBlk9)
 k_resid9(Level<T> L, const T* __restrict__ r, T* __restrict__ z, T* __restrict__ res,
          double* partials, int nb, double d) {
-    __shared__ T part[kRowWaves][3][64];
-    __shared__ double red[64];
+    // row partial sums, double-buffered: the buffer of chunk q is rewritten
+    // in chunk q + 2, after every wave has passed the barrier of chunk q + 1,
+    // which wave 0 reaches only once it has read chunk q's sums
+    __shared__ T part[2][kRowWaves][3][64];
     __shared__ double sh[kThreads];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
     const T za = T(0) + alpha_residual<T>(partials, SL_AUX, nb, d, r[3 * L.nn], T(0), sh) / (T)d;
     if (blockIdx.x == 0 && threadIdx.x == 0) z[3 * L.nn] = za;
     double acc = 0.0;
-    for (int64_t base = (int64_t)blockIdx.x * 64; base < L.nn; base += (int64_t)gridDim.x * 64) {
+    int buf = 0;
+    for (int64_t base = (int64_t)blockIdx.x * 64; base < L.nn;
+         base += (int64_t)gridDim.x * 64, buf ^= 1) {
         const int64_t t = base + lane;
         const bool valid = t < L.nn;
         int i = 0, j = 0, k = 0;
-        T a0 = 0, a1 = 0, a2 = 0;
+        int64_t n = 0;
+        T a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0;
         if (valid) {
             cm_decode(L, t, i, j, k);
+            if (g == 0) {
+                // operands of the update, loaded while the rows are summed
+                n = nat(i, j, k, L.NX, L.NY);
+                b0 = r[3 * n] - L.acol[3 * n] * za;
+                b1 = r[3 * n + 1] - L.acol[3 * n + 1] * za;
+                b2 = r[3 * n + 2] - L.acol[3 * n + 2] * za;
+            }
             row_partial(L, t, i, j, k, g, z, a0, a1, a2);
         }
-        part[g][0][lane] = a0;
-        part[g][1][lane] = a1;
-        part[g][2][lane] = a2;
+        part[buf][g][0][lane] = a0;
+        part[buf][g][1][lane] = a1;
+        part[buf][g][2][lane] = a2;
         __syncthreads();
         if (g == 0 && valid) {
-            const int64_t n = nat(i, j, k, L.NX, L.NY);
-            T b0 = r[3 * n] - L.acol[3 * n] * za;
-            T b1 = r[3 * n + 1] - L.acol[3 * n + 1] * za;
-            T b2 = r[3 * n + 2] - L.acol[3 * n + 2] * za;
             for (int h = 0; h < kRowWaves; ++h) {
-                b0 -= part[h][0][lane];
-                b1 -= part[h][1][lane];
-                b2 -= part[h][2][lane];
+                b0 -= part[buf][h][0][lane];
+                b1 -= part[buf][h][1][lane];
+                b2 -= part[buf][h][2][lane];
             }
             res[3 * n] = L.fixed[3 * n] ? T(0) : b0;
             res[3 * n + 1] = L.fixed[3 * n + 1] ? T(0) : b1;
@@ -772,7 +780,6 @@ k_resid9(Level<T> L, const T* __restrict__ r, T* __restrict__ z, T* __restrict__
             acc += (double)L.acol[3 * n] * z[3 * n] + (double)L.acol[3 * n + 1] * z[3 * n + 1] +
                    (double)L.acol[3 * n + 2] * z[3 * n + 2];
         }
-        __syncthreads();
     }
     if (g == 0) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
