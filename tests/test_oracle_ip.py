@@ -143,3 +143,36 @@ def test_multigrid_run_stops_at_the_paper_test():
     assert k["kkt"] <= 1e-3
     last = res.history[-1]
     assert last["ratio"] < 1e-5 and last["res_ip"] < 1e-4
+
+
+def test_uniform_strain_bar_has_uniform_optimum():
+    """A bar under uniform traction on symmetry rollers: every element has
+    the same energy at uniform rho, so rho* = V/m (closed form)."""
+    pr = W.bar_rollers(4, 2, 2, 2, vol_frac=0.5)
+    # every element is interior here, so nu -> 0 and W -> infinity for all of
+    # them: 1e-8 is reached, a much tighter eps_ip makes the Newton systems
+    # numerically singular
+    sol = ip.Solver(pr, ip.IPOptions(eps_ip=1e-8), linsolve=direct)
+    res = sol.solve()
+    assert res.converged
+    P, x = sol.P, res.state
+    assert np.max(np.abs(x.rho - P.V / P.grid.m)) <= 1e-6
+    c_uni = kkt.compliance(P.grid, P.Ke, np.full(P.grid.m, P.V / P.grid.m), P.f)
+    assert abs(0.5 * P.f @ x.u - c_uni) <= 1e-8 * c_uni
+
+
+def test_load_scaling():
+    """f -> s f leaves rho* unchanged and scales the compliance and the
+    multiplier by s^2 (alpha_IP = -lambda)."""
+    out = []
+    for scale in (1.0, 3.0):
+        pr = W.config(0)
+        pr.f = pr.f * scale
+        sol = ip.Solver(pr, ip.IPOptions(eps_ip=1e-10), linsolve=direct)
+        res = sol.solve()
+        assert res.converged
+        out.append((res.state, 0.5 * sol.P.f @ res.state.u))
+    (a, ca), (b, cb) = out
+    assert np.max(np.abs(a.rho - b.rho)) <= 1e-6
+    assert abs(cb - 9.0 * ca) <= 1e-8 * cb
+    assert abs(b.alpha - 9.0 * a.alpha) <= 1e-6 * abs(b.alpha)
