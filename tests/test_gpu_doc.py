@@ -59,3 +59,34 @@ def test_doc_converges_like_oracle(precision):
     # volume to the bisection tolerance tau = 0.1 eps_doc
     assert abs(rho.sum() - P.V) <= 3e-5 * P.V
     ctx.close()
+
+
+def test_doc_step_at_benchmark_size():
+    """One iteration of Algorithm 4 on the 64x32x32 cantilever (the size the
+    DOC benchmark times), checked output by output on the host: the state
+    solve's true residual, the element energies of the returned u, and the
+    new densities against the update formula at the reported multiplier."""
+    from oracle import fe
+    pr = W.config(1)
+    say("benchmark-size step", pr.name)
+    ctx = V.Context.from_problem(pr, precision=V.VTS_FP64)
+    P = pbm.VTS(pr)
+    rho0 = ctx.vector("rho").cpu().numpy().copy()
+    eps, q = 1e-3, 0.5
+    s = ctx.doc_step(q=q, tau=0.1 * eps, eps_doc=-1.0, eps_mr=1e-8)
+    ud = ctx.vector("u")
+    ed = torch.empty(ctx.m, dtype=torch.float64, device="cuda")
+    ctx.element_energy(ud, ed)                # the kernel the DOC step uses
+    u, e = ud.cpu().numpy(), ed.cpu().numpy()
+    rho1 = ctx.vector("rho").cpu().numpy()
+    ctx.close()
+    r = fe.apply_K(P.grid, P.Ke, rho0, u) - P.f
+    assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(P.f)
+    eo = fe.element_energies(P.grid, P.Ke, u)
+    assert np.max(np.abs(e - eo)) <= 1e-12 * np.max(np.abs(eo))
+    cand = np.minimum(np.maximum(rho0 * (2.0 * e) ** q / s["alpha"], P.rho_lo), P.rho_hi)
+    assert np.max(np.abs(rho1 - cand)) <= 1e-12
+    assert abs(s["volume"] - rho1.sum()) <= 1e-9 * P.V
+    # the bisection stops at a relative bracket of tau: volume to about tau
+    assert abs(rho1.sum() - P.V) <= 3 * 0.1 * eps * P.V
+    assert s["compliance"] == pytest.approx(0.5 * float(P.f @ u), rel=1e-12)
