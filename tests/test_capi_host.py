@@ -125,3 +125,19 @@ def test_product_code_does_not_use_the_oracle():
             assert not list(oracle_imports(fn)), fn.name
     assert not [n for n in tree.body if isinstance(n, (ast.Import, ast.ImportFrom))
                 and list(oracle_imports(n))]
+
+
+def test_header_is_plain_c99(tmp_path):
+    """include/vts.h compiles as ISO C99 (no C++ or torch types cross the ABI)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "abi.c"
+    src.write_text('#include "vts.h"\nint main(void) { vts_options o; vts_default_options(&o);'
+                   ' return o.max_outer > 0 ? 0 : 1; }\n')
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                        "-I", os.path.join(ROOT, "include"), "-c", str(src), "-o",
+                        str(tmp_path / "abi.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
