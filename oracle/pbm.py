@@ -25,7 +25,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import fe
-from .penalty import phi, dphi, d2phi
+from .penalty import phi, dphi, d2phi, phi_diff
 
 
 # ----------------------------------------------------------------------------
@@ -192,18 +192,30 @@ def lagrangian(P: VTS, st: State) -> float:
             + np.sum(st.mu_hi * st.q_hi * phi(-st.nu_hi / st.q_hi)))
 
 
-def lagrangian_change(P: VTS, st: State, new: State) -> float:
-    """L(new) - L(st), eq. (3.9), summed term by term so that the difference
-    is not lost to cancellation between two large totals."""
-    e0 = fe.element_energies(P.grid, P.Ke, st.u)
-    e1 = fe.element_energies(P.grid, P.Ke, new.u)
-    s0 = (e0 - st.alpha + st.nu_lo - st.nu_hi) / st.p
-    s1 = (e1 - new.alpha + new.nu_lo - new.nu_hi) / st.p
-    lin = ((new.alpha - st.alpha) * P.V - P.f @ (new.u - st.u)
-           - P.rho_lo @ (new.nu_lo - st.nu_lo) + P.rho_hi @ (new.nu_hi - st.nu_hi))
-    pen = np.sum(st.rho * st.p * (phi(s1) - phi(s0)))
-    pen += np.sum(st.mu_lo * st.q_lo * (phi(-new.nu_lo / st.q_lo) - phi(-st.nu_lo / st.q_lo)))
-    pen += np.sum(st.mu_hi * st.q_hi * (phi(-new.nu_hi / st.q_hi) - phi(-st.nu_hi / st.q_hi)))
+def lagrangian_change(P: VTS, st: State, ev: Eval, du: np.ndarray, dalpha: float,
+                      dnl: np.ndarray, dnh: np.ndarray, kappa: float) -> float:
+    """L(xi + kappa dxi) - L(xi) of eq. (3.9) along the Newton direction
+    dxi = (du, dalpha, dnl, dnh), as the Armijo rule of Algorithm 2 needs it.
+
+    Every term is formed as a change along the ray, never as the difference
+    of two large totals: the element energy is quadratic in u, so exactly
+        e_i(u + kappa du) - e_i(u) = kappa b_i^T du_i + kappa^2 e_i(du),
+    with b_i = K_i u from the evaluation at xi; the arguments of phi change
+    by that amount (and by the alpha and nu steps) over p or q; phi's change
+    is taken from its branch-wise difference formula; the linear terms of
+    (3.9) change by kappa times their directional part.  Near the optimum
+    the decrease kappa * slope is far below the rounding of e_i(u), phi and
+    f^T u, and forming the two totals lets that rounding decide the Armijo
+    test."""
+    g = P.grid
+    c1 = np.einsum("ei,ei->e", ev.be, du[g.dofs])
+    c2 = fe.element_energies(g, P.Ke, du)
+    s0 = (ev.e - st.alpha + st.nu_lo - st.nu_hi) / st.p
+    ds = kappa * (c1 + kappa * c2 - dalpha + dnl - dnh) / st.p
+    lin = kappa * (dalpha * P.V - P.f @ du - P.rho_lo @ dnl + P.rho_hi @ dnh)
+    pen = np.sum(st.rho * st.p * phi_diff(s0, ds))
+    pen += np.sum(st.mu_lo * st.q_lo * phi_diff(-st.nu_lo / st.q_lo, -kappa * dnl / st.q_lo))
+    pen += np.sum(st.mu_hi * st.q_hi * phi_diff(-st.nu_hi / st.q_hi, -kappa * dnh / st.q_hi))
     return float(lin + pen)
 
 
@@ -436,18 +448,17 @@ class Solver:
                 self.status = "nondescent"
                 return st, ev
             kappa = 1.0
-            while True:
-                new = st.copy()
-                new.u = st.u + kappa * du
-                new.alpha = st.alpha + kappa * da
-                new.nu_lo = st.nu_lo + kappa * dnl
-                new.nu_hi = st.nu_hi + kappa * dnh
-                if lagrangian_change(P, st, new) <= o.armijo_c1 * kappa * slope:
-                    break
+            while lagrangian_change(P, st, ev, du, da, dnl, dnh, kappa) > \
+                    o.armijo_c1 * kappa * slope:
                 kappa *= 0.5
                 if kappa < o.armijo_min:
                     self.status = "linesearch"
                     return st, ev
+            new = st.copy()
+            new.u = st.u + kappa * du
+            new.alpha = st.alpha + kappa * da
+            new.nu_lo = st.nu_lo + kappa * dnl
+            new.nu_hi = st.nu_hi + kappa * dnh
             st = new
             ev = evaluate(P, st)
             res = res_pbm(P, ev)

@@ -35,3 +35,21 @@ def d2phi(t, that: float = TAU_HAT):
     a = (1.0 + that) ** 2
     den = np.where(t < that, 1.0 + 2.0 * that - t, 1.0)
     return np.where(t >= that, np.ones_like(t), a / (den * den))
+
+
+def phi_diff(t, dt, that: float = TAU_HAT):
+    """phi(t + dt) - phi(t) formed without subtracting two values of phi
+    where both points lie on one branch: dt (1 + t + dt/2) on the quadratic
+    branch, -(1+t_hat)^2 log1p(-dt / (1 + 2 t_hat - t)) on the logarithmic
+    one (both exact rearrangements of eq. (3.8)); points on different
+    branches take the plain difference."""
+    t = np.asarray(t, dtype=np.float64)
+    dt = np.asarray(dt, dtype=np.float64)
+    t1 = t + dt
+    a = (1.0 + that) ** 2
+    quad = dt * (1.0 + t + 0.5 * dt)
+    both_log = (t < that) & (t1 < that)
+    den = np.where(both_log, 1.0 + 2.0 * that - t, 1.0)
+    logd = -a * np.log1p(np.where(both_log, -dt / den, 0.0))
+    plain = phi(t1, that) - phi(t, that)
+    return np.where((t >= that) & (t1 >= that), quad, np.where(both_log, logd, plain))

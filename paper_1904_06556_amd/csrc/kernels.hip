@@ -36,6 +36,14 @@ __device__ __forceinline__ double pen_dphi(double t) {
 __device__ __forceinline__ double pen_d2phi(double t) {
     return t >= -0.5 ? 1.0 : 0.25 / (t * t);
 }
+// phi(t + dt) - phi(t) without subtracting two values of phi when both points
+// lie on one branch: dt (1 + t + dt/2) (quadratic), -1/4 log1p(dt/t) (log)
+__device__ __forceinline__ double pen_phi_diff(double t, double dt) {
+    const double t1 = t + dt;
+    if (t >= -0.5 && t1 >= -0.5) return dt * (1.0 + t + 0.5 * dt);
+    if (t < -0.5 && t1 < -0.5) return -0.25 * log1p(dt / t);
+    return pen_phi(t1) - pen_phi(t);
+}
 
 // block-wide sum of NQ values per thread; thread 0 writes partials[q*kRedBlocks + block]
 template <int NQ>
@@ -490,9 +498,12 @@ void launch_dnu(Ctx& c) {
                        (int)SL_SLOPE_NU, 0u, c.red);
 }
 
-// Elementwise part of L(xi + k dxi) - L(xi), eq. (3.9), summed term by term:
-//   rho p (phi(s+) - phi(s)) + mu_lo q_lo (phi(t_lo+) - phi(t_lo)) + ...
+// Elementwise part of L(xi + k dxi) - L(xi), eq. (3.9), formed along the ray:
+// the argument of each phi changes by k (c1 + k c2 - dalpha + dnu_lo - dnu_hi)/p
+// (resp. -k dnu/q), phi's change comes from its branch-wise difference, and
+//   rho p dphi(s) + mu_lo q_lo dphi(t_lo) + mu_hi q_hi dphi(t_hi)
 //   - k rho_lo dnu_lo + k rho_hi dnu_hi
+// is summed; the linear terms in alpha and u are added on the host.
 struct LsArgs {
     int64_t m;
     double kappa, alpha, dalpha;
@@ -506,15 +517,13 @@ __global__ void __launch_bounds__(kThreads) k_linesearch(LsArgs a) {
     const double k = a.kappa;
     for (int64_t e = gid(); e < a.m; e += (int64_t)gridDim.x * blockDim.x) {
         const double pe = a.p[e], ql = a.qlo[e], qh = a.qhi[e];
-        const double e0 = a.e[e], e1 = e0 + k * a.c1[e] + k * k * a.c2[e];
-        const double nl0 = a.nlo[e], nh0 = a.nhi[e];
-        const double nl1 = nl0 + k * a.dnl[e], nh1 = nh0 + k * a.dnh[e];
-        const double s0 = (e0 - a.alpha + nl0 - nh0) / pe;
-        const double s1 = (e1 - (a.alpha + k * a.dalpha) + nl1 - nh1) / pe;
-        double v = a.rho[e] * pe * (pen_phi(s1) - pen_phi(s0));
-        v += a.mlo[e] * ql * (pen_phi(-nl1 / ql) - pen_phi(-nl0 / ql));
-        v += a.mhi[e] * qh * (pen_phi(-nh1 / qh) - pen_phi(-nh0 / qh));
-        v += -a.rlo[e] * (nl1 - nl0) + a.rhi[e] * (nh1 - nh0);
+        const double nl0 = a.nlo[e], nh0 = a.nhi[e], dl = a.dnl[e], dh = a.dnh[e];
+        const double s0 = (a.e[e] - a.alpha + nl0 - nh0) / pe;
+        const double ds = k * (a.c1[e] + k * a.c2[e] - a.dalpha + dl - dh) / pe;
+        double v = a.rho[e] * pe * pen_phi_diff(s0, ds);
+        v += a.mlo[e] * ql * pen_phi_diff(-nl0 / ql, -k * dl / ql);
+        v += a.mhi[e] * qh * pen_phi_diff(-nh0 / qh, -k * dh / qh);
+        v += k * (-a.rlo[e] * dl + a.rhi[e] * dh);
         acc[0] += v;
     }
     block_sum_store<1>(acc, a.partials, SL_LS);

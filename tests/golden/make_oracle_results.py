@@ -1,7 +1,8 @@
 """Writes tests/golden/oracle_<workload>.json: the FP64 oracle's PBM result on
 a benchmark workload (compliance 1/2 f^T u, exact compliance of the final
 density by a sparse direct solve, KKT terms, duality certificate, iteration
-counts).  Calls only oracle/ and workloads/; the GPU path is not involved.
+counts and the per-step logs of Algorithms 1 and 2).  Calls only oracle/ and
+workloads/; the GPU path is not involved.
 
     python tests/golden/make_oracle_results.py 1        # the 64x32x32 cantilever
 
@@ -39,7 +40,8 @@ def main(idx: int):
                alpha=float(st.alpha), sum_rho=float(st.rho.sum()), V=P.V,
                outer=len(s.log.outer), newton=len(s.log.newton),
                minres=int(sum(d["minres"] for d in s.log.newton)),
-               options={k: getattr(opts, k) for k in vars(opts)}, **r)
+               options={k: getattr(opts, k) for k in vars(opts)},
+               newton_log=s.log.newton, outer_log=s.log.outer, **r)
     path = os.path.join(HERE, f"oracle_{pr.name}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)

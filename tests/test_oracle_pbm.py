@@ -38,6 +38,16 @@ def test_phi_derivatives_by_finite_differences():
     assert np.allclose(phi(tl), -0.25 * np.log(-2 * tl) - 0.375, rtol=1e-15)
 
 
+def test_phi_diff_matches_plain_difference_and_first_order():
+    from oracle.penalty import phi_diff
+    t = np.array([-40.0, -3.0, -0.7, -0.51, -0.49, -0.3, 0.0, 0.3, 5.0])
+    for dt in (0.4, -0.2, 1e-3, -1e-3):
+        assert np.allclose(phi_diff(t, dt), phi(t + dt) - phi(t), rtol=1e-12, atol=1e-15)
+    # tiny steps on each branch: the change is phi'(t) dt to second order
+    dt = 1e-12
+    assert np.allclose(phi_diff(t, dt), dphi(t) * dt, rtol=1e-9, atol=0)
+
+
 # ------------------------------------------------------------- helpers
 def _tiny(rho_lo=1e-3, seed=0):
     pr = W.cantilever_edge(2, 1, 1, 1, vol_frac=0.4, rho_lo=rho_lo)
@@ -172,13 +182,47 @@ def test_schur_weight_is_harmonic_combination():
 
 
 def test_lagrangian_change_matches_difference():
+    # the change along the Newton ray (Armijo rule of Algorithm 2) equals the
+    # literal difference of eq. (3.9) at the two points
     P, st = _tiny(seed=9)
+    ev = pbm.evaluate(P, st)
+    rng = np.random.default_rng(2)
+    du = P.grid.mask(rng.standard_normal(P.grid.n_dof))
+    da = 0.3
+    dnl = 0.1 * rng.standard_normal(P.grid.m)
+    dnh = 0.1 * rng.standard_normal(P.grid.m)
+    for kappa in (1.0, 0.25, 0.01):
+        new = st.copy()
+        new.u = st.u + kappa * du
+        new.alpha += kappa * da
+        new.nu_lo = st.nu_lo + kappa * dnl
+        new.nu_hi = st.nu_hi + kappa * dnh
+        d = pbm.lagrangian_change(P, st, ev, du, da, dnl, dnh, kappa)
+        assert np.isclose(d, pbm.lagrangian(P, new) - pbm.lagrangian(P, st), rtol=1e-9, atol=1e-12)
+
+
+def test_lagrangian_change_is_exact_where_totals_cancel():
+    # a tiny step: the change along the ray keeps the first-order term
+    # kappa * grad L^T dxi (eq. (3.10)) to near machine precision, while the
+    # difference of the two totals of eq. (3.9) loses most of its digits
+    P, st = _tiny(seed=9)
+    ev = pbm.evaluate(P, st)
+    rng = np.random.default_rng(3)
+    du = P.grid.mask(rng.standard_normal(P.grid.n_dof))
+    da = 0.2
+    dnl = 0.1 * rng.standard_normal(P.grid.m)
+    dnh = 0.1 * rng.standard_normal(P.grid.m)
+    slope = float(ev.g1 @ du + ev.g2 * da + ev.g3 @ dnl + ev.g4 @ dnh)
+    kappa = 1e-11
+    d = pbm.lagrangian_change(P, st, ev, du, da, dnl, dnh, kappa)
+    assert abs(d - kappa * slope) <= 1e-7 * abs(kappa * slope)
     new = st.copy()
-    new.u = st.u + 0.01 * P.grid.mask(np.random.default_rng(2).standard_normal(P.grid.n_dof))
-    new.alpha += 0.003
-    new.nu_lo = st.nu_lo * 1.01
-    d = pbm.lagrangian_change(P, st, new)
-    assert np.isclose(d, pbm.lagrangian(P, new) - pbm.lagrangian(P, st), rtol=1e-9, atol=1e-12)
+    new.u = st.u + kappa * du
+    new.alpha += kappa * da
+    new.nu_lo = st.nu_lo + kappa * dnl
+    new.nu_hi = st.nu_hi + kappa * dnh
+    lit = pbm.lagrangian(P, new) - pbm.lagrangian(P, st)
+    assert abs(lit - kappa * slope) > 10 * abs(d - kappa * slope)
 
 
 # --------------------------------------------------------- gap (2.6)
