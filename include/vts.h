@@ -276,9 +276,14 @@ vts_status vts_profile_stop(vts_ctx* ctx, double* total_ms, int64_t* launches,
                             double* bytes);
 
 /* Checkpoint of the PBM state to host memory, layout (FP64):
+ *   header {5657683 (magic), 2 (layout version), n_dof, m},
  *   u[n_dof], alpha, nu_lo[m], nu_hi[m], rho[m], mu_lo[m], mu_hi[m],
- *   p[m], q_lo[m], q_hi[m], eps_nwt, eps_mr
- * *bytes: in = capacity of host_buf (or 0 to query), out = size needed. */
+ *   p[m], q_lo[m], q_hi[m], eps_nwt, eps_mr,
+ *   outer iterations, Newton steps, MINRES iterations (the run's counters,
+ *   so that a resumed run keeps its budgets and totals)
+ * *bytes: in = capacity of host_buf (or 0 to query), out = size needed.
+ * vts_set_state gives VTS_EINVAL for a wrong size, a header that does not
+ * match the context, or counters that are not non-negative integers. */
 vts_status vts_get_state(const vts_ctx* ctx, void* host_buf, size_t* bytes);
 vts_status vts_set_state(vts_ctx* ctx, const void* host_buf, size_t bytes);
 

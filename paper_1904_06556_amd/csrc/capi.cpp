@@ -1149,7 +1149,10 @@ vts_status vts_pbm_solve(vts_ctx* cp, vts_result* res) {
     vts_newtonstats ns{};
     if (st == VTS_OK) {
         st = newton(c, c.opt.eps_nwt_final, true, &ns, nullptr);
-        if (st != VTS_OK && c.res_prev >= 0 && c.res_prev < c.opt.accept_stall) st = VTS_OK;
+        // a stalled final Newton (no progress, or no descent step) is accepted
+        // near the optimum; device, argument and definiteness errors never are
+        const bool stall = st == VTS_ENOTCONV || st == VTS_ENONDESCENT;
+        if (stall && c.res_prev >= 0 && c.res_prev < c.opt.accept_stall) st = VTS_OK;
         // the last accepted state was evaluated; make sure of it before the rho update
         if (!c.eval_valid) {
             vts_status s2 = evaluate(c);
@@ -1317,15 +1320,29 @@ vts_status vts_get_vector(const vts_ctx* cp, int32_t which, double* dst) {
     return VTS_OK;
 }
 
+// checkpoint layout (FP64): header {magic, version, n_dof, m}, u, alpha, the
+// eight m-vectors, eps_nwt, eps_mr, and the outer / Newton / MINRES counters
+constexpr double kStateMagic = 5657683.0;   // "VTS" as a number
+constexpr double kStateVersion = 2.0;
+constexpr int kStateHead = 4, kStateTail = 5;
+
+size_t state_bytes(const Ctx& c) {
+    return (size_t)(kStateHead + c.ndof + 1 + 8 * c.m + kStateTail) * 8;
+}
+
 vts_status vts_get_state(const vts_ctx* cp, void* buf, size_t* bytes) {
     if (!cp || !bytes) return VTS_EINVAL;
     Ctx& c = const_cast<vts_ctx&>(*cp);
-    const size_t need = (size_t)(c.ndof + 1 + 8 * c.m + 2) * 8;
+    const size_t need = state_bytes(c);
     if (!buf || *bytes < need) {
         *bytes = need;
         return buf ? VTS_EINVAL : VTS_OK;
     }
     double* b = (double*)buf;
+    *b++ = kStateMagic;
+    *b++ = kStateVersion;
+    *b++ = (double)c.ndof;
+    *b++ = (double)c.m;
     HIPCHK(hipMemcpyAsync(b, c.u, c.ndof * 8, hipMemcpyDeviceToHost, c.s));
     b += c.ndof;
     *b++ = c.alpha;
@@ -1336,6 +1353,9 @@ vts_status vts_get_state(const vts_ctx* cp, void* buf, size_t* bytes) {
     }
     *b++ = c.eps_nwt;
     *b++ = c.eps_mr;
+    *b++ = (double)c.outer;
+    *b++ = (double)c.newton_total;
+    *b++ = (double)c.minres_total;
     HIPCHK(hipStreamSynchronize(c.s));
     *bytes = need;
     return VTS_OK;
@@ -1344,9 +1364,21 @@ vts_status vts_get_state(const vts_ctx* cp, void* buf, size_t* bytes) {
 vts_status vts_set_state(vts_ctx* cp, const void* buf, size_t bytes) {
     if (!cp || !buf) return VTS_EINVAL;
     Ctx& c = *cp;
-    const size_t need = (size_t)(c.ndof + 1 + 8 * c.m + 2) * 8;
+    const size_t need = state_bytes(c);
     if (bytes != need) { c.err = "state size mismatch"; return VTS_EINVAL; }
     const double* b = (const double*)buf;
+    if (b[0] != kStateMagic || b[1] != kStateVersion || b[2] != (double)c.ndof ||
+        b[3] != (double)c.m) {
+        c.err = "state header does not match this context (magic, version, n_dof, m)";
+        return VTS_EINVAL;
+    }
+    const double* t = b + kStateHead + c.ndof + 1 + 8 * c.m;
+    for (int q = 2; q < kStateTail; ++q)
+        if (!(t[q] >= 0 && t[q] < 2147483647.0 && t[q] == std::floor(t[q]))) {
+            c.err = "state counters out of range";
+            return VTS_EINVAL;
+        }
+    b += kStateHead;
     HIPCHK(hipMemcpyAsync(c.u, b, c.ndof * 8, hipMemcpyHostToDevice, c.s));
     b += c.ndof;
     c.alpha = *b++;
@@ -1357,6 +1389,9 @@ vts_status vts_set_state(vts_ctx* cp, const void* buf, size_t bytes) {
     }
     c.eps_nwt = *b++;
     c.eps_mr = *b++;
+    c.outer = (int)*b++;
+    c.newton_total = (int)*b++;
+    c.minres_total = (int)*b++;
     HIPCHK(hipStreamSynchronize(c.s));
     launch_round_rho(c);
     c.eval_valid = false;

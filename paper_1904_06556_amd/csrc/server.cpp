@@ -6,6 +6,8 @@
 // range; admitted requests overlap on the device through their streams.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -204,7 +206,7 @@ vts_status vts_server_create(int32_t slots, size_t hbm_bytes, vts_server** out) 
 }
 
 vts_status vts_server_submit(vts_server* S, const vts_problem* pr, const vts_options* opt,
-                             int64_t* id) {
+                             int64_t* id) try {
     if (!S || !pr || !id) return VTS_EINVAL;
     std::string err;
     if (check_problem(pr, err) != VTS_OK) return VTS_EINVAL;
@@ -238,6 +240,8 @@ vts_status vts_server_submit(vts_server* S, const vts_problem* pr, const vts_opt
     }
     S->cv_work.notify_all();
     return VTS_OK;
+} catch (...) {
+    return VTS_ENOMEM;   // host copies of the request could not be allocated
 }
 
 int32_t vts_server_poll(vts_server* S, vts_request_info* out, int32_t max, double timeout_s) {
@@ -250,7 +254,8 @@ int32_t vts_server_poll(vts_server* S, vts_request_info* out, int32_t max, doubl
     while (n < max && !S->unpolled.empty()) {
         const int64_t id = S->unpolled.front();
         S->unpolled.pop_front();
-        out[n++] = S->finished.at(id).info;
+        auto it = S->finished.find(id);
+        if (it != S->finished.end()) out[n++] = it->second.info;   // else fetched already
     }
     return n;
 }
@@ -264,6 +269,9 @@ vts_status vts_server_fetch(vts_server* S, int64_t id, double* rho_host, double*
     if (rho_host) std::copy(f.rho.begin(), f.rho.end(), rho_host);
     if (u_host) std::copy(f.u.begin(), f.u.end(), u_host);
     S->finished.erase(it);
+    // a request fetched before it was polled is not reported by a later poll
+    auto up = std::find(S->unpolled.begin(), S->unpolled.end(), id);
+    if (up != S->unpolled.end()) S->unpolled.erase(up);
     return VTS_OK;
 }
 

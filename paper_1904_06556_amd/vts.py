@@ -21,6 +21,8 @@ VTS_OK, VTS_EINVAL, VTS_ENOMEM, VTS_EDEVICE, VTS_ESTATE, VTS_ENOTCONV, \
 STATUS_NAMES = {0: "VTS_OK", 1: "VTS_EINVAL", 2: "VTS_ENOMEM", 3: "VTS_EDEVICE",
                 4: "VTS_ESTATE", 5: "VTS_ENOTCONV", 6: "VTS_ENONDESCENT", 7: "VTS_ENONSPD"}
 VTS_FP64, VTS_MIXED = 0, 1
+# checkpoint header (vts_get_state): magic, layout version, n_dof, m
+STATE_MAGIC, STATE_VERSION, STATE_HEAD = 5657683.0, 2.0, 4
 
 PROF = dict(gs_fine=1, apply_K=2, apply_S=3)
 VEC = dict(u=0, rho=1, energy=2, rhs=3, dy=4, g1=5, dnu_lo=6, dnu_hi=7, rho1=8, w=9)
@@ -434,20 +436,26 @@ class Context:
         """Unpacks get_state() by the layout documented in vts.h."""
         b = self.get_state()
         nd, m = self.n_dof, self.m
-        out = {"u": b[:nd], "alpha": b[nd]}
-        o = nd + 1
+        o = STATE_HEAD
+        out = {"u": b[o:o + nd], "alpha": b[o + nd]}
+        o += nd + 1
         for name in ("nu_lo", "nu_hi", "rho", "mu_lo", "mu_hi", "p", "q_lo", "q_hi"):
             out[name] = b[o:o + m]
             o += m
         out["eps_nwt"], out["eps_mr"] = b[o], b[o + 1]
+        out["outer"], out["newton"], out["minres"] = (int(b[o + 2]), int(b[o + 3]),
+                                                      int(b[o + 4]))
         return out
 
     @staticmethod
     def pack_state(d, n_dof, m):
-        parts = [np.asarray(d["u"], float), [d["alpha"]]]
+        """Packs a state dict into the checkpoint layout; the counters
+        (outer, newton, minres) default to 0."""
+        parts = [[STATE_MAGIC, STATE_VERSION, n_dof, m], np.asarray(d["u"], float), [d["alpha"]]]
         for name in ("nu_lo", "nu_hi", "rho", "mu_lo", "mu_hi", "p", "q_lo", "q_hi"):
             parts.append(np.asarray(d[name], float))
-        parts.append([d["eps_nwt"], d["eps_mr"]])
+        parts.append([d["eps_nwt"], d["eps_mr"], d.get("outer", 0), d.get("newton", 0),
+                      d.get("minres", 0)])
         return np.concatenate(parts)
 
 

@@ -82,6 +82,16 @@ def test_rejects_supports_not_nested_across_levels():
     _expect(V.VTS_EINVAL, lambda: _create(pr))
 
 
+def test_rejects_non_finite_load():
+    pr = W.cantilever_edge(8, 4, 4, 3)
+    f = pr.f.copy()
+    f[3 * 10 + 1] = np.nan
+    pr.f = f
+    _expect(V.VTS_EINVAL, lambda: _create(pr))
+    f[3 * 10 + 1] = np.inf
+    _expect(V.VTS_EINVAL, lambda: _create(pr))
+
+
 def test_rejects_too_large_coarsest_level():
     pr = W.cantilever_edge(32, 16, 16, 1)
     _expect(V.VTS_EINVAL, lambda: _create(pr))
@@ -91,7 +101,12 @@ def test_state_layout_roundtrip_pack():
     d = dict(u=np.arange(6.0), alpha=2.0, nu_lo=[1.0], nu_hi=[2.0], rho=[3.0], mu_lo=[4.0],
              mu_hi=[5.0], p=[6.0], q_lo=[7.0], q_hi=[8.0], eps_nwt=0.5, eps_mr=1e-3)
     b = V.Context.pack_state(d, 6, 1)
-    assert b.size == 6 + 1 + 8 + 2 and b[6] == 2.0 and b[-1] == 1e-3
+    h = V.STATE_HEAD
+    assert b.size == h + 6 + 1 + 8 + 2 + 3 and b[h + 6] == 2.0 and b[h + 6 + 1 + 8 + 1] == 1e-3
+    assert list(b[:h]) == [V.STATE_MAGIC, V.STATE_VERSION, 6, 1]
+    assert list(b[-3:]) == [0, 0, 0]
+    d.update(outer=7, newton=11, minres=123)
+    assert list(V.Context.pack_state(d, 6, 1)[-3:]) == [7, 11, 123]
 
 
 def test_bench_refuses_more_than_one_gpu():

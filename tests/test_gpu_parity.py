@@ -283,6 +283,15 @@ def test_checkpoint_roundtrip():
     b = ctx.pbm_iterate()
     assert np.array_equal(ctx.get_state(), s2)
     assert a["gap"] == b["gap"]
+    # resumed in a fresh context: same iterate and the run's counters
+    fresh = V.Context.from_problem(pr, precision=V.VTS_FP64)
+    fresh.set_state(s1)
+    c = fresh.pbm_iterate()
+    assert np.array_equal(fresh.get_state(), s2)
+    assert c["gap"] == a["gap"]
+    d = fresh.state_dict()
+    assert d["outer"] == 2 and d["newton"] > 0 and d["minres"] > 0
+    fresh.close()
     ctx.close()
 
 

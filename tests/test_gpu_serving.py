@@ -111,3 +111,25 @@ def test_group_step_equals_single_steps():
         assert np.array_equal(g.get_state(), c.get_state())
         g.close()
         c.close()
+
+
+def test_fetch_before_poll():
+    # a finished request may be fetched before any poll has reported it; the
+    # next poll then reports only the others
+    import time
+    probs = [W.cantilever_edge(8, 4, 4, 3, vol_frac=0.3), W.cantilever_edge(8, 4, 4, 3, vol_frac=0.35)]
+    srv = V.Server(2, 1 << 30)
+    ids = [srv.submit(p, precision=V.VTS_FP64) for p in probs]
+    say("fetch before poll", ids)
+    t0 = time.time()
+    while srv.counts()["finished"] < 2:
+        assert time.time() - t0 < 60, srv.counts()
+        time.sleep(0.05)
+    rho, u = srv.fetch(ids[0], probs[0].m, probs[0].n_dof)
+    assert np.all(np.isfinite(rho)) and np.all(np.isfinite(u))
+    infos = srv.poll(timeout_s=1.0)
+    assert [i["id"] for i in infos] == [ids[1]]
+    with pytest.raises(V.VtsError):
+        srv.fetch(ids[0], probs[0].m, probs[0].n_dof)
+    srv.fetch(ids[1], probs[1].m, probs[1].n_dof)
+    srv.close()
