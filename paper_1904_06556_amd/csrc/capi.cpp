@@ -125,7 +125,7 @@ Plan make_plan(const vts_problem* pr) {
     const int64_t nn = nodes_of(d), ndof = 3 * nn, m = (int64_t)d.nx * d.ny * d.nz;
     auto add = [&](size_t b) { p.bytes.push_back(b); };
     add(576 * 8); add(576 * 4); add(8 * 576 * 8); add(512 * 8);     // Ke, Kef, Mc, Qc
-    add(ndof); add(ndof * 8);                                        // fixed, f
+    add(ndof); add(nn); add(ndof * 8);                               // fixed, nmask, f
     add(m * 8); add(m * 8);                                          // bounds
     add(ndof * 8);                                                   // u
     for (int q = 0; q < 8; ++q) add(m * 8);                          // nlo..qhi
@@ -859,8 +859,13 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
     HIPCHK(hipMemcpyAsync(c.Mc, Mc, sizeof(Mc), hipMemcpyHostToDevice, c.s));
     HIPCHK(hipMemcpyAsync(c.Qc, Q, sizeof(Q), hipMemcpyHostToDevice, c.s));
 
-    ALLOC(c.fixed, c.ndof); ALLOC(c.f, c.ndof); ALLOC(c.rlo, c.m); ALLOC(c.rhi, c.m);
+    ALLOC(c.fixed, c.ndof); ALLOC(c.nmask, c.nn); ALLOC(c.f, c.ndof); ALLOC(c.rlo, c.m);
+    ALLOC(c.rhi, c.m);
     HIPCHK(hipMemcpyAsync(c.fixed, mask.data(), c.ndof, hipMemcpyHostToDevice, c.s));
+    std::vector<uint8_t> nmask(c.nn);
+    for (int64_t q = 0; q < c.nn; ++q)
+        nmask[q] = (uint8_t)(mask[3 * q] | (mask[3 * q + 1] << 1) | (mask[3 * q + 2] << 2));
+    HIPCHK(hipMemcpyAsync(c.nmask, nmask.data(), c.nn, hipMemcpyHostToDevice, c.s));
     HIPCHK(hipMemcpyAsync(c.f, f.data(), c.ndof * 8, hipMemcpyHostToDevice, c.s));
     HIPCHK(hipMemcpyAsync(c.rlo, lo.data(), c.m * 8, hipMemcpyHostToDevice, c.s));
     HIPCHK(hipMemcpyAsync(c.rhi, hi.data(), c.m * 8, hipMemcpyHostToDevice, c.s));

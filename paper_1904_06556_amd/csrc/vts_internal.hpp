@@ -76,6 +76,7 @@ struct Ctx {
 
     // problem data (device)
     uint8_t* fixed = nullptr;    // ndof
+    uint8_t* nmask = nullptr;    // nn: bit c set if DOF 3 node + c is fixed
     double* f = nullptr;         // ndof
     double* rlo = nullptr;       // m
     double* rhi = nullptr;       // m
