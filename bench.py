@@ -1,18 +1,24 @@
 """Benchmark of the PBM + multigrid-MINRES hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload N]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-A step is one complete PBM solve (Algorithm 1 with its Newton method,
-Algorithm 2, and MINRES preconditioned by one V-cycle) of the workload from
-the initial point to a KKT residual of 1e-6; every row of the hot path runs
-in each step.  Inputs (grid, supports, loads, bounds) are resident on the
-device before the timed region; each step re-initializes the PBM state on the
-device (vts_reset) and solves.
+Default run: the 192x96x96 cantilever with three point loads (5.4 M DOFs, the
+largest single-GPU workload).  A step is one pass of the whole hot path on
+it: one outer iteration of Algorithm 1 in mixed precision (evaluation,
+gradient and reduced right-hand side, multigrid setup, MINRES preconditioned
+by one V-cycle per iteration, Newton completion and Armijo search, multiplier
+and penalty update) and K(rho)u in FP64 on a batch of at least 8 independent
+(x, y, rho) sets (more than 1 GB, beyond the 256 MB Infinity Cache).  Inputs
+are resident on the device before the timed region.
 
-Printed: one JSON line with the throughput (VTS solves per second, i.e.
-1/time-to-KKT), the K(rho)u and MINRES-MG rates, the roofline figures of the
-dominant kernel measured with HIP events, and the CPU oracle timed on a
-bounded sample of the same workload.
+Printed: one JSON line.  value = K(rho)u throughput in GDOF/s over every
+launch in the timed region (HIP events on the library's stream), with its
+roofline against the compulsory bytes (read x and rho, write y); the hot
+path's rates (outer iterations, MINRES-MG iterations per second), MINRES-MG
+at a fixed Newton point in FP64 and mixed precision, time-to-KKT of the
+64x32x32 cantilever in FP64 and mixed, and the CPU oracle's K(rho)u on the
+same workload.  Other modes (--solve, --serve, --doc, --ip, --paper, --scale,
+--scale-kernels, --kernels) are listed by --help.
 """
 from __future__ import annotations
 
@@ -35,10 +41,14 @@ METRIC = "K(rho)u GDOF/s + MINRES-MG iters/s; time-to-KKT 1e-6 per VTS; p50/p99"
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", type=int, default=1,
-                    help="0: cantilever 8x4x4, 1: cantilever 64x32x32 (default)")
+                    help="--solve / --kernels: 0 cantilever 8x4x4, 1 cantilever 64x32x32, "
+                         "2 bridge 128x64x64, 3 cantilever 192x96x96 (three point loads)")
+    ap.add_argument("--solve", action="store_true",
+                    help="time-to-KKT: complete PBM solves of --workload from the initial "
+                         "point, --steps timed after --warmup")
     ap.add_argument("--precision", choices=["config", "fp64", "mixed"], default="config",
                     help="override the workload's precision (mixed: FP32 multigrid)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -210,12 +220,19 @@ def kernels_only(a, torch, W, V):
     g = torch.Generator(device="cpu").manual_seed(1)
     r = (torch.rand(ctx.n_dof + 1, generator=g, dtype=torch.float64) - 0.5).cuda()
     z = torch.empty_like(r)
-    x = (torch.rand(ctx.n_dof, generator=g, dtype=torch.float64) - 0.5).cuda()
-    y = torch.empty_like(x)
+    # K(rho)x on rotating (x, y, rho) sets beyond the Infinity Cache, as timed
+    # by the default run
+    k_bytes = 16.0 * ctx.n_dof + 8.0 * ctx.m
+    nsets = max(8, int(math.ceil(K_SET_BYTES / k_bytes)))
+    xs = [(torch.rand(ctx.n_dof, generator=g, dtype=torch.float64) - 0.5).cuda()
+          for _ in range(nsets)]
+    rs = [(1e-3 + torch.rand(ctx.m, generator=g, dtype=torch.float64)).cuda()
+          for _ in range(nsets)]
+    ys = [torch.empty_like(xs[0]) for _ in range(nsets)]
     for _ in range(a.reps):
         ctx.precondition(r, z)
-    for _ in range(a.reps):
-        ctx.apply_K(x, y)
+    for q in range(a.reps * nsets):
+        ctx.apply_K_rho(rs[q % nsets], xs[q % nsets], ys[q % nsets])
     for _ in range(a.reps):
         ctx.apply_S(r, z)
     copy_bytes = 256 << 20
@@ -225,6 +242,8 @@ def kernels_only(a, torch, W, V):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"mode": "kernels", "workload": pr.name, "reps": a.reps,
+                      "k_sets": nsets, "k_launches": a.reps * nsets, "k_bytes": k_bytes,
+                      "operator_source_sha256_16": operator_source_hash(),
                       "n_dof": ctx.n_dof, "m": ctx.m,
                       "copy_bytes_read": copy_bytes, "copy_bytes_written": copy_bytes}),
           flush=True)
@@ -644,32 +663,9 @@ def serving(a, torch, W, V):
     return 0
 
 
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print(f"bench.py measures one GPU: --gpus {a.gpus} is not supported "
-              f"(the path runs on one GPU; there is no multi-GPU code)", file=sys.stderr)
-        return 2
-    import torch
-    import workloads as W
-    from paper_1904_06556_amd import vts as V
-
-    if a.kernels:
-        return kernels_only(a, torch, W, V)
-    if a.serve:
-        return serving(a, torch, W, V)
-    if a.doc:
-        return doc_compare(a, torch, W, V)
-    if a.scale_kernels:
-        return scaling_kernels(a, torch, W, V)
-    if a.scale:
-        return scaling_run(a, torch, W, V)
-    if a.paper and a.ip:
-        return paper_problems_ip(a, torch, W, V)
-    if a.ip:
-        return ip_compare(a, torch, W, V)
-    if a.paper:
-        return paper_problems(a, torch, W, V)
+def solve_run(a, torch, W, V):
+    """Time-to-KKT of complete PBM solves of --workload (the initial point
+    re-set on the device before each solve)."""
     pr = W.config(a.workload)
     eps_mr0 = pr.extra.get("eps_mr0")
     opts = V.default_options()
@@ -760,6 +756,251 @@ def main():
     print(json.dumps(line), flush=True)
     ctx.close()
     return 0
+
+
+HEADLINE_WORKLOAD = 3      # cantilever 192x96x96, three point loads, mixed precision
+K_SET_BYTES = 1.0e9        # rotating K(rho)u sets: more than the 256 MB Infinity Cache
+TRAFFIC_K_FILE = os.path.join(ROOT, "profiles", "traffic_pmc_k_apply_cant3pt-192x96x96.md")
+
+
+def operator_source_hash():
+    """Hash of the operator kernels' source (the K(rho)u counters stay valid
+    while it is unchanged)."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1904_06556_amd", "csrc", "operator.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_k_traffic():
+    """HBM bytes per K(rho)u launch at 192x96x96 from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (copy-scaled); None if the
+    operator source changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_K_FILE):
+        return None
+    val, src = None, None
+    with open(TRAFFIC_K_FILE) as fh:
+        for line in fh:
+            if line.startswith("traffic_bytes_per_launch k_apply_K_plane<double>"):
+                val = float(line.split("=")[1])
+            elif line.startswith("operator_source_sha256_16"):
+                src = line.split("=")[1].strip()
+    return val if (val is not None and src == operator_source_hash()) else None
+
+
+def cpu_baseline_k_apply(pr, budget_s):
+    """The FP64 oracle's K(rho)u (element gather, dense 24x24 element
+    products, scatter by bincount) on the same grid, repeated for about
+    budget_s seconds on the host cores."""
+    from oracle import fe
+    g = fe.Grid(pr.nx, pr.ny, pr.nz, pr.fixed)
+    Ke = fe.element_stiffness(pr.E, pr.nu, pr.h)
+    import workloads as W
+    rho = W.random_rho(pr.m, seed=1)
+    x = W.random_vector(pr.n_dof, seed=2)
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((d.get("num_threads") or 1) for d in threadpool_info()) or None
+    except Exception:
+        pass
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        fe.apply_K(g, Ke, rho, x)
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = (time.perf_counter() - t0) / n
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except Exception:
+        avail = os.cpu_count()
+    return dict(value=pr.n_dof / dt / 1e9, unit="GDOF/s (K(rho)u, FP64)",
+                cores=threads or 1, cores_available=avail, kind="oracle",
+                seconds_per_apply=dt, applications=n,
+                sample=(f"{n} applications of the oracle's K(rho)u (gather, 24x24 element "
+                        f"products through BLAS with {threads or 1} threads, bincount "
+                        f"scatter on one thread) on the same {pr.name} grid, random x and "
+                        f"rho"))
+
+
+def headline(a, torch, W, V):
+    """Default run: the 192x96x96 three-load cantilever.  A step is one outer
+    PBM iteration (mixed precision) plus K(rho)u on the rotating FP64 sets."""
+    pr = W.config(HEADLINE_WORKLOAD)
+    stream = torch.cuda.Stream()
+    opts = V.default_options()
+    ctx = V.Context.from_problem(pr, precision=V.VTS_MIXED, options=opts, stream=stream)
+    ctxk = V.Context.from_problem(pr, precision=V.VTS_FP64, options=opts, stream=stream)
+    nd, m = ctx.n_dof, ctx.m
+    k_bytes = 16.0 * nd + 8.0 * m          # read x and rho, write y (8 B each)
+    nsets = max(8, int(math.ceil(K_SET_BYTES / k_bytes)))
+    gen = torch.Generator(device="cpu").manual_seed(1)
+    xs, rhos, ys = [], [], []
+    for _ in range(nsets):
+        xs.append((2.0 * torch.rand(nd, generator=gen, dtype=torch.float64) - 1.0).cuda())
+        rhos.append((1e-3 + (1.0 - 1e-3) * torch.rand(m, generator=gen,
+                                                        dtype=torch.float64)).cuda())
+        ys.append(torch.empty(nd, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+
+    def k_batch():
+        for i in range(nsets):
+            ctxk.apply_K_rho(rhos[i], xs[i], ys[i])
+
+    def step():
+        st = ctx.pbm_iterate()
+        k_batch()
+        return st
+
+    for w in range(a.warmup):
+        st = step()
+        print(f"warmup {w}: outer iteration newton {st['newton_its']} minres "
+              f"{st['minres_its']} ratio {st['ratio']:.2e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ctxk.profile_start("apply_K")
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        stats.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kp = ctxk.profile_stop()
+    wall = t1 - t0
+    k_ms = kp["total_ms"] / max(kp["launches"], 1)
+    k_gdofs = nd / (k_ms * 1e-3) / 1e9
+    k_gbs = k_bytes / (k_ms * 1e-3) / 1e9
+    minres = sum(s["minres_its"] for s in stats)
+    newton = sum(s["newton_its"] for s in stats)
+    print(f"timed: {a.steps} steps in {wall:.2f} s; K(rho)u {kp['launches']} launches "
+          f"{k_ms * 1e3:.2f} us; {newton} Newton steps, {minres} MINRES iterations",
+          file=sys.stderr, flush=True)
+
+    # the other kernels of the hot path over one more outer iteration
+    def one_iteration():
+        ctx.pbm_iterate()
+    gs = profiled(ctx, "gs_fine", one_iteration)
+    sa = profiled(ctx, "apply_S", one_iteration)
+
+    # MINRES-MG at a fixed Newton point (the current state), fixed count
+    def fixed_point_rate(c):
+        c.newton_setup()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = c.solve_newton(0.0)
+        torch.cuda.synchronize()
+        return r["iterations"] / (time.perf_counter() - t), r["iterations"]
+    mr_mixed, mr_its = fixed_point_rate(ctx)
+    ctxk.set_state(ctx.get_state())
+    mr_fp64, _ = fixed_point_rate(ctxk)
+    print(f"fixed-point MINRES-MG: mixed {mr_mixed:.1f} it/s, FP64 {mr_fp64:.1f} it/s",
+          file=sys.stderr, flush=True)
+    ctx.close()
+    ctxk.close()
+    del xs, rhos, ys
+
+    # time-to-KKT of the 64x32x32 cantilever, FP64 and mixed
+    pr2 = W.config(1)
+    gold = os.path.join(ROOT, "tests", "golden", f"oracle_{pr2.name}.json")
+    c_or = json.load(open(gold))["compliance_half_fu"] if os.path.exists(gold) else None
+    ttk = {}
+    for name, prec in (("fp64", V.VTS_FP64), ("mixed", V.VTS_MIXED)):
+        o2 = V.default_options(eps_mr0=pr2.extra["eps_mr0"])
+        tc = time.perf_counter()
+        c2 = V.Context.from_problem(pr2, precision=prec, options=o2)
+        r = c2.pbm_solve()
+        torch.cuda.synchronize()
+        t_create = time.perf_counter() - tc
+        runs = []
+        for _ in range(2):
+            c2.reset()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = c2.pbm_solve()
+            torch.cuda.synchronize()
+            runs.append(time.perf_counter() - t)
+        k = device_kkt(torch, c2, pr2, c2.state_dict()["alpha"])
+        ttk[name] = dict(seconds=min(runs), seconds_from_create=t_create,
+                         outer=r["outer"], newton=r["newton"], minres=r["minres"],
+                         kkt=k["kkt"], compliance=r["compliance"],
+                         compliance_rel_err_vs_oracle=(abs(r["compliance"] - c_or) / c_or
+                                                       if c_or else None))
+        print(f"time-to-KKT {pr2.name} {name}: {min(runs):.3f} s (from vts_create "
+              f"{t_create:.3f} s) KKT {k['kkt']:.2e}", file=sys.stderr, flush=True)
+        c2.close()
+
+    line = {
+        "metric": METRIC,
+        "value": k_gdofs,
+        "unit": "GDOF/s (K(rho)u, FP64, rotating sets beyond the Infinity Cache)",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": wall * 1e3 / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": pr.name, "grid": [pr.nx, pr.ny, pr.nz], "levels": pr.levels,
+                   "m": pr.m, "n": pr.n, "n_dof": nd, "V_over_m": pr.V / pr.m,
+                   "hot_path_precision": "mixed (FP32 multigrid, FP64 MINRES/Newton/PBM)",
+                   "k_sets": nsets, "k_set_bytes": nsets * (k_bytes + 8.0 * nd),
+                   "step": "one outer PBM iteration + K(rho)u on every set",
+                   "parallelism": "1 GPU"},
+        "roofline": {"kernel": "k_apply_K_plane<double> (K(rho)x, FP64)",
+                     "bound": "hbm", "achieved": k_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": k_gbs / HBM_PEAK_GBS, "traffic": measured_k_traffic(),
+                     "bytes_per_launch": k_bytes, "avg_launch_ms": k_ms,
+                     "launches": kp["launches"]},
+        "hot_path": {"outer_iterations_per_s": a.steps / wall,
+                     "minres_mg_iters_per_s": minres / wall,
+                     "newton_steps": newton, "minres_iterations": minres,
+                     "last_gap_ratio": stats[-1]["ratio"], "last_stat": stats[-1]["stat"],
+                     "minres_mg_fixed_point_iters_per_s": {"mixed": mr_mixed, "fp64": mr_fp64,
+                                                           "iterations": mr_its}},
+        "kernels": {
+            "gs_fine": {"avg_launch_ms": gs["avg_launch_ms"], "gbs": gs["gbs"],
+                        "bytes_per_launch": gs["bytes_per_launch"],
+                        "launches_per_outer_iteration": gs["launches"],
+                        "precision": "fp32"},
+            "apply_S": {"avg_launch_ms": sa["avg_launch_ms"], "gbs": sa["gbs"],
+                        "bytes_per_launch": sa["bytes_per_launch"],
+                        "launches_per_outer_iteration": sa["launches"]}},
+        "time_to_kkt_cant-64x32x32": ttk,
+        "mixed_over_fp64_time_to_kkt": ttk["mixed"]["seconds"] / ttk["fp64"]["seconds"],
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_k_apply(pr, a.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {a.gpus} is not supported "
+              f"(the path runs on one GPU; there is no multi-GPU code)", file=sys.stderr)
+        return 2
+    import torch
+    import workloads as W
+    from paper_1904_06556_amd import vts as V
+
+    if a.kernels:
+        return kernels_only(a, torch, W, V)
+    if a.serve:
+        return serving(a, torch, W, V)
+    if a.doc:
+        return doc_compare(a, torch, W, V)
+    if a.scale_kernels:
+        return scaling_kernels(a, torch, W, V)
+    if a.scale:
+        return scaling_run(a, torch, W, V)
+    if a.paper and a.ip:
+        return paper_problems_ip(a, torch, W, V)
+    if a.ip:
+        return ip_compare(a, torch, W, V)
+    if a.paper:
+        return paper_problems(a, torch, W, V)
+    if a.solve:
+        return solve_run(a, torch, W, V)
+    return headline(a, torch, W, V)
 
 
 if __name__ == "__main__":

@@ -202,6 +202,16 @@ vts_status vts_apply_K(vts_ctx* ctx, const double* x_dev, double* y_dev);
  * x_dev, y_dev n_dof floats; rho taken from the FP64 rho rounded to FP32. */
 vts_status vts_apply_K_f32(vts_ctx* ctx, const float* x_dev, float* y_dev);
 
+/* y = K(rho) x for a caller-supplied rho (problem (1.1)), leaving the
+ * context's own rho untouched: rho_dev m FP64 values on the device, x_dev,
+ * y_dev as for vts_apply_K (fixed DOFs masked on read, written as 0; x and y
+ * must not overlap).  The _f32 form takes FP32 rho, x and y.  Reads x and
+ * rho once and writes y once (the operator's compulsory traffic). */
+vts_status vts_apply_K_rho(vts_ctx* ctx, const double* rho_dev, const double* x_dev,
+                           double* y_dev);
+vts_status vts_apply_K_rho_f32(vts_ctx* ctx, const float* rho_dev, const float* x_dev,
+                               float* y_dev);
+
 /* e_i = 1/2 u_e^T K_e u_e for all elements (the constraint of (2.1)).
  * u_dev: n_dof FP64; e_dev: m FP64. */
 vts_status vts_element_energy(vts_ctx* ctx, const double* u_dev, double* e_dev);

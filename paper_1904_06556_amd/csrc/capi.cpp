@@ -1085,6 +1085,22 @@ vts_status vts_apply_K_f32(vts_ctx* cp, const float* x, float* y) {
     return VTS_OK;
 }
 
+vts_status vts_apply_K_rho(vts_ctx* cp, const double* rho, const double* x, double* y) {
+    if (!cp || !rho || !x || !y || x == y) return VTS_EINVAL;
+    Ctx& c = *cp;
+    launch_apply_K_f64(c, rho, x, y);
+    HIPCHK(hipGetLastError());
+    return VTS_OK;
+}
+
+vts_status vts_apply_K_rho_f32(vts_ctx* cp, const float* rho, const float* x, float* y) {
+    if (!cp || !rho || !x || !y || x == y) return VTS_EINVAL;
+    Ctx& c = *cp;
+    launch_apply_K_f32(c, rho, x, y);
+    HIPCHK(hipGetLastError());
+    return VTS_OK;
+}
+
 vts_status vts_element_energy(vts_ctx* cp, const double* u, double* e) {
     if (!cp || !u || !e) return VTS_EINVAL;
     Ctx& c = *cp;

@@ -157,10 +157,11 @@ k_apply_K(int nx, int ny, int nz, const T* __restrict__ Ke, const T* __restrict_
 
 void launch_apply_K_f64(Ctx& c, const double* rho, const double* x, double* y) {
     if (tile_ok(c)) {
-        // algorithmic bytes: x, y, rho (8 B each entry) and the DOF mask
+        // algorithmic bytes: read x and rho, write y (8 B each entry); the
+        // Dirichlet data (one mask byte per node) are not counted
         const bool prof = prof_begin(c, VTS_PROF_APPLY_K);
         launch_apply_K_tile_f64(c, rho, x, y);
-        if (prof) prof_end(c, 16.0 * c.ndof + 8.0 * c.m + c.ndof);
+        if (prof) prof_end(c, 16.0 * c.ndof + 8.0 * c.m);
         return;
     }
     hipLaunchKernelGGL(k_apply_K<double>, dim3(grid1d(c.nn)), dim3(kThreads), 0, c.s,

@@ -125,6 +125,8 @@ SIGNATURES = {
     "vts_set_rho": (C.c_int, [_P, _P]),
     "vts_apply_K": (C.c_int, [_P, _P, _P]),
     "vts_apply_K_f32": (C.c_int, [_P, _P, _P]),
+    "vts_apply_K_rho": (C.c_int, [_P, _P, _P, _P]),
+    "vts_apply_K_rho_f32": (C.c_int, [_P, _P, _P, _P]),
     "vts_element_energy": (C.c_int, [_P, _P, _P]),
     "vts_newton_setup": (C.c_int, [_P]),
     "vts_apply_S": (C.c_int, [_P, _P, _P]),
@@ -306,6 +308,18 @@ class Context:
         import torch
         self._check(lib().vts_apply_K_f32(self.h, _ptr(x, torch.float32, self.n_dof),
                                           _ptr(y, torch.float32, self.n_dof)))
+
+    def apply_K_rho(self, rho, x, y):
+        import torch
+        self._check(lib().vts_apply_K_rho(self.h, _ptr(rho, torch.float64, self.m),
+                                          _ptr(x, torch.float64, self.n_dof),
+                                          _ptr(y, torch.float64, self.n_dof)))
+
+    def apply_K_rho_f32(self, rho, x, y):
+        import torch
+        self._check(lib().vts_apply_K_rho_f32(self.h, _ptr(rho, torch.float32, self.m),
+                                              _ptr(x, torch.float32, self.n_dof),
+                                              _ptr(y, torch.float32, self.n_dof)))
 
     def element_energy(self, u, e):
         import torch
