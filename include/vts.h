@@ -229,6 +229,20 @@ vts_status vts_newton_setup(vts_ctx* ctx);
  * S-vectors (FP64).  VTS_ESTATE before the first vts_newton_setup. */
 vts_status vts_apply_S(vts_ctx* ctx, const double* x_dev, double* y_dev);
 
+/* For callers that cannot allocate device memory at call time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same y = S [x; beta] as vts_apply_S, with its per-workgroup partial
+ * sums of the alpha row kept in a static workspace of the library (65536
+ * doubles per device, held until the process ends) instead of the context's
+ * buffer.  Calls no hipMalloc, hipFree or allocating library routine.
+ * Every partial sum is written before it is read, so nothing in the
+ * workspace needs clearing; all calls on one device share the workspace, so
+ * calls that overlap on one device (different streams or threads) race.
+ * VTS_EINVAL if the grid needs more than 65536 partial sums (about 9e7
+ * nodes) or the element is not the cube; VTS_ESTATE before the first
+ * vts_newton_setup; VTS_EDEVICE if the workspace address cannot be found. */
+vts_status vts_apply_S_noalloc(vts_ctx* ctx, const double* x_dev, double* y_dev);
+
 /* z = M^{-1} r: one V-cycle (Section 6.1) on the hierarchy of the last
  * vts_newton_setup, in FP64 or FP32 per the problem's precision.
  * r_dev, z_dev: S-vectors (FP64); may not overlap. */

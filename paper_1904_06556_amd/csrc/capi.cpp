@@ -1125,6 +1125,28 @@ vts_status vts_apply_S(vts_ctx* cp, const double* x, double* y) {
     return VTS_OK;
 }
 
+vts_status vts_apply_S_noalloc(vts_ctx* cp, const double* x, double* y) {
+    if (!cp || !x || !y || x == y) return VTS_EINVAL;
+    Ctx& c = *cp;
+    if (!c.eval_valid) { c.err = "apply_S before newton_setup"; return VTS_ESTATE; }
+    if (!tile_ok(c)) {
+        c.err = "allocation-free S-apply needs the tiled operator (cube element)";
+        return VTS_EINVAL;
+    }
+    const int nb = apply_S_tile_blocks(c);
+    if (nb > kScratchPartials) {
+        c.err = "grid needs " + std::to_string(nb) + " partial sums; the workspace holds " +
+                std::to_string(kScratchPartials);
+        return VTS_EINVAL;
+    }
+    double* ws = nullptr;
+    const vts_status st = scratch_partials(c.device, &ws, c.err);
+    if (st != VTS_OK) return st;
+    launch_apply_S_tile_ws(c, x, y, ws);
+    HIPCHK(hipGetLastError());
+    return VTS_OK;
+}
+
 vts_status vts_precondition(vts_ctx* cp, const double* r, double* z) {
     if (!cp || !r || !z || r == z) return VTS_EINVAL;
     Ctx& c = *cp;

@@ -22,6 +22,9 @@
 // y-neighbours through LDS, in a fixed order (deterministic, no atomics).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <string>
+
 #include "vts_internal.hpp"
 
 namespace vts {
@@ -702,14 +705,57 @@ int apply_S_tile_blocks(const Ctx& c) {
     return g.tiles_x * g.tiles_y * ((c.nz + 1 + kz - 1) / kz);
 }
 
-void launch_apply_S_tile(Ctx& c, const double* x, double* y) {
+void launch_apply_S_tile_ws(Ctx& c, const double* x, double* y, double* partials) {
     const int kz = choose_kz(c);
     TileGeom g = geom_of(c, kz);
     KhVals<double> kh{c.kh8[0], c.kh8[1], c.kh8[2], c.kh8[3], c.kh8[4], c.kh8[5], c.kh8[6], c.kh8[7]};
     const int nb = g.tiles_x * g.tiles_y * ((c.nz + 1 + kz - 1) / kz);
     hipLaunchKernelGGL(k_apply_S_tile<double>, dim3(nb), dim3(kTileThreads), 0, c.s, g, kh, x, c.u,
-                       c.r1, c.w, c.fixed, c.ndof, y, c.spart);
-    hipLaunchKernelGGL(k_sum_neg, dim3(1), dim3(256), 0, c.s, c.spart, nb, y + c.ndof);
+                       c.r1, c.w, c.fixed, c.ndof, y, partials);
+    hipLaunchKernelGGL(k_sum_neg, dim3(1), dim3(256), 0, c.s, partials, nb, y + c.ndof);
+}
+
+void launch_apply_S_tile(Ctx& c, const double* x, double* y) {
+    launch_apply_S_tile_ws(c, x, y, c.spart);
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free S-apply: the per-workgroup partial sums of
+// the alpha row live in this file-scope device array instead of the
+// context's buffer.  Each device holds its own copy; host code reaches it
+// only through the address hipGetSymbolAddress returns for that device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kScratchPartials];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+vts_status scratch_partials(int device, double** out, std::string& err) {
+    if (device < 0 || device >= kMaxScratchDevices) {
+        err = "device index beyond the scratch table";
+        return VTS_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess) { err = "hipGetDevice failed"; return VTS_EDEVICE; }
+        if (cur != device && hipSetDevice(device) != hipSuccess) {
+            err = "hipSetDevice failed";
+            return VTS_EDEVICE;
+        }
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) hipSetDevice(cur);
+        if (e != hipSuccess || !p) {
+            err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+            return VTS_EDEVICE;
+        }
+        g_scratch_ptr[device] = (double*)p;
+    }
+    *out = g_scratch_ptr[device];
+    return VTS_OK;
 }
 
 }  // namespace vts

@@ -240,6 +240,13 @@ int apply_S_tile_blocks(const Ctx& c);
 void launch_apply_K_tile_f64(Ctx& c, const double* rho, const double* x, double* y);
 void launch_apply_K_tile_f32(Ctx& c, const float* rho, const float* x, float* y);
 void launch_apply_S_tile(Ctx& c, const double* x, double* y);
+// the same with the per-workgroup partial sums in `partials`
+void launch_apply_S_tile_ws(Ctx& c, const double* x, double* y, double* partials);
+// allocation-free S-apply: the device address of the file-scope workspace of
+// kScratchPartials doubles (looked up once per device)
+constexpr int kScratchPartials = 1 << 16;
+constexpr int kMaxScratchDevices = 64;
+vts_status scratch_partials(int device, double** out, std::string& err);
 bool walsh_form(const double* Ke, double* kh8);    // host_fe.cpp
 
 template <typename T> void mg_build(Ctx& c, Hierarchy<T>& H);

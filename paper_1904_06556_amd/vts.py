@@ -126,6 +126,7 @@ SIGNATURES = {
     "vts_apply_K": (C.c_int, [_P, _P, _P]),
     "vts_apply_K_f32": (C.c_int, [_P, _P, _P]),
     "vts_apply_K_rho": (C.c_int, [_P, _P, _P, _P]),
+    "vts_apply_S_noalloc": (C.c_int, [_P, _P, _P]),
     "vts_apply_K_rho_f32": (C.c_int, [_P, _P, _P, _P]),
     "vts_element_energy": (C.c_int, [_P, _P, _P]),
     "vts_newton_setup": (C.c_int, [_P]),
@@ -333,6 +334,11 @@ class Context:
         import torch
         self._check(lib().vts_apply_S(self.h, _ptr(x, torch.float64, self.n_dof + 1),
                                       _ptr(y, torch.float64, self.n_dof + 1)))
+
+    def apply_S_noalloc(self, x, y):
+        import torch
+        self._check(lib().vts_apply_S_noalloc(self.h, _ptr(x, torch.float64, self.n_dof + 1),
+                                              _ptr(y, torch.float64, self.n_dof + 1)))
 
     def precondition(self, r, z):
         import torch
