@@ -500,6 +500,8 @@ def ip_compare(a, torch, W, V):
     opts = V.default_options()
     if eps_mr0:
         opts.eps_mr0 = eps_mr0
+    if pr.extra.get("p_min"):
+        opts.p_min = pr.extra["p_min"]
     ctx = V.Context.from_problem(pr, precision=V.VTS_FP64, options=opts)
     ctx.reset()
     ctx.pbm_solve()
@@ -671,6 +673,8 @@ def solve_run(a, torch, W, V):
     opts = V.default_options()
     if eps_mr0:
         opts.eps_mr0 = eps_mr0
+    if pr.extra.get("p_min"):
+        opts.p_min = pr.extra["p_min"]
     want = pr.extra.get("precision") if a.precision == "config" else a.precision
     prec = V.VTS_MIXED if want == "mixed" else V.VTS_FP64
     ctx = V.Context.from_problem(pr, precision=prec, options=opts)

@@ -114,6 +114,18 @@ typedef struct {
                                      nothing).  Default 0: measured no faster on MI355X,
                                      the V-cycle waits on dependent-kernel latency on the
                                      device, not on host launch cost */
+    double kkt_tol;               /* > 0: vts_pbm_solve succeeds (VTS_OK) iff the KKT residual of
+                                     the returned (rho, u, alpha) is at most this, whatever the
+                                     final Newton call's own test gave; a final Newton that
+                                     stalled (VTS_ENOTCONV, VTS_ENONDESCENT) then goes on to the
+                                     rho update and state solve.  <= 0: the accept_stall rule
+                                     decides.  Default 1e-6 */
+    double eps_state;             /* > 0: after the last update of rho, vts_pbm_solve solves the
+                                     state equation K(rho) u = f for the returned rho (MINRES
+                                     with one V-cycle of blockdiag(K(rho), 1), stopping at this
+                                     relative residual in the preconditioner norm), so that the
+                                     returned u is the state of the returned density; <= 0: u is
+                                     the last Newton iterate.  Default 1e-10 */
 } vts_options;
 
 typedef struct {
@@ -144,6 +156,12 @@ typedef struct {
     double res_pbm;
     int32_t outer, newton, minres;
     int32_t status;               /* vts_status of the run */
+    /* KKT residual of the returned (rho, u) with multiplier lambda = alpha
+     * (conditions of problem (1.1)): r_eq = ||K(rho)u - f|| / ||f||,
+     * r_vol = |sum rho - V| / V, r_box = max bound violation / max rho_hi,
+     * r_stat = max_i |rho_i - clip(rho_i + (e_i - lambda)/lambda)| / rho_hi_i;
+     * kkt = the largest of the four (all 0 if the run ended before them) */
+    double kkt, r_eq, r_vol, r_box, r_stat;
 } vts_result;
 
 /* Which internal vector vts_get_vector copies (device to device). */
@@ -270,8 +288,13 @@ vts_status vts_newton(vts_ctx* ctx, double eps_nwt, int32_t final_call,
  * eps_NWT update. */
 vts_status vts_pbm_iterate(vts_ctx* ctx, vts_pbmstats* stats);
 
-/* Algorithm 1 to convergence, followed by the final Newton call and the
- * last update of rho. */
+/* Algorithm 1 to convergence, followed by the final Newton call, the last
+ * update of rho, (eps_state > 0) the state solve K(rho) u = f for that rho
+ * and the KKT residual of the result.  With kkt_tol > 0 the status is
+ * VTS_OK iff that residual is at most kkt_tol (VTS_ENOTCONV otherwise);
+ * with kkt_tol <= 0 a final Newton that stalls (VTS_ENOTCONV,
+ * VTS_ENONDESCENT) with res_PBM below accept_stall is accepted.  Device,
+ * argument and definiteness errors are always returned. */
 vts_status vts_pbm_solve(vts_ctx* ctx, vts_result* result);
 
 /* Copies an internal vector (see vts_vector) to dst_dev (device). */

@@ -68,6 +68,8 @@ class Options:
     max_minres: int = 500
     final_res4: bool = True                   # final Newton also tests res_4
     stall_steps: int = 10                     # final Newton: stop after this many steps without progress
+    final_state_solve: bool = True            # u <- K(rho)^-1 f for the returned rho
+    kkt_tol: float = 1e-6                     # > 0: success iff the KKT residual is below it
 
 
 def p_floor(o: "Options", alpha: float) -> float:
@@ -89,7 +91,7 @@ def paper_options(eps_pbm: float = 1e-5) -> "Options":
     """The parameter values of the paper's experiments (Section 7)."""
     return Options(eps_pbm=eps_pbm, eps_nwt_min=1e-3, eps_nwt_final=None,
                    final_res4=False, eps_stat=None, accept_stall=0.0, p_min=1e-8,
-                   p_min_relative=False, q_min=1e-8)
+                   p_min_relative=False, q_min=1e-8, final_state_solve=False, kkt_tol=0.0)
 
 
 @dataclass
@@ -407,6 +409,7 @@ class Solver:
         self.res_prev = None
         self.log = Log()
         self.status = "ok"
+        self.progress = None                  # optional callback(outer index, outer log entry)
 
     # one linear solve of eq. (3.13)
     def linsolve(self, ev, S, rhs):
@@ -497,6 +500,8 @@ class Solver:
             rho_n, mul_n, muh_n = update_multipliers(st, ev, o.beta)
             stat = stationarity(P, rho_n, ev.e, st.alpha) if o.eps_stat else 0.0
             self.log.outer[-1]["stat"] = stat
+            if self.progress is not None:
+                self.progress(k, self.log.outer[-1])
             if self.status != "ok" or (ratio < o.eps_pbm and stat < (o.eps_stat or 1.0)):
                 break
             st.rho, st.mu_lo, st.mu_hi = rho_n, mul_n, muh_n
@@ -505,11 +510,25 @@ class Solver:
             st.q_hi = np.maximum(o.gamma * st.q_hi, q_floor(o, st.alpha))
             eps_nwt = max(min(100.0 * ratio, eps_nwt), o.eps_nwt_min)
         eps_final = o.eps_nwt_final if o.eps_nwt_final is not None else 10.0 * o.eps_pbm
+        self.kkt = None
         if self.status == "ok":
             st, ev = self.newton(st, eps_final, final=True)
-            if self.status != "ok" and self.res_prev is not None and \
+            stalled = self.status != "ok"   # every Newton failure mode here is a stall
+            if stalled and o.kkt_tol <= 0 and self.res_prev is not None and \
                     self.res_prev < o.accept_stall:
                 self.status = "ok"          # near-optimal stall accepted
-        st.rho, _, _ = update_multipliers(st, ev, o.beta, rho_only=True)
+            if self.status == "ok" or (stalled and o.kkt_tol > 0):
+                st.rho, _, _ = update_multipliers(st, ev, o.beta, rho_only=True)
+                if o.final_state_solve:
+                    # the primal pair of problem (1.1): the state of the returned density
+                    from .kkt import solve_state
+                    st.u = solve_state(P.grid, P.Ke, st.rho, P.f)
+                from .kkt import kkt_residual
+                self.kkt = kkt_residual(P.grid, P.Ke, P.f, P.V, P.rho_lo, P.rho_hi, st.rho,
+                                        st.u, st.alpha)
+                if o.kkt_tol > 0:
+                    self.status = "ok" if self.kkt["kkt"] <= o.kkt_tol else "kkt"
+        else:
+            st.rho, _, _ = update_multipliers(st, ev, o.beta, rho_only=True)
         self.state = st
         return st

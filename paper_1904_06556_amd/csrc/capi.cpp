@@ -621,6 +621,27 @@ vts_status pbm_iterate(Ctx& c, vts_pbmstats* out) {
     return VTS_OK;
 }
 
+// The state equation K(rho) u = f for the context's rho: MINRES with one
+// V-cycle of blockdiag(K(rho), 1) (the Schur operator with rho' = rho, no
+// rank-one terms, alpha decoupled), u <- solution.  Used after the last rho
+// update of Algorithm 1 so that (rho, u) satisfy the equilibrium condition
+// to the solver's accuracy; the Newton iterate u is only near it.
+vts_status state_solve(Ctx& c, double eps) {
+    c.eval_valid = false;
+    c.setup_valid = false;
+    launch_doc_setup(c);
+    c.sum_w = 1.0;
+    vts_status st = build_mg(c);
+    if (st != VTS_OK) return st;
+    vts_linstats ls{0, 0.0};
+    if ((st = minres(c, eps, &ls)) != VTS_OK) return st;
+    HIPCHK(hipMemcpyAsync(c.u, c.dy, c.ndof * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+    c.eval_valid = false;
+    c.setup_valid = false;
+    HIPCHK(hipGetLastError());
+    return VTS_OK;
+}
+
 // ---------------------------------------------------------------------------
 // primal-dual interior point method (Section 4, Algorithm 3)
 // ---------------------------------------------------------------------------
@@ -1007,6 +1028,8 @@ void vts_default_options(vts_options* o) {
     o->p_min_relative = 1;
     o->stall_steps = 10;
     o->use_graphs = 0;
+    o->kkt_tol = 1e-6;
+    o->eps_state = 1e-10;
 }
 
 vts_status vts_create(const vts_problem* pr, const vts_options* opt, void* stream, vts_ctx** out) {
@@ -1190,21 +1213,47 @@ vts_status vts_pbm_solve(vts_ctx* cp, vts_result* res) {
     }
     if (st == VTS_OK && !c.converged) st = VTS_ENOTCONV;
     vts_newtonstats ns{};
+    bool kkt_done = false;
+    double kk[5] = {0, 0, 0, 0, 0};   // kkt, r_eq, r_vol, r_box, r_stat
     if (st == VTS_OK) {
         st = newton(c, c.opt.eps_nwt_final, true, &ns, nullptr);
-        // a stalled final Newton (no progress, or no descent step) is accepted
-        // near the optimum; device, argument and definiteness errors never are
+        // a stalled final Newton (no progress, or no descent step) goes on to the
+        // rho update; device, argument and definiteness errors never do
         const bool stall = st == VTS_ENOTCONV || st == VTS_ENONDESCENT;
-        if (stall && c.res_prev >= 0 && c.res_prev < c.opt.accept_stall) st = VTS_OK;
-        // the last accepted state was evaluated; make sure of it before the rho update
-        if (!c.eval_valid) {
-            vts_status s2 = evaluate(c);
-            if (s2 != VTS_OK && st == VTS_OK) st = s2;
+        const bool by_kkt = c.opt.kkt_tol > 0;
+        if (stall && (by_kkt || (c.res_prev >= 0 && c.res_prev < c.opt.accept_stall)))
+            st = by_kkt ? VTS_ENOTCONV : VTS_OK;
+        if (st == VTS_OK || (by_kkt && stall)) {
+            vts_status s2 = VTS_OK;
+            // the last accepted state was evaluated; make sure of it before the rho update
+            if (!c.eval_valid) s2 = evaluate(c);
+            if (s2 == VTS_OK) {
+                launch_mult_update(c, 1);
+                launch_round_rho(c);
+                c.eval_valid = false;
+                c.setup_valid = false;
+                if (c.opt.eps_state > 0) s2 = state_solve(c, c.opt.eps_state);
+            }
+            if (s2 == VTS_OK) {
+                launch_kkt(c, c.alpha, c.g1);
+                s2 = sync_red(c);
+            }
+            if (s2 != VTS_OK) {
+                st = s2;
+            } else {
+                const double* r = c.red_host;
+                kk[1] = std::sqrt(r[SL_WT]) / c.norm_f;
+                kk[2] = std::fabs(r[SL_SUM_RHO] - c.V) / c.V;
+                kk[3] = std::max(0.0, r[SL_AUX]) / r[SL_MRALPHA];
+                kk[4] = r[SL_STAT];
+                kk[0] = std::max(std::max(kk[1], kk[2]), std::max(kk[3], kk[4]));
+                kkt_done = true;
+                if (by_kkt) {
+                    st = kk[0] <= c.opt.kkt_tol ? VTS_OK : VTS_ENOTCONV;
+                    if (st != VTS_OK) c.err = "KKT residual above kkt_tol";
+                }
+            }
         }
-        launch_mult_update(c, 1);
-        launch_round_rho(c);
-        c.eval_valid = false;
-        c.setup_valid = false;
     }
     if (res) {
         launch_dot(c, c.f, c.u, c.ndof, SL_DOT);
@@ -1219,6 +1268,11 @@ vts_status vts_pbm_solve(vts_ctx* cp, vts_result* res) {
         res->newton = c.newton_total;
         res->minres = c.minres_total;
         res->status = st;
+        res->kkt = kkt_done ? kk[0] : 0.0;
+        res->r_eq = kkt_done ? kk[1] : 0.0;
+        res->r_vol = kkt_done ? kk[2] : 0.0;
+        res->r_box = kkt_done ? kk[3] : 0.0;
+        res->r_stat = kkt_done ? kk[4] : 0.0;
     }
     c.status = st;
     return st;

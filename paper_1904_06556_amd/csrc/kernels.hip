@@ -594,6 +594,44 @@ void launch_outer_eval(Ctx& c) {
                        1u << 3, c.red);
 }
 
+// KKT residual of (rho, u, lam) by its definition, from Ku = K(rho)u and
+// e = e(u): the sums ||Ku - f||^2 and sum rho, and the maxima of
+// |rho - clip(rho + (e - lam)/lam)| / hi, of the bound violation and of hi.
+__global__ void __launch_bounds__(kThreads)
+k_kkt(int64_t ndof, int64_t m, double lam, const double* __restrict__ Ku,
+      const double* __restrict__ f, const double* __restrict__ rho, const double* __restrict__ e,
+      const double* __restrict__ lo, const double* __restrict__ hi, double* partials) {
+    // slots: STAT (max), SUM_RHO, WT (= ||Ku - f||^2), AUX (box, max), MRALPHA (max hi)
+    double acc[5] = {-DBL_MAX, 0.0, 0.0, 0.0, -DBL_MAX};
+    const int64_t n = ndof > m ? ndof : m;
+    for (int64_t t = gid(); t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        if (t < ndof) {
+            const double d = Ku[t] - f[t];
+            acc[2] += d * d;
+        }
+        if (t < m) {
+            const double r = rho[t], l = lo[t], h = hi[t];
+            const double proj = fmin(fmax(r + (e[t] - lam) / lam, l), h);
+            acc[0] = fmax(acc[0], fabs(r - proj) / h);
+            acc[1] += r;
+            acc[3] = fmax(acc[3], fmax(l - r, r - h));
+            acc[4] = fmax(acc[4], h);
+        }
+    }
+    block_sum_store<5>(acc, partials, SL_STAT, 0x19u);
+}
+
+void launch_kkt(Ctx& c, double lam, double* Ku) {
+    launch_apply_K_f64(c, c.rho, c.u, Ku);
+    launch_energy(c, c.u, c.e);
+    const int64_t n = c.ndof > c.m ? c.ndof : c.m;
+    const int g = red_grid(n);
+    hipLaunchKernelGGL(k_kkt, dim3(g), dim3(kThreads), 0, c.s, c.ndof, c.m, lam, Ku, c.f, c.rho,
+                       c.e, c.rlo, c.rhi, c.partials);
+    hipLaunchKernelGGL(k_finalize, dim3(5), dim3(kThreads), 0, c.s, c.partials, g, (int)SL_STAT,
+                       0x19u, c.red);
+}
+
 // Multiplier update of Algorithm 1 with the safeguard beta x <= x+ <= x/beta.
 __global__ void k_mult(int64_t m, double alpha, double beta, int rho_only,
                        const double* __restrict__ e, const double* __restrict__ nlo,

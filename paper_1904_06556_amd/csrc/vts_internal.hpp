@@ -210,6 +210,9 @@ void launch_dnu(Ctx& c);                     // c1, c2, dnl, dnh, slope parts ->
 void launch_linesearch(Ctx& c, double kappa, double dalpha); // elementwise Delta L -> red
 void launch_update(Ctx& c, double kappa);    // u, nu
 void launch_outer_eval(Ctx& c);              // gap, dual parts, stationarity -> red
+// KKT terms of (rho, u, lam) -> red[STAT, SUM_RHO, WT (||Ku-f||^2), AUX (box), MRALPHA (max hi)];
+// Ku: n_dof scratch; overwrites e
+void launch_kkt(Ctx& c, double lam, double* Ku);
 void launch_mult_update(Ctx& c, int rho_only);
 void launch_penalty_update(Ctx& c);
 void launch_init_state(Ctx& c);

@@ -54,7 +54,8 @@ class Options_t(C.Structure):
                 ("armijo_min", C.c_double), ("max_outer", C.c_int32),
                 ("max_newton", C.c_int32), ("max_minres", C.c_int32),
                 ("final_res4", C.c_int32), ("p_min_relative", C.c_int32),
-                ("stall_steps", C.c_int32), ("use_graphs", C.c_int32)]
+                ("stall_steps", C.c_int32), ("use_graphs", C.c_int32),
+                ("kkt_tol", C.c_double), ("eps_state", C.c_double)]
 
 
 class LinStats_t(C.Structure):
@@ -75,7 +76,9 @@ class PbmStats_t(C.Structure):
 class Result_t(C.Structure):
     _fields_ = [("compliance", C.c_double), ("alpha", C.c_double), ("sum_rho", C.c_double),
                 ("res_pbm", C.c_double), ("outer", C.c_int32), ("newton", C.c_int32),
-                ("minres", C.c_int32), ("status", C.c_int32)]
+                ("minres", C.c_int32), ("status", C.c_int32),
+                ("kkt", C.c_double), ("r_eq", C.c_double), ("r_vol", C.c_double),
+                ("r_box", C.c_double), ("r_stat", C.c_double)]
 
 
 class DocStats_t(C.Structure):

@@ -28,6 +28,9 @@ def main(idx: int):
         opts.eps_mr0 = pr.extra["eps_mr0"]
     t0 = time.time()
     s = pbm.Solver(pr, opts)
+    s.progress = lambda k, d: print(f"outer {k}: ratio {d['ratio']:.3e} stat {d['stat']:.3e} "
+                                    f"newton so far {len(s.log.newton)} "
+                                    f"({time.time() - t0:.0f} s)", file=sys.stderr, flush=True)
     st = s.solve()
     t1 = time.time()
     P = s.P
