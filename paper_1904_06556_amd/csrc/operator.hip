@@ -20,6 +20,12 @@
 // the two faces; the face sums of two consecutive elements are transformed
 // back to nodes once per plane.  x-neighbours meet through a DPP row shift,
 // y-neighbours through LDS, in a fixed order (deterministic, no atomics).
+//
+// S [x; beta] (k_apply_S_plane) marches the same way with x and u staged
+// together; per element b_e = K_e u_e and t = b_e^T x_e - beta are formed in
+// the transformed basis, and y_e = K_e (rho'_e x_e + w_e t u_e) goes through
+// Kh once more.  Bottom-face transforms are taken again from the LDS ring
+// (not carried in registers) to keep two workgroups resident per CU.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -49,171 +55,6 @@ template <typename T>
 struct KhVals {
     T A, B, C, D, E, F, G, H;
 };
-
-// in-place butterflies over the 8 nodes of each component: v <- H v
-template <typename T>
-__device__ __forceinline__ void hadamard24(T (&v)[24]) {
-#pragma unroll
-    for (int bit = 1; bit < 8; bit <<= 1) {
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-            if (a & bit) continue;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const T p = v[3 * a + c], q = v[3 * (a | bit) + c];
-                v[3 * a + c] = p + q;
-                v[3 * (a | bit) + c] = p - q;
-            }
-        }
-    }
-}
-
-// v <- s * K_e v, in place (keeps one 24-vector live)
-template <typename T>
-__device__ __forceinline__ void ke_apply(const KhVals<T>& k, T s, T (&v)[24]) {
-    hadamard24(v);
-#pragma unroll
-    for (int q = 3; q < 24; ++q) v[q] *= s;
-    v[0] = v[1] = v[2] = T(0);
-    // linear modes: normals 3, 7, 14; shears (4,6), (5,12), (8,13)
-    const T vol = k.B * (v[3] + v[7] + v[14]);
-    const T AmB = k.A - k.B;
-    v[3] = AmB * v[3] + vol;
-    v[7] = AmB * v[7] + vol;
-    v[14] = AmB * v[14] + vol;
-    const T sxy = k.C * (v[4] + v[6]);
-    const T sxz = k.C * (v[5] + v[12]);
-    const T syz = k.C * (v[8] + v[13]);
-    v[4] = sxy;
-    v[6] = sxy;
-    v[5] = sxz;
-    v[12] = sxz;
-    v[8] = syz;
-    v[13] = syz;
-    // bilinear pairs (9,20), (10,17), (15,19)
-    T p0 = v[9], p1 = v[20];
-    v[9] = k.D * p0 + k.E * p1;
-    v[20] = k.E * p0 + k.D * p1;
-    p0 = v[10];
-    p1 = v[17];
-    v[10] = k.D * p0 + k.E * p1;
-    v[17] = k.E * p0 + k.D * p1;
-    p0 = v[15];
-    p1 = v[19];
-    v[15] = k.D * p0 + k.E * p1;
-    v[19] = k.E * p0 + k.D * p1;
-    // bilinear triple 11, 16, 18
-    const T tri = k.G * (v[11] + v[16] + v[18]);
-    const T FmG = k.F - k.G;
-    v[11] = FmG * v[11] + tri;
-    v[16] = FmG * v[16] + tri;
-    v[18] = FmG * v[18] + tri;
-    // trilinear
-    v[21] *= k.H;
-    v[22] *= k.H;
-    v[23] *= k.H;
-    hadamard24(v);
-}
-
-struct TileGeom {
-    int nx, ny, nz;
-    int tiles_x, tiles_y, kz;     // tiles in x, y; owned node planes per workgroup
-};
-
-__device__ __forceinline__ int64_t nid(int i, int j, int k, int NX, int NY) {
-    return (int64_t)i + (int64_t)NX * ((int64_t)j + (int64_t)NY * k);
-}
-
-// Node plane k of the tile (nodes [X0-1, X0-1+TXE] x [Y0-1, Y0-1+TYE]) of one
-// or two vectors into LDS, masked, zero outside the grid.  LDS layout
-// [vector][component][node], node = ly*NXL + lx, so lanes reading
-// neighbouring nodes hit neighbouring banks.
-constexpr int kPlaneNodes = NXL * NYL;
-constexpr int kPlaneVals = kPlaneNodes * 3;
-
-constexpr int kPerThread = (kPlaneVals + kTileThreads - 1) / kTileThreads;
-
-template <typename T, int NV>
-struct PlaneRegs {
-    T v[NV][kPerThread];
-};
-
-// issue the global loads of node plane k (masked, zero outside the grid)
-template <typename T, int NV>
-__device__ __forceinline__ void fetch_plane(const TileGeom& g, int X0, int Y0, int k,
-                                            const T* const (&src)[NV],
-                                            const uint8_t* __restrict__ fixed,
-                                            PlaneRegs<T, NV>& pr) {
-    const int NX = g.nx + 1, NY = g.ny + 1;
-#pragma unroll
-    for (int s = 0; s < kPerThread; ++s) {
-        const int q = threadIdx.x + s * kTileThreads;
-        const int c = q % 3, nd = q / 3;
-        const int lx = nd % NXL, ly = nd / NXL;
-        const int i = X0 - 1 + lx, j = Y0 - 1 + ly;
-        const bool in = q < kPlaneVals && k >= 0 && k <= g.nz && i >= 0 && i < NX && j >= 0 &&
-                        j < NY;
-        const int dof = in ? 3 * (i + NX * (j + NY * k)) + c : 0;
-        const bool keep = in && fixed[dof] == 0;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const T val = in ? src[v][dof] : T(0);
-            pr.v[v][s] = keep ? val : T(0);
-        }
-    }
-}
-
-template <typename T, int NV>
-__device__ __forceinline__ void commit_plane(const PlaneRegs<T, NV>& pr, T (*dst)[kPlaneVals]) {
-#pragma unroll
-    for (int s = 0; s < kPerThread; ++s) {
-        const int q = threadIdx.x + s * kTileThreads;
-        if (q < kPlaneVals) {
-            const int c = q % 3, nd = q / 3;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) dst[v][c * kPlaneNodes + nd] = pr.v[v][s];
-        }
-    }
-}
-
-// the element's 24 local values of staged vector v: bottom face from plane
-// buffer `lo`, top face from `hi`
-template <typename T>
-__device__ __forceinline__ T elem_val(const T* lo, const T* hi, int tx, int ty, int q) {
-    const int a = q / 3, c = q % 3;
-    const T* P = (a & 4) ? hi : lo;
-    return P[c * kPlaneNodes + (ty + ((a >> 1) & 1)) * NXL + tx + (a & 1)];
-}
-
-// Plane contributions of one element column (its 4 nodes (tx+ax, ty+ay), 3
-// components each, in v[3*(ax + 2 ay) + c]) are summed into node values.
-// x-neighbours meet through a lane shuffle (a tile row is 16 consecutive
-// lanes of one wave), y-neighbours through the LDS row buffer `part`
-// (one value per node and component).  Fixed order, no atomics.
-template <typename T>
-__device__ __forceinline__ void combine_store(const T (&v)[12], T* part, int tx, int ty,
-                                              bool store, int64_t n,
-                                              const uint8_t* __restrict__ fixed,
-                                              T* __restrict__ y) {
-    T row0[3], row1[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        // node (tx, ty+ay) gets own ax=0 part and the ax=1 part of lane tx-1
-        const T left0 = __shfl_up(v[3 * 1 + c], 1, 16);
-        const T left1 = __shfl_up(v[3 * 3 + c], 1, 16);
-        row0[c] = v[3 * 0 + c] + (tx >= 1 ? left0 : T(0));
-        row1[c] = v[3 * 2 + c] + (tx >= 1 ? left1 : T(0));
-        part[c * kPlaneNodes + (ty + 1) * NXL + tx] = row1[c];
-    }
-    __syncthreads();
-    if (store) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const T s = row0[c] + part[c * kPlaneNodes + ty * NXL + tx];
-            y[3 * n + c] = fixed[3 * n + c] ? T(0) : s;
-        }
-    }
-}
 
 // ---------------------------------------------------------------------------
 // y = K(rho) x, plane-marching form
@@ -331,12 +172,11 @@ __device__ __forceinline__ void face_fwd(const T* buf, int tx, int ty, T (&F)[3]
     }
 }
 
-// the element's modes from its bottom/top face transforms, rho Kh applied, and
-// the result split back into bottom (Gb) and top (Gt) face transforms
+// z-stage of the transform: the element's 24 modes v[3 m + c] (m = mxy + 4 mz)
+// from the face transforms of its bottom (Fb) and top (Ft) faces
 template <typename T>
-__device__ __forceinline__ void elem_modes(const KhVals<T>& k, T r, const T (&Fb)[3][4],
-                                           const T (&Ft)[3][4], T (&Gb)[3][4], T (&Gt)[3][4]) {
-    T v[24];
+__device__ __forceinline__ void modes_from_faces(const T (&Fb)[3][4], const T (&Ft)[3][4],
+                                                 T (&v)[24]) {
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -344,9 +184,13 @@ __device__ __forceinline__ void elem_modes(const KhVals<T>& k, T r, const T (&Fb
             v[3 * m + c] = Fb[c][m] + Ft[c][m];
             v[3 * (m + 4) + c] = Fb[c][m] - Ft[c][m];
         }
+}
+
+// y = r Kh v (the constant modes of v are ignored; y's are zero)
+template <typename T>
+__device__ __forceinline__ void kh_apply(const KhVals<T>& k, T r, const T (&v)[24], T (&y)[24]) {
     const T AmB = r * (k.A - k.B), rB = r * k.B, rC = r * k.C, rD = r * k.D, rE = r * k.E;
     const T FmG = r * (k.F - k.G), rG = r * k.G, rH = r * k.H;
-    T y[24];
     y[0] = y[1] = y[2] = T(0);
     const T vol = rB * (v[3] + v[7] + v[14]);
     y[3] = AmB * v[3] + vol;
@@ -368,6 +212,11 @@ __device__ __forceinline__ void elem_modes(const KhVals<T>& k, T r, const T (&Fb
     y[21] = rH * v[21];
     y[22] = rH * v[22];
     y[23] = rH * v[23];
+}
+
+// inverse z-stage: bottom (Gb) and top (Gt) face transforms of the modes y
+template <typename T>
+__device__ __forceinline__ void faces_from_modes(const T (&y)[24], T (&Gb)[3][4], T (&Gt)[3][4]) {
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -375,6 +224,17 @@ __device__ __forceinline__ void elem_modes(const KhVals<T>& k, T r, const T (&Fb
             Gb[c][m] = y[3 * m + c] + y[3 * (m + 4) + c];
             Gt[c][m] = y[3 * m + c] - y[3 * (m + 4) + c];
         }
+}
+
+// the element's modes from its bottom/top face transforms, rho Kh applied, and
+// the result split back into bottom (Gb) and top (Gt) face transforms
+template <typename T>
+__device__ __forceinline__ void elem_modes(const KhVals<T>& k, T r, const T (&Fb)[3][4],
+                                           const T (&Ft)[3][4], T (&Gb)[3][4], T (&Gt)[3][4]) {
+    T v[24], y[24];
+    modes_from_faces(Fb, Ft, v);
+    kh_apply(k, r, v, y);
+    faces_from_modes(y, Gb, Gt);
 }
 
 // plane contributions in face-transform form -> node values of the column's
@@ -539,85 +399,192 @@ k_apply_K_plane(PlaneGeom g, KhVals<T> kh, const T* __restrict__ x, const T* __r
 }
 
 // ---------------------------------------------------------------------------
-// S [x; beta] = [K(rho') x + sum_e w_e b_e (b_e^T x - beta); -sum_e w_e (b_e^T x - beta)]
-// with b_e = K_e u_e recomputed: y_e = K_e (rho'_e x_e + w_e t_e u_e),
-// t_e = (K_e u_e)^T x_e - beta.  Per-block partial sums of w_e t_e.
+// S [x; beta] of eq. (3.12), plane-marching form: x and u staged together;
+// per element b^ = Kh u^ (b_e = K_e u_e in the transformed basis), t = b^ . x^
+// - beta (= b_e^T x_e - beta: H is symmetric and H H = 8 I per direction pair
+// folded into Kh), y_e = K_e (rho'_e x_e + w_e t u_e) through Kh once more.
+// Per-workgroup partial sums of w t over the elements the tile owns.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kTileThreads)
-k_apply_S_tile(TileGeom g, KhVals<T> kh, const T* __restrict__ x, const T* __restrict__ u,
-               const T* __restrict__ r1, const T* __restrict__ w, const uint8_t* __restrict__ fixed,
-               int64_t ndof, T* __restrict__ y, double* __restrict__ partials) {
-    __shared__ T xs[2][2][kPlaneVals];
-    __shared__ T part[kPlaneVals];
-    __shared__ double red[kTileThreads / 64];
-    const int tx = threadIdx.x % TXE, ty = threadIdx.x / TXE;
-    const int b = blockIdx.x;
-    const int bx = b % g.tiles_x, by = (b / g.tiles_x) % g.tiles_y, bz = b / (g.tiles_x * g.tiles_y);
-    const int X0 = bx * (TXE - 1), Y0 = by * (TYE - 1);
-    const int K0 = bz * g.kz;
-    const int K1 = min(K0 + g.kz, g.nz + 1);
-    const int ex = X0 - 1 + tx, ey = Y0 - 1 + ty;
-    const bool col_ok = ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny;
-    const int NX = g.nx + 1, NY = g.ny + 1;
-    const int i = X0 - 1 + tx, j = Y0 - 1 + ty;
-    const bool owner = tx >= 1 && ty >= 1 && i < NX && j < NY;
-    const T beta = x[ndof];
-    const T* const src[2] = {x, u};
-    double wsum = 0.0;
+struct SMarch {
+    int tx, ty, K0, K1, NX, NY, ex, ey;   // (ex, ey): this thread's element column = node
+    int64_t plane_nodes;
+    bool col_ok, owner, own_col;
+    PlaneSlots ps;
+    T (*rx)[kPV];
+    T (*ru)[kPV];
+    uint8_t (*mring)[kPN];
+    T (*part)[3][kTileThreads];
+    PlaneRegsK<T> px[2], pu[2];
+    T r1pre[2], wpre[2];
+    T Gtp[3][4];
+    T pend[3];
+    uint32_t omask;
+    double wsum;
 
-    PlaneRegs<T, 2> pre;
-    T topacc[12];
-#pragma unroll
-    for (int q = 0; q < 12; ++q) topacc[q] = T(0);
-    fetch_plane<T, 2>(g, X0, Y0, K0 - 1, src, fixed, pre);
-    commit_plane<T, 2>(pre, xs[(K0 - 1) & 1]);
-    fetch_plane<T, 2>(g, X0, Y0, K0, src, fixed, pre);
-    for (int l = K0 - 1; l < K1; ++l) {
-        commit_plane<T, 2>(pre, xs[(l + 1) & 1]);
-        if (l + 1 < K1) fetch_plane<T, 2>(g, X0, Y0, l + 2, src, fixed, pre);
-        const bool el_ok = col_ok && l >= 0 && l < g.nz;
-        const int e = el_ok ? ex + g.nx * (ey + g.ny * l) : 0;
-        const T rr = el_ok ? r1[e] : T(0), ww = el_ok ? w[e] : T(0);
-        __syncthreads();
-        const T* xlo = xs[l & 1][0];
-        const T* xhi = xs[(l + 1) & 1][0];
-        const T* ulo = xs[l & 1][1];
-        const T* uhi = xs[(l + 1) & 1][1];
-        T v[24];
-        // b_e = K_e u_e, t = b_e . x_e - beta
-#pragma unroll
-        for (int q = 0; q < 24; ++q) v[q] = elem_val(ulo, uhi, tx, ty, q);
-        ke_apply(kh, T(1), v);
-        T t = T(0);
-#pragma unroll
-        for (int q = 0; q < 24; ++q) t += v[q] * elem_val(xlo, xhi, tx, ty, q);
-        t -= beta;
-        const T wt = ww * t;                   // 0 outside the grid
-        // the tile's halo elements are counted by their owning tile
-        if (el_ok && tx >= 1 && ty >= 1 && l >= K0) wsum += (double)wt;
-#pragma unroll
-        for (int q = 0; q < 24; ++q)
-            v[q] = rr * elem_val(xlo, xhi, tx, ty, q) + wt * elem_val(ulo, uhi, tx, ty, q);
-        ke_apply(kh, T(1), v);
-        T face[12];
-#pragma unroll
-        for (int q = 0; q < 12; ++q) {
-            face[q] = v[q] + topacc[q];
-            topacc[q] = v[12 + q];
-        }
-        combine_store(face, part, tx, ty, l >= K0 && owner,
-                      (int64_t)i + NX * ((int64_t)j + NY * l), fixed, y);
-        __syncthreads();
+    __device__ __forceinline__ int64_t clamp_plane(int k, int nz) const {
+        return (int64_t)(k < 0 ? 0 : (k > nz ? nz : k)) * plane_nodes;
     }
-    // block partial of sum w t
-    for (int off = 32; off > 0; off >>= 1) wsum += __shfl_down(wsum, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = wsum;
+};
+
+template <typename T>
+__device__ __forceinline__ void s_fetch_elem(SMarch<T>& M, const PlaneGeom& g, const T* r1,
+                                             const T* w, int le, T& r, T& ww) {
+    const bool ok = M.col_ok && le >= 0 && le < g.nz;
+    const int64_t e = M.ex + (int64_t)g.nx * (M.ey + (int64_t)g.ny * le);
+    r = ok ? r1[e] : T(0);
+    ww = ok ? w[e] : T(0);
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void s_step(SMarch<T>& M, const PlaneGeom& g, const KhVals<T>& kh,
+                                       const T* __restrict__ x, const T* __restrict__ u,
+                                       const T* __restrict__ r1, const T* __restrict__ w,
+                                       const uint8_t* __restrict__ nmask, T beta,
+                                       T* __restrict__ y, int l) {
+    const int rel = l + 1 - (M.K0 - 1);
+    plane_commit(M.ps, M.px[S], M.rx[rel % kRing], M.mring[rel % kRing]);
+    plane_commit(M.ps, M.pu[S], M.ru[rel % kRing], M.mring[rel % kRing]);
+    if (l + 3 <= M.K1) {
+        plane_fetch(M.ps, x, nmask, M.clamp_plane(l + 3, g.nz), M.px[S]);
+        plane_fetch(M.ps, u, nmask, M.clamp_plane(l + 3, g.nz), M.pu[S]);
+    }
+    const T rr = M.r1pre[S], ww = M.wpre[S];
+    s_fetch_elem(M, g, r1, w, l + 2, M.r1pre[S], M.wpre[S]);
+    __syncthreads();
+    if (l - 1 >= M.K0 && M.owner) {
+        const T* pp = &M.part[(rel - 2) & 1][0][0];
+        const int64_t n = (int64_t)(l - 1) * M.plane_nodes + (int64_t)M.ey * M.NX + M.ex;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T v = M.pend[c] + pp[c * kTileThreads + (M.ty - 1) * TXE + M.tx];
+            y[3 * n + c] = ((M.omask >> c) & 1u) ? T(0) : v;
+        }
+    }
+    M.omask = M.mring[(rel - 1) % kRing][M.ty * NXL + M.tx];
+    // bottom faces from the plane still in the ring (keeps registers low)
+    T vx[24], vu[24], b[24];
+    {
+        T Fb[3][4], Ft[3][4];
+        face_fwd(M.rx[(rel - 1) % kRing], M.tx, M.ty, Fb);
+        face_fwd(M.rx[rel % kRing], M.tx, M.ty, Ft);
+        modes_from_faces(Fb, Ft, vx);
+        face_fwd(M.ru[(rel - 1) % kRing], M.tx, M.ty, Fb);
+        face_fwd(M.ru[rel % kRing], M.tx, M.ty, Ft);
+        modes_from_faces(Fb, Ft, vu);
+    }
+    kh_apply(kh, T(1), vu, b);
+    T t = T(0);
+#pragma unroll
+    for (int q = 3; q < 24; ++q) t += b[q] * vx[q];
+    t -= beta;
+    const T wt = ww * t;                                  // 0 outside the grid
+    if (M.own_col && l >= M.K0) M.wsum += (double)wt;     // elements owned by this tile
+#pragma unroll
+    for (int q = 3; q < 24; ++q) vx[q] = rr * vx[q] + wt * vu[q];
+    kh_apply(kh, T(1), vx, b);
+    T Gb[3][4], Gt[3][4];
+    faces_from_modes(b, Gb, Gt);
+    T P[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            P[c][m] = Gb[c][m] + M.Gtp[c][m];
+            M.Gtp[c][m] = Gt[c][m];
+        }
+    T row0[3], row1[3];
+    face_inv_combine(P, row0, row1);
+    T* pw = &M.part[(rel - 1) & 1][0][0];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        pw[c * kTileThreads + M.ty * TXE + M.tx] = row1[c];
+        M.pend[c] = row0[c];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTileThreads)
+k_apply_S_plane(PlaneGeom g, KhVals<T> kh, const T* __restrict__ x, const T* __restrict__ u,
+                const T* __restrict__ r1, const T* __restrict__ w,
+                const uint8_t* __restrict__ nmask, int64_t ndof, T* __restrict__ y,
+                double* __restrict__ partials) {
+    __shared__ T rx[kRing][kPV];
+    __shared__ T ru[kRing][kPV];
+    __shared__ uint8_t mring[kRing][kPN];
+    __shared__ T part[2][3][kTileThreads];
+    __shared__ double red[kTileThreads / 64];
+    const int lb = logical_block(g);
+    if (lb < 0) return;
+    SMarch<T> M;
+    M.tx = threadIdx.x % TXE;
+    M.ty = threadIdx.x / TXE;
+    const int bx = lb % g.tiles_x, by = (lb / g.tiles_x) % g.tiles_y;
+    const int bz = lb / (g.tiles_x * g.tiles_y);
+    const int X0 = bx * (TXE - 1), Y0 = by * (TYE - 1);
+    M.NX = g.nx + 1;
+    M.NY = g.ny + 1;
+    M.K0 = (int)((int64_t)(g.nz + 1) * bz / g.zblocks);
+    M.K1 = (int)((int64_t)(g.nz + 1) * (bz + 1) / g.zblocks);
+    M.plane_nodes = (int64_t)M.NX * M.NY;
+    M.ex = X0 - 1 + M.tx;
+    M.ey = Y0 - 1 + M.ty;
+    M.col_ok = M.ex >= 0 && M.ex < g.nx && M.ey >= 0 && M.ey < g.ny;
+    M.owner = M.tx >= 1 && M.ty >= 1 && M.ex < M.NX && M.ey < M.NY;
+    M.own_col = M.col_ok && M.tx >= 1 && M.ty >= 1;
+    M.ps = plane_slots(X0, Y0, M.NX, M.NY);
+    M.rx = rx;
+    M.ru = ru;
+    M.mring = mring;
+    M.part = part;
+    M.omask = 0;
+    M.wsum = 0.0;
+    const T beta = x[ndof];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        M.pend[c] = T(0);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) M.Gtp[c][m] = T(0);
+    }
+    plane_fetch(M.ps, x, nmask, M.clamp_plane(M.K0 - 1, g.nz), M.px[0]);
+    plane_fetch(M.ps, u, nmask, M.clamp_plane(M.K0 - 1, g.nz), M.pu[0]);
+    plane_fetch(M.ps, x, nmask, M.clamp_plane(M.K0, g.nz), M.px[1]);
+    plane_fetch(M.ps, u, nmask, M.clamp_plane(M.K0, g.nz), M.pu[1]);
+    s_fetch_elem(M, g, r1, w, M.K0 - 1, M.r1pre[1], M.wpre[1]);
+    s_fetch_elem(M, g, r1, w, M.K0, M.r1pre[0], M.wpre[0]);
+    plane_commit(M.ps, M.px[0], M.rx[0], M.mring[0]);
+    plane_commit(M.ps, M.pu[0], M.ru[0], M.mring[0]);
+    if (M.K0 + 1 <= M.K1) {
+        plane_fetch(M.ps, x, nmask, M.clamp_plane(M.K0 + 1, g.nz), M.px[0]);
+        plane_fetch(M.ps, u, nmask, M.clamp_plane(M.K0 + 1, g.nz), M.pu[0]);
+    }
+    __syncthreads();
+    int l = M.K0 - 1;
+    for (;;) {
+        s_step<T, 1>(M, g, kh, x, u, r1, w, nmask, beta, y, l);
+        if (++l >= M.K1) break;
+        s_step<T, 0>(M, g, kh, x, u, r1, w, nmask, beta, y, l);
+        if (++l >= M.K1) break;
+    }
+    __syncthreads();
+    if (M.owner) {
+        const T* pp = &M.part[(M.K1 - M.K0) & 1][0][0];
+        const int64_t n = (int64_t)(M.K1 - 1) * M.plane_nodes + (int64_t)M.ey * M.NX + M.ex;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T v = M.pend[c] + pp[c * kTileThreads + (M.ty - 1) * TXE + M.tx];
+            y[3 * n + c] = ((M.omask >> c) & 1u) ? T(0) : v;
+        }
+    }
+    // block partial of sum w t (fixed order)
+    double ws = M.wsum;
+    for (int off = 32; off > 0; off >>= 1) ws += __shfl_down(ws, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ws;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int q = 0; q < kTileThreads / 64; ++q) s += red[q];
-        partials[blockIdx.x] = s;
+        double sum = 0.0;
+        for (int q = 0; q < kTileThreads / 64; ++q) sum += red[q];
+        partials[lb] = sum;
     }
 }
 
@@ -633,25 +600,6 @@ __global__ void k_sum_neg(const double* __restrict__ partials, int nb, double* _
         __syncthreads();
     }
     if (threadIdx.x == 0) dst[0] = -sh[0];
-}
-
-TileGeom geom_of(const Ctx& c, int kz) {
-    TileGeom g;
-    g.nx = c.nx;
-    g.ny = c.ny;
-    g.nz = c.nz;
-    g.tiles_x = (c.nx + 1 + TXE - 2) / (TXE - 1);
-    g.tiles_y = (c.ny + 1 + TYE - 2) / (TYE - 1);
-    g.kz = kz;
-    return g;
-}
-
-// owned node planes per workgroup: enough workgroups to fill the chip
-int choose_kz(const Ctx& c) {
-    const int cols = ((c.nx + TXE - 1) / (TXE - 1)) * ((c.ny + TYE - 1) / (TYE - 1));
-    int kz = 16;
-    while (kz > 2 && (int64_t)cols * ((c.nz + 1 + kz - 1) / kz) < 2048) kz /= 2;
-    return kz;
 }
 
 PlaneGeom plane_geom(const Ctx& c, int zblocks) {
@@ -700,19 +648,16 @@ void launch_apply_K_tile_f32(Ctx& c, const float* rho, const float* x, float* y)
 }
 
 int apply_S_tile_blocks(const Ctx& c) {
-    const int kz = choose_kz(c);
-    TileGeom g = geom_of(c, kz);
-    return g.tiles_x * g.tiles_y * ((c.nz + 1 + kz - 1) / kz);
+    return plane_geom(c, choose_zblocks(c)).nblocks;
 }
 
 void launch_apply_S_tile_ws(Ctx& c, const double* x, double* y, double* partials) {
-    const int kz = choose_kz(c);
-    TileGeom g = geom_of(c, kz);
-    KhVals<double> kh{c.kh8[0], c.kh8[1], c.kh8[2], c.kh8[3], c.kh8[4], c.kh8[5], c.kh8[6], c.kh8[7]};
-    const int nb = g.tiles_x * g.tiles_y * ((c.nz + 1 + kz - 1) / kz);
-    hipLaunchKernelGGL(k_apply_S_tile<double>, dim3(nb), dim3(kTileThreads), 0, c.s, g, kh, x, c.u,
-                       c.r1, c.w, c.fixed, c.ndof, y, partials);
-    hipLaunchKernelGGL(k_sum_neg, dim3(1), dim3(256), 0, c.s, partials, nb, y + c.ndof);
+    const PlaneGeom g = plane_geom(c, choose_zblocks(c));
+    const KhVals<double> kh{c.kh8[0], c.kh8[1], c.kh8[2], c.kh8[3],
+                            c.kh8[4], c.kh8[5], c.kh8[6], c.kh8[7]};
+    hipLaunchKernelGGL(k_apply_S_plane<double>, dim3(8 * g.per_xcd), dim3(kTileThreads), 0, c.s,
+                       g, kh, x, c.u, c.r1, c.w, c.nmask, c.ndof, y, partials);
+    hipLaunchKernelGGL(k_sum_neg, dim3(1), dim3(256), 0, c.s, partials, g.nblocks, y + c.ndof);
 }
 
 void launch_apply_S_tile(Ctx& c, const double* x, double* y) {
@@ -747,7 +692,7 @@ vts_status scratch_partials(int device, double** out, std::string& err) {
         }
         void* p = nullptr;
         const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
-        if (cur != device) hipSetDevice(cur);
+        if (cur != device) (void)hipSetDevice(cur);
         if (e != hipSuccess || !p) {
             err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
             return VTS_EDEVICE;
