@@ -119,6 +119,12 @@ bool nested(const std::vector<uint8_t>& fm, const Dims& f, const std::vector<uin
     return true;
 }
 
+// the finest level keeps no stencil when it is too large for the one-workgroup
+// V-cycle (its Gauss-Seidel rows are formed from the element data instead)
+bool fine_matrix_free(int levels, int64_t fine_nodes) {
+    return levels >= 2 && fine_nodes > kSmallNodes;
+}
+
 Plan make_plan(const vts_problem* pr) {
     Plan p;
     const Dims d{pr->nx, pr->ny, pr->nz};
@@ -147,7 +153,13 @@ Plan make_plan(const vts_problem* pr) {
     for (int k = pr->levels - 1; k >= 0; --k) {
         const int64_t lnn = nodes_of(dl), lm = (int64_t)dl.nx * dl.ny * dl.nz;
         add(3 * lnn);                                                // fixed
-        add(kStencilVals * lnn * ts); add(9 * lnn * ts); add(3 * lnn * ts);
+        if (k == pr->levels - 1 && fine_matrix_free(pr->levels, lnn)) {
+            add(24 * lnn * ts); add(lm * ts);                        // bc, te
+            if (ts == 4) { add(lm * 4); add(lm * 4); add(3 * lnn * 4); }   // r1f, wf, uf
+        } else {
+            add(kStencilVals * lnn * ts);                            // stencil
+        }
+        add(9 * lnn * ts); add(3 * lnn * ts);                        // dinv, acol
         if (k < pr->levels - 1) {
             add(576 * lm * ts);                                      // E
             if (k > 0) add(576 * lm * ts);                           // TQ (levels with a parent)
@@ -219,7 +231,23 @@ vts_status build_hierarchy(Ctx& c, Hierarchy<T>& H, const std::vector<uint8_t>& 
         fill_level_geom(Lk, dims[k]);
         ALLOC(Lk.fixed, 3 * Lk.nn);
         HIPCHK(hipMemcpyAsync(Lk.fixed, masks[k].data(), 3 * Lk.nn, hipMemcpyHostToDevice, c.s));
-        ALLOC(Lk.st, (int64_t)kStencilVals * Lk.nn);
+        if (k == L - 1 && fine_matrix_free(L, Lk.nn)) {
+            H.mf = true;
+            ALLOC(H.bc, 24 * Lk.nn);
+            ALLOC(H.te, Lk.m);
+            if (sizeof(T) == 4) {
+                ALLOC(H.r1f, Lk.m);
+                ALLOC(H.wf, Lk.m);
+                ALLOC(H.uf, 3 * Lk.nn);
+            } else {
+                // FP64 levels read the context's own vectors
+                H.r1f = (T*)c.r1;
+                H.wf = (T*)c.w;
+                H.uf = (T*)c.u;
+            }
+        } else {
+            ALLOC(Lk.st, (int64_t)kStencilVals * Lk.nn);
+        }
         ALLOC(Lk.dinv, 9 * Lk.nn);
         ALLOC(Lk.acol, 3 * Lk.nn);
         if (k < L - 1) {
@@ -870,6 +898,7 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
     double Ke[576], Q[512], Mc[8 * 576];
     float Kef[576];
     element_stiffness(c.E, c.nu, c.h, Ke);
+    std::memcpy(c.ke_host, Ke, sizeof(Ke));
     child_interp(Q);
     galerkin_child_matrices(Ke, Q, Mc);
     for (int q = 0; q < 576; ++q) Kef[q] = (float)Ke[q];

@@ -144,6 +144,64 @@ k_fine_stencil(Level<T> L, const double* __restrict__ Ke, const double* __restri
     for (int c = 0; c < 3; ++c) L.acol[3 * n + c] = fx[c] ? T(0) : (T)ac[c];
 }
 
+// ---------------------------------------------------------------------------
+// finest level without a stored stencil: per node (colour-major t) its 3x3
+// diagonal block sum_e rho'_e K_e[a,a] + w_e b_{e,a} b_{e,a}^T (inverted, masked),
+// the alpha column -sum_e w_e b_{e,a}, and bc[t][o] = b_{e,a} of the element
+// at offset o in {-1,0}^3 (the node is its corner a = o; zero outside the grid)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_fine_mf_setup(Level<T> L, const double* __restrict__ Ke, const double* __restrict__ r1,
+                const double* __restrict__ w, const double* __restrict__ be, T* __restrict__ bc) {
+    const int64_t t = gidx();
+    if (t >= L.nn) return;
+    int i, j, k;
+    cm_decode(L, t, i, j, k);
+    const int64_t n = nat(i, j, k, L.NX, L.NY);
+    const int64_t m = L.m;
+    double D[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double ac[3] = {0, 0, 0};
+    for (int o = 0; o < 8; ++o) {
+        const int ii = i - (o & 1), jj = j - ((o >> 1) & 1), kk = k - (o >> 2);
+        const bool in = ii >= 0 && ii < L.nx && jj >= 0 && jj < L.ny && kk >= 0 && kk < L.nz;
+        double bv[3] = {0, 0, 0};
+        if (in) {
+            const int64_t e = ii + (int64_t)L.nx * (jj + (int64_t)L.ny * kk);
+            const double rr = r1[e], ww = w[e];
+            for (int r = 0; r < 3; ++r) bv[r] = be[(3 * o + r) * m + e];
+            for (int r = 0; r < 3; ++r) {
+                for (int cc = 0; cc < 3; ++cc)
+                    D[r * 3 + cc] += rr * Ke[(3 * o + r) * 24 + 3 * o + cc] + ww * bv[r] * bv[cc];
+                ac[r] -= ww * bv[r];
+            }
+        }
+        for (int r = 0; r < 3; ++r) bc[t * 24 + 3 * o + r] = (T)bv[r];
+    }
+    bool fx[3];
+    for (int cc = 0; cc < 3; ++cc) fx[cc] = L.fixed[3 * n + cc] != 0;
+    // inverse of the block rounded to T, as for the stored stencil
+    double d0[9], di[9];
+    for (int q = 0; q < 9; ++q) d0[q] = (double)(T)D[q];
+    masked_inverse3(d0, fx, di);
+    for (int q = 0; q < 9; ++q) L.dinv[(int64_t)q * L.nn + t] = (T)di[q];
+    for (int cc = 0; cc < 3; ++cc) L.acol[3 * n + cc] = fx[cc] ? T(0) : (T)ac[cc];
+}
+
+// rho', w (m each) and u (3 nn) in the level precision
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_fine_mf_convert(int64_t m, int64_t nu, const double* __restrict__ r1,
+                  const double* __restrict__ w, const double* __restrict__ u, T* __restrict__ r1f,
+                  T* __restrict__ wf, T* __restrict__ uf) {
+    const int64_t t = gidx();
+    if (t < m) {
+        r1f[t] = (T)r1[t];
+        wf[t] = (T)w[t];
+    }
+    if (t < nu) uf[t] = (T)u[t];
+}
+
 // g_e = Q_{c(e)}^T b_e: the element force seen from the parent element's nodes
 __global__ void k_child_g(int nx, int ny, int nz, const double* __restrict__ Q,
                           const double* __restrict__ be, double* __restrict__ gch) {
@@ -305,11 +363,11 @@ k_acol_dot(Level<T> L, const T* __restrict__ z, double* partials) {
 // barriers).  Same partial-sum order and the same operations as k_alpha_fin,
 // so the result is bitwise the same: returns v = r_a - (T)(sum partials) - d z_a.
 template <typename T>
-__device__ __forceinline__ T alpha_residual(const double* __restrict__ partials, int slot, int nb,
-                                            double d, T ra, T za, double* sh) {
+__device__ __forceinline__ T alpha_residual(const double* __restrict__ parts, int nb, double d,
+                                            T ra, T za, double* sh) {
     if ((int)threadIdx.x < kThreads) {
         double x = 0.0;
-        for (int b = threadIdx.x; b < nb; b += kThreads) x += partials[slot * kRedBlocks + b];
+        for (int b = threadIdx.x; b < nb; b += kThreads) x += parts[b];
         sh[threadIdx.x] = x;
     }
     __syncthreads();
@@ -357,15 +415,15 @@ __global__ void k_alpha_fin(const double* __restrict__ partials, int nb, int64_t
 // ---------------------------------------------------------------------------
 // restriction P^T; with_alpha: the alpha entry by identity.  With nb > 0 the
 // parent's alpha residual res_a = r_a - acol.z - d z_a is formed here first
-// (block 0, from the nb partial sums of the residual kernel in SL_STAT) and
+// (block 0, from the nb partial sums parts of acol . z of the residual kernel) and
 // becomes the coarse alpha entry.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_restrict(Level<T> F, Level<T> C, const T* __restrict__ rf, T* __restrict__ rc, int with_alpha,
-           const double* __restrict__ partials, int nb, double d) {
+           const double* __restrict__ parts, int nb, double d) {
     __shared__ double sh[kThreads];
     if (nb > 0 && blockIdx.x == 0) {
-        const T v = alpha_residual<T>(partials, SL_STAT, nb, d, F.r[3 * F.nn], F.z[3 * F.nn], sh);
+        const T v = alpha_residual<T>(parts, nb, d, F.r[3 * F.nn], F.z[3 * F.nn], sh);
         if (threadIdx.x == 0) {
             F.res[3 * F.nn] = v;
             rc[3 * C.nn] = v;
@@ -597,11 +655,11 @@ k_top_init(Level<T> L, const double* __restrict__ rin) {
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_restrict_init(Level<T> F, Level<T> C, const T* __restrict__ rf,
-                const double* __restrict__ partials, int nb, double d) {
+                const double* __restrict__ parts, int nb, double d) {
     __shared__ double sh[kThreads];
     T va = T(0);
     if (blockIdx.x == 0)
-        va = alpha_residual<T>(partials, SL_STAT, nb, d, F.r[3 * F.nn], F.z[3 * F.nn], sh);
+        va = alpha_residual<T>(parts, nb, d, F.r[3 * F.nn], F.z[3 * F.nn], sh);
     const int64_t N = gidx();
     if (N < C.nn) {
         const int I = (int)(N % C.NX);
@@ -639,6 +697,151 @@ k_restrict_init(Level<T> F, Level<T> C, const T* __restrict__ rf,
         F.res[3 * F.nn] = va;
         C.r[3 * C.nn] = va;
         C.z[3 * C.nn] = T(0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// finest level without a stored stencil: one Gauss-Seidel colour pass, one
+// thread per node of the colour.  The node's row of S z is formed from its 8
+// elements: rho'_e (K_e z_e)_a + w_e b_{e,a} (b_e^T z_e), with b_e^T z_e = te
+// kept current by the passes themselves (after the update of the node, each
+// of its elements gets te += b_{e,a} . dz; every element has exactly one
+// node of each colour, so each te has one writer per pass).  K_e's rows are
+// the same for every thread of the launch (a = element offset o).
+// ---------------------------------------------------------------------------
+constexpr int kMfBlock = 64;   // one wave per workgroup: many workgroups at every grid size
+
+// The rows of K_e at corner a follow from those at corner 0 by the cube's
+// reflections: K_e[3a+r][3b+c] = s_r(a) s_c(a) K0[a^b][r][c], s_r(a) = -1 if
+// bit r of a is set (reflecting axis r maps corner a to a ^ 2^r and flips the
+// r components).  K0[d][r][c] = K_e[r][3d+c]: 72 numbers for all corners.
+template <typename T>
+struct KeRows0 {
+    T v[8 * 9];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kMfBlock)
+k_gs_mf(Level<T> L, int col, KeRows0<T> K0, const T* __restrict__ r1, const T* __restrict__ w,
+        const T* __restrict__ bc, T* __restrict__ te) {
+    const int64_t tl = gidx();
+    const int64_t cnt = L.coff[col + 1] - L.coff[col];
+    if (tl >= cnt) return;
+    const int64_t tcm = L.coff[col] + tl;
+    int64_t q = tl;
+    const int i = 2 * (int)(q % L.cnx[col]) + (col & 1);
+    q /= L.cnx[col];
+    const int j = 2 * (int)(q % L.cny[col]) + ((col >> 1) & 1);
+    const int k = 2 * (int)(q / L.cny[col]) + (col >> 2);
+    const int64_t n = nat(i, j, k, L.NX, L.NY);
+    T* __restrict__ z = L.z;
+    const T za = z[3 * L.nn];
+    T b0 = L.r[3 * n] - L.acol[3 * n] * za;
+    T b1 = L.r[3 * n + 1] - L.acol[3 * n + 1] * za;
+    T b2 = L.r[3 * n + 2] - L.acol[3 * n + 2] * za;
+    // the 8 elements around the node (offset o: bit set = element on the low side;
+    // the node is the element's corner a = o): rho', and the rank-one terms
+    T rr[8], tv[8];
+    int64_t ei[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        const int ii = i - (o & 1), jj = j - ((o >> 1) & 1), kk = k - (o >> 2);
+        const bool in = ii >= 0 && ii < L.nx && jj >= 0 && jj < L.ny && kk >= 0 && kk < L.nz;
+        const int64_t e = in ? ii + (int64_t)L.nx * (jj + (int64_t)L.ny * kk) : -1;
+        ei[o] = e;
+        rr[o] = in ? r1[e] : T(0);
+        tv[o] = in ? te[e] : T(0);
+        const T wt = (in ? w[e] : T(0)) * tv[o];
+        const T* bb = bc + tcm * 24 + 3 * o;
+        b0 -= wt * bb[0];
+        b1 -= wt * bb[1];
+        b2 -= wt * bb[2];
+    }
+    // K(rho') z at the node, neighbour by neighbour: neighbour at offset
+    // (dx, dy, dz) is node bn = a ^ d of element o when it lies in that element
+    T zc0 = 0, zc1 = 0, zc2 = 0;
+#pragma unroll
+    for (int s = 0; s < 27; ++s) {
+        const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+        const int ii = i + dx, jj = j + dy, kk = k + dz;
+        const bool in = ii >= 0 && ii < L.NX && jj >= 0 && jj < L.NY && kk >= 0 && kk < L.NZ;
+        const int64_t mm = in ? nat(ii, jj, kk, L.NX, L.NY) : n;
+        const T x0 = in ? z[3 * mm] : T(0), x1 = in ? z[3 * mm + 1] : T(0),
+                x2 = in ? z[3 * mm + 2] : T(0);
+        if (s == 13) {
+            zc0 = x0;
+            zc1 = x1;
+            zc2 = x2;
+        }
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            // element o spans offsets -(o bit) .. 1 - (o bit) along each axis
+            const int lx = -(o & 1), ly = -((o >> 1) & 1), lz = -(o >> 2);
+            if (dx < lx || dx > lx + 1 || dy < ly || dy > ly + 1 || dz < lz || dz > lz + 1)
+                continue;
+            const int bn = (dx - lx) | ((dy - ly) << 1) | ((dz - lz) << 2);
+            const int dd = o ^ bn;
+            // s_c(a) rho'_e z_c, then s_r(a) sum_c K0[d][r][c] (.)
+            const T p0 = ((o & 1) ? -rr[o] : rr[o]) * x0;
+            const T p1 = ((o & 2) ? -rr[o] : rr[o]) * x1;
+            const T p2 = ((o & 4) ? -rr[o] : rr[o]) * x2;
+            const T y0 = K0.v[dd * 9 + 0] * p0 + K0.v[dd * 9 + 1] * p1 + K0.v[dd * 9 + 2] * p2;
+            const T y1 = K0.v[dd * 9 + 3] * p0 + K0.v[dd * 9 + 4] * p1 + K0.v[dd * 9 + 5] * p2;
+            const T y2 = K0.v[dd * 9 + 6] * p0 + K0.v[dd * 9 + 7] * p1 + K0.v[dd * 9 + 8] * p2;
+            if (o & 1) b0 += y0; else b0 -= y0;
+            if (o & 2) b1 += y1; else b1 -= y1;
+            if (o & 4) b2 += y2; else b2 -= y2;
+        }
+    }
+    T D[9];
+#pragma unroll
+    for (int q9 = 0; q9 < 9; ++q9) D[q9] = L.dinv[(int64_t)q9 * L.nn + tcm];
+    const T d0 = D[0] * b0 + D[1] * b1 + D[2] * b2;
+    const T d1 = D[3] * b0 + D[4] * b1 + D[5] * b2;
+    const T d2 = D[6] * b0 + D[7] * b1 + D[8] * b2;
+    z[3 * n] = zc0 + d0;
+    z[3 * n + 1] = zc1 + d1;
+    z[3 * n + 2] = zc2 + d2;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        if (ei[o] < 0) continue;
+        const T* bb = bc + tcm * 24 + 3 * o;
+        te[ei[o]] = tv[o] + (bb[0] * d0 + bb[1] * d1 + bb[2] * d2);
+    }
+}
+
+// finest level without a stored stencil: r (FP64 S-vector) into T, the first
+// colour (z = D^-1 r on colour-0 nodes, zero elsewhere), and te = b_e^T z_e,
+// written by each element's colour-0 node
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_top_init_mf(Level<T> L, const double* __restrict__ rin, const T* __restrict__ bc,
+              T* __restrict__ te) {
+    const int64_t N = gidx();
+    if (N < L.nn) {
+        const int i = (int)(N % L.NX);
+        const int64_t tt = N / L.NX;
+        const int j = (int)(tt % L.NY), k = (int)(tt / L.NY);
+        const T r0 = (T)rin[3 * N], r1 = (T)rin[3 * N + 1], r2 = (T)rin[3 * N + 2];
+        L.r[3 * N] = r0;
+        L.r[3 * N + 1] = r1;
+        L.r[3 * N + 2] = r2;
+        first_colour(L, N, i, j, k, r0, r1, r2);
+        if (((i | j | k) & 1) == 0) {
+            const int64_t t = cm_index(L, i, j, k);
+            const T z0 = L.z[3 * N], z1 = L.z[3 * N + 1], z2 = L.z[3 * N + 2];
+            for (int o = 0; o < 8; ++o) {
+                const int ii = i - (o & 1), jj = j - ((o >> 1) & 1), kk = k - (o >> 2);
+                if (ii < 0 || ii >= L.nx || jj < 0 || jj >= L.ny || kk < 0 || kk >= L.nz) continue;
+                const T* bb = bc + t * 24 + 3 * o;
+                te[ii + (int64_t)L.nx * (jj + (int64_t)L.ny * kk)] =
+                    bb[0] * z0 + bb[1] * z1 + bb[2] * z2;
+            }
+        }
+    }
+    if (N == 0) {
+        L.r[3 * L.nn] = (T)rin[3 * L.nn];
+        L.z[3 * L.nn] = T(0);
     }
 }
 
@@ -742,7 +945,8 @@ k_resid9(Level<T> L, const T* __restrict__ r, T* __restrict__ z, T* __restrict__
     __shared__ T part[2][kRowWaves][3][64];
     __shared__ double sh[kThreads];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const T za = T(0) + alpha_residual<T>(partials, SL_AUX, nb, d, r[3 * L.nn], T(0), sh) / (T)d;
+    const T za = T(0) + alpha_residual<T>(partials + SL_AUX * kRedBlocks, nb, d, r[3 * L.nn], T(0),
+                                          sh) / (T)d;
     if (blockIdx.x == 0 && threadIdx.x == 0) z[3 * L.nn] = za;
     double acc = 0.0;
     int buf = 0;
@@ -1089,8 +1293,18 @@ template <typename T>
 void mg_build(Ctx& c, Hierarchy<T>& H) {
     const int L = (int)H.lev.size();
     Level<T>& fine = H.lev[L - 1];
-    hipLaunchKernelGGL(k_fine_stencil<T>, dim3(grid_of(fine.nn)), dim3(kThreads), 0, c.s, fine,
-                       c.Ke, c.r1, c.w, c.be);
+    if (H.mf) {
+        hipLaunchKernelGGL(k_fine_mf_setup<T>, dim3(grid_of(fine.nn)), dim3(kThreads), 0, c.s,
+                           fine, c.Ke, c.r1, c.w, c.be, H.bc);
+        if (sizeof(T) == 4)
+            hipLaunchKernelGGL(k_fine_mf_convert<T>,
+                               dim3(grid_of(std::max<int64_t>(fine.m, 3 * fine.nn))),
+                               dim3(kThreads), 0, c.s, fine.m, 3 * fine.nn, c.r1, c.w, c.u, H.r1f,
+                               H.wf, H.uf);
+    } else {
+        hipLaunchKernelGGL(k_fine_stencil<T>, dim3(grid_of(fine.nn)), dim3(kThreads), 0, c.s,
+                           fine, c.Ke, c.r1, c.w, c.be);
+    }
     if (L >= 2) {
         hipLaunchKernelGGL(k_child_g, dim3(grid_of(c.m)), dim3(kThreads), 0, c.s, c.nx, c.ny, c.nz,
                            c.Qc, c.be, c.gch);
@@ -1151,6 +1365,29 @@ static void gs_sweep(Ctx& c, Level<T>& Lk, bool forward, bool top) {
     if (prof) prof_end(c, bytes, launches);
 }
 
+// the same sweep on the finest level without a stored stencil
+template <typename T>
+static void gs_sweep_mf(Ctx& c, Hierarchy<T>& H, Level<T>& Lk, bool forward) {
+    const bool prof = prof_begin(c, VTS_PROF_GS_FINE);
+    KeRows0<T> K0;
+    for (int d = 0; d < 8; ++d)
+        for (int r = 0; r < 3; ++r)
+            for (int q = 0; q < 3; ++q) K0.v[d * 9 + r * 3 + q] = (T)c.ke_host[r * 24 + 3 * d + q];
+    double bytes = 0.0;
+    int launches = 0;
+    for (int q = forward ? 1 : 0; q < 8; ++q) {
+        const int col = forward ? q : 7 - q;
+        const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
+        if (cnt == 0) continue;
+        hipLaunchKernelGGL(k_gs_mf<T>, dim3((unsigned)((cnt + kMfBlock - 1) / kMfBlock)),
+                           dim3(kMfBlock), 0, c.s, Lk, col, K0,
+                           (const T*)H.r1f, (const T*)H.wf, (const T*)H.bc, H.te);
+        bytes += gs_mf_color_bytes(Lk, col, sizeof(T));
+        ++launches;
+    }
+    if (prof) prof_end(c, bytes, launches);
+}
+
 // per-block partial sums of acol . z into SL_AUX; returns the block count
 template <typename T>
 static int acol_partials(Ctx& c, Level<T>& Lk) {
@@ -1191,6 +1428,30 @@ static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
         return;
     }
     const double d = c.sum_w;
+    if (top && H.mf) {
+        // finest level without a stored stencil: forward sweep, alpha update,
+        // residual with the partial sums of acol . z (one per workgroup of the
+        // residual kernel), restriction, coarse correction, prolongation, the
+        // element products b_e^T z_e of the corrected z, alpha, backward sweep
+        gs_sweep_mf(c, H, Lk, true);
+        alpha_update(c, Lk);
+        launch_fine_resid<T>(c, Lk, H.uf, H.r1f, H.wf, c.spart);
+        const int nbr = fine_resid_blocks(c);
+        Level<T>& Lc = H.lev[k - 1];
+        if (k - 1 <= H.ksmall || k - 1 == 0)
+            hipLaunchKernelGGL(k_restrict<T>, dim3(grid_of(Lc.nn)), dim3(kThreads), 0, c.s, Lk, Lc,
+                               (const T*)Lk.res, Lc.r, 1, (const double*)c.spart, nbr, d);
+        else
+            hipLaunchKernelGGL(k_restrict_init<T>, dim3(grid_of(Lc.nn)), dim3(kThreads), 0, c.s, Lk,
+                               Lc, (const T*)Lk.res, (const double*)c.spart, nbr, d);
+        vcycle_level(c, H, k - 1);
+        hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s, Lc, Lk,
+                           (const T*)Lc.z, Lk.z);
+        launch_fine_tdot<T>(c, Lk, H.uf, H.r1f, H.wf, H.te);
+        alpha_update(c, Lk);
+        gs_sweep_mf(c, H, Lk, false);
+        return;
+    }
     // forward sweep (colours 1..7) and the partial sums for its alpha update
     gs_sweep(c, Lk, true, top);
     const int gr = acol_partials(c, Lk);
@@ -1207,10 +1468,12 @@ static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
     Level<T>& Lc = H.lev[k - 1];
     if (k - 1 <= H.ksmall || k - 1 == 0)
         hipLaunchKernelGGL(k_restrict<T>, dim3(grid_of(Lc.nn)), dim3(kThreads), 0, c.s, Lk, Lc,
-                           (const T*)Lk.res, Lc.r, 1, (const double*)c.partials, grr, d);
+                           (const T*)Lk.res, Lc.r, 1,
+                           (const double*)c.partials + SL_STAT * kRedBlocks, grr, d);
     else
         hipLaunchKernelGGL(k_restrict_init<T>, dim3(grid_of(Lc.nn)), dim3(kThreads), 0, c.s, Lk,
-                           Lc, (const T*)Lk.res, (const double*)c.partials, grr, d);
+                           Lc, (const T*)Lk.res, (const double*)c.partials + SL_STAT * kRedBlocks,
+                           grr, d);
     vcycle_level(c, H, k - 1);
     hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s, Lc, Lk,
                        (const T*)Lc.z, Lk.z);
@@ -1227,6 +1490,9 @@ void mg_vcycle(Ctx& c, Hierarchy<T>& H, const double* r, double* z) {
     if (L - 1 <= H.ksmall || L == 1)
         hipLaunchKernelGGL((k_convert<double, T>), dim3(grid_of(nv)), dim3(kThreads), 0, c.s, r,
                            fine.r, nv);
+    else if (H.mf)
+        hipLaunchKernelGGL(k_top_init_mf<T>, dim3(grid_of(fine.nn)), dim3(kThreads), 0, c.s, fine,
+                           r, (const T*)H.bc, H.te);
     else
         hipLaunchKernelGGL(k_top_init<T>, dim3(grid_of(fine.nn)), dim3(kThreads), 0, c.s, fine,
                            r);

@@ -436,12 +436,20 @@ __device__ __forceinline__ void s_fetch_elem(SMarch<T>& M, const PlaneGeom& g, c
     ww = ok ? w[e] : T(0);
 }
 
-template <typename T, int S>
+// what a march over (x, u) produces
+enum SMode {
+    S_APPLY = 0,   // y = S [x; beta] (displacement part), partials of sum w (b.x - beta)
+    S_RESID = 1,   // y = r - S [x; beta], partials of acol . x = -sum w b.x
+    S_TDOT = 2     // te[e] = b_e . x_e for every element, nothing else
+};
+
+template <typename T, int S, int MODE>
 __device__ __forceinline__ void s_step(SMarch<T>& M, const PlaneGeom& g, const KhVals<T>& kh,
                                        const T* __restrict__ x, const T* __restrict__ u,
                                        const T* __restrict__ r1, const T* __restrict__ w,
                                        const uint8_t* __restrict__ nmask, T beta,
-                                       T* __restrict__ y, int l) {
+                                       const T* __restrict__ rr_in, T* __restrict__ y,
+                                       T* __restrict__ te, int l) {
     const int rel = l + 1 - (M.K0 - 1);
     plane_commit(M.ps, M.px[S], M.rx[rel % kRing], M.mring[rel % kRing]);
     plane_commit(M.ps, M.pu[S], M.ru[rel % kRing], M.mring[rel % kRing]);
@@ -452,16 +460,17 @@ __device__ __forceinline__ void s_step(SMarch<T>& M, const PlaneGeom& g, const K
     const T rr = M.r1pre[S], ww = M.wpre[S];
     s_fetch_elem(M, g, r1, w, l + 2, M.r1pre[S], M.wpre[S]);
     __syncthreads();
-    if (l - 1 >= M.K0 && M.owner) {
+    if (MODE != S_TDOT && l - 1 >= M.K0 && M.owner) {
         const T* pp = &M.part[(rel - 2) & 1][0][0];
         const int64_t n = (int64_t)(l - 1) * M.plane_nodes + (int64_t)M.ey * M.NX + M.ex;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const T v = M.pend[c] + pp[c * kTileThreads + (M.ty - 1) * TXE + M.tx];
+            T v = M.pend[c] + pp[c * kTileThreads + (M.ty - 1) * TXE + M.tx];
+            if (MODE == S_RESID) v = rr_in[3 * n + c] - v;
             y[3 * n + c] = ((M.omask >> c) & 1u) ? T(0) : v;
         }
     }
-    M.omask = M.mring[(rel - 1) % kRing][M.ty * NXL + M.tx];
+    if (MODE != S_TDOT) M.omask = M.mring[(rel - 1) % kRing][M.ty * NXL + M.tx];
     // bottom faces from the plane still in the ring (keeps registers low)
     T vx[24], vu[24], b[24];
     {
@@ -474,12 +483,16 @@ __device__ __forceinline__ void s_step(SMarch<T>& M, const PlaneGeom& g, const K
         modes_from_faces(Fb, Ft, vu);
     }
     kh_apply(kh, T(1), vu, b);
-    T t = T(0);
+    T traw = T(0);
 #pragma unroll
-    for (int q = 3; q < 24; ++q) t += b[q] * vx[q];
-    t -= beta;
-    const T wt = ww * t;                                  // 0 outside the grid
-    if (M.own_col && l >= M.K0) M.wsum += (double)wt;     // elements owned by this tile
+    for (int q = 3; q < 24; ++q) traw += b[q] * vx[q];
+    const bool own = M.own_col && l >= M.K0 && l < g.nz;  // elements owned by this tile
+    if (MODE == S_TDOT) {
+        if (own) te[M.ex + (int64_t)g.nx * (M.ey + (int64_t)g.ny * l)] = traw;
+        return;
+    }
+    const T wt = ww * (traw - beta);                      // 0 outside the grid
+    if (own) M.wsum += MODE == S_RESID ? -(double)(ww * traw) : (double)wt;
 #pragma unroll
     for (int q = 3; q < 24; ++q) vx[q] = rr * vx[q] + wt * vu[q];
     kh_apply(kh, T(1), vx, b);
@@ -503,12 +516,15 @@ __device__ __forceinline__ void s_step(SMarch<T>& M, const PlaneGeom& g, const K
     }
 }
 
-template <typename T>
+// The march over (x, u) for the S-apply (S_APPLY), the finest-level residual
+// of the V-cycle (S_RESID: x = z, beta = z_alpha, r_in = r) and the element
+// products b_e^T x_e (S_TDOT).  beta is x[ndof].
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kTileThreads)
-k_apply_S_plane(PlaneGeom g, KhVals<T> kh, const T* __restrict__ x, const T* __restrict__ u,
-                const T* __restrict__ r1, const T* __restrict__ w,
-                const uint8_t* __restrict__ nmask, int64_t ndof, T* __restrict__ y,
-                double* __restrict__ partials) {
+k_S_plane(PlaneGeom g, KhVals<T> kh, const T* __restrict__ x, const T* __restrict__ u,
+          const T* __restrict__ r1, const T* __restrict__ w, const uint8_t* __restrict__ nmask,
+          int64_t ndof, const T* __restrict__ r_in, T* __restrict__ y, T* __restrict__ te,
+          double* __restrict__ partials) {
     __shared__ T rx[kRing][kPV];
     __shared__ T ru[kRing][kPV];
     __shared__ uint8_t mring[kRing][kPN];
@@ -539,7 +555,7 @@ k_apply_S_plane(PlaneGeom g, KhVals<T> kh, const T* __restrict__ x, const T* __r
     M.part = part;
     M.omask = 0;
     M.wsum = 0.0;
-    const T beta = x[ndof];
+    const T beta = MODE == S_TDOT ? T(0) : x[ndof];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         M.pend[c] = T(0);
@@ -561,22 +577,24 @@ k_apply_S_plane(PlaneGeom g, KhVals<T> kh, const T* __restrict__ x, const T* __r
     __syncthreads();
     int l = M.K0 - 1;
     for (;;) {
-        s_step<T, 1>(M, g, kh, x, u, r1, w, nmask, beta, y, l);
+        s_step<T, 1, MODE>(M, g, kh, x, u, r1, w, nmask, beta, r_in, y, te, l);
         if (++l >= M.K1) break;
-        s_step<T, 0>(M, g, kh, x, u, r1, w, nmask, beta, y, l);
+        s_step<T, 0, MODE>(M, g, kh, x, u, r1, w, nmask, beta, r_in, y, te, l);
         if (++l >= M.K1) break;
     }
+    if (MODE == S_TDOT) return;
     __syncthreads();
     if (M.owner) {
         const T* pp = &M.part[(M.K1 - M.K0) & 1][0][0];
         const int64_t n = (int64_t)(M.K1 - 1) * M.plane_nodes + (int64_t)M.ey * M.NX + M.ex;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const T v = M.pend[c] + pp[c * kTileThreads + (M.ty - 1) * TXE + M.tx];
+            T v = M.pend[c] + pp[c * kTileThreads + (M.ty - 1) * TXE + M.tx];
+            if (MODE == S_RESID) v = r_in[3 * n + c] - v;
             y[3 * n + c] = ((M.omask >> c) & 1u) ? T(0) : v;
         }
     }
-    // block partial of sum w t (fixed order)
+    // block partial (fixed order)
     double ws = M.wsum;
     for (int off = 32; off > 0; off >>= 1) ws += __shfl_down(ws, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ws;
@@ -655,14 +673,50 @@ void launch_apply_S_tile_ws(Ctx& c, const double* x, double* y, double* partials
     const PlaneGeom g = plane_geom(c, choose_zblocks(c));
     const KhVals<double> kh{c.kh8[0], c.kh8[1], c.kh8[2], c.kh8[3],
                             c.kh8[4], c.kh8[5], c.kh8[6], c.kh8[7]};
-    hipLaunchKernelGGL(k_apply_S_plane<double>, dim3(8 * g.per_xcd), dim3(kTileThreads), 0, c.s,
-                       g, kh, x, c.u, c.r1, c.w, c.nmask, c.ndof, y, partials);
+    hipLaunchKernelGGL((k_S_plane<double, S_APPLY>), dim3(8 * g.per_xcd), dim3(kTileThreads), 0,
+                       c.s, g, kh, x, c.u, c.r1, c.w, c.nmask, c.ndof, (const double*)nullptr, y,
+                       (double*)nullptr, partials);
     hipLaunchKernelGGL(k_sum_neg, dim3(1), dim3(256), 0, c.s, partials, g.nblocks, y + c.ndof);
 }
 
 void launch_apply_S_tile(Ctx& c, const double* x, double* y) {
     launch_apply_S_tile_ws(c, x, y, c.spart);
 }
+
+// finest level of the V-cycle, matrix-free (precision T): res = r - S [z; z_a]
+// with partial sums of acol . z (one per workgroup) into parts, and the
+// element products te = b_e^T z_e
+template <typename T>
+void launch_fine_resid(Ctx& c, const Level<T>& L, const T* u, const T* r1, const T* w,
+                       double* parts) {
+    const PlaneGeom g = plane_geom(c, choose_zblocks(c));
+    const KhVals<T> kh{(T)c.kh8[0], (T)c.kh8[1], (T)c.kh8[2], (T)c.kh8[3],
+                       (T)c.kh8[4], (T)c.kh8[5], (T)c.kh8[6], (T)c.kh8[7]};
+    hipLaunchKernelGGL((k_S_plane<T, S_RESID>), dim3(8 * g.per_xcd), dim3(kTileThreads), 0, c.s,
+                       g, kh, (const T*)L.z, u, r1, w, c.nmask, 3 * L.nn, (const T*)L.r, L.res,
+                       (T*)nullptr, parts);
+}
+
+template <typename T>
+void launch_fine_tdot(Ctx& c, const Level<T>& L, const T* u, const T* r1, const T* w, T* te) {
+    const PlaneGeom g = plane_geom(c, choose_zblocks(c));
+    const KhVals<T> kh{(T)c.kh8[0], (T)c.kh8[1], (T)c.kh8[2], (T)c.kh8[3],
+                       (T)c.kh8[4], (T)c.kh8[5], (T)c.kh8[6], (T)c.kh8[7]};
+    hipLaunchKernelGGL((k_S_plane<T, S_TDOT>), dim3(8 * g.per_xcd), dim3(kTileThreads), 0, c.s,
+                       g, kh, (const T*)L.z, u, r1, w, c.nmask, 3 * L.nn, (const T*)nullptr,
+                       (T*)nullptr, te, (double*)nullptr);
+}
+
+int fine_resid_blocks(const Ctx& c) { return plane_geom(c, choose_zblocks(c)).nblocks; }
+
+template void launch_fine_resid<float>(Ctx&, const Level<float>&, const float*, const float*,
+                                       const float*, double*);
+template void launch_fine_resid<double>(Ctx&, const Level<double>&, const double*,
+                                        const double*, const double*, double*);
+template void launch_fine_tdot<float>(Ctx&, const Level<float>&, const float*, const float*,
+                                      const float*, float*);
+template void launch_fine_tdot<double>(Ctx&, const Level<double>&, const double*, const double*,
+                                       const double*, double*);
 
 // ---------------------------------------------------------------------------
 // Workspace of the allocation-free S-apply: the per-workgroup partial sums of

@@ -49,6 +49,14 @@ struct Hierarchy {
     int* cinv = nullptr;         // dense index -> DOF of level 0 (nc-1 entries)
     int* flag = nullptr;         // device: 1 if the factorization met a non-positive pivot
     int ksmall = -1;             // levels 0..ksmall run in one workgroup (-1: none)
+    // finest level without a stored stencil (when it is not one of the small
+    // levels): the Gauss-Seidel rows are formed from the element data
+    bool mf = false;
+    T* bc = nullptr;             // 24 per node (colour-major): b_e rows at the node, per element
+    T* te = nullptr;             // m: b_e^T z_e of the current z
+    T* r1f = nullptr;            // m: rho' in T (aliases Ctx::r1 when T is double)
+    T* wf = nullptr;             // m: w in T (aliases Ctx::w when T is double)
+    T* uf = nullptr;             // 3 nn: u in T (aliases Ctx::u when T is double)
 };
 
 constexpr int kSmallNodes = 512;    // largest level handled by the one-workgroup V-cycle
@@ -70,6 +78,7 @@ struct Ctx {
     float* Kef = nullptr;        // 576
     double* Mc = nullptr;        // 8 x 576: Q_c^T K_e Q_c
     double* Qc = nullptr;        // 8 x 8 x 8: Q_c[a][A] nodal interpolation weights
+    double ke_host[576] = {};    // K_e on the host (rows of corner 0 feed the smoother)
     double kh8[8] = {};          // the 8 coefficients of H K_e H / 64 (sum/difference basis)
     bool kh_ok = false;          // K_e has the cube's structure in that basis
     double* spart = nullptr;     // per-workgroup partial sums of the tiled S-apply
@@ -194,6 +203,15 @@ inline double gs_color_bytes(const Level<T>& L, int col, size_t ts) {
     return cnt * (kStencilVals + 9 + 12) * ts + ((double)L.nn - cnt) * 3 * ts;
 }
 
+// compulsory bytes of one colour pass on the finest level without a stored
+// stencil: per node of the colour r, acol, dinv, its 24 b values and z written;
+// per element rho', w and b^T z read and written; z of every node read
+template <typename T>
+inline double gs_mf_color_bytes(const Level<T>& L, int col, size_t ts) {
+    const double cnt = (double)(L.coff[col + 1] - L.coff[col]);
+    return (cnt * (3 + 3 + 9 + 24 + 3) + (double)L.m * 4 + (double)L.nn * 3) * ts;
+}
+
 // host-side finite-element tables (host_fe.cpp)
 void element_stiffness(double E, double nu, double h, double* Ke576);
 void child_interp(double* Q512);                       // Q[c][a][A]
@@ -245,6 +263,14 @@ void launch_apply_K_tile_f32(Ctx& c, const float* rho, const float* x, float* y)
 void launch_apply_S_tile(Ctx& c, const double* x, double* y);
 // the same with the per-workgroup partial sums in `partials`
 void launch_apply_S_tile_ws(Ctx& c, const double* x, double* y, double* partials);
+// matrix-free finest level of the V-cycle (operator.hip): residual with
+// per-workgroup partials of acol . z, and the element products b_e^T z_e
+template <typename T>
+void launch_fine_resid(Ctx& c, const Level<T>& L, const T* u, const T* r1, const T* w,
+                       double* parts);
+template <typename T>
+void launch_fine_tdot(Ctx& c, const Level<T>& L, const T* u, const T* r1, const T* w, T* te);
+int fine_resid_blocks(const Ctx& c);
 // allocation-free S-apply: the device address of the file-scope workspace of
 // kScratchPartials doubles (looked up once per device)
 constexpr int kScratchPartials = 1 << 16;
