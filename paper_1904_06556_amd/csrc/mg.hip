@@ -701,20 +701,26 @@ k_restrict_init(Level<T> F, Level<T> C, const T* __restrict__ rf,
 }
 
 // ---------------------------------------------------------------------------
-// finest level without a stored stencil: one Gauss-Seidel colour pass, one
-// thread per node of the colour.  The node's row of S z is formed from its 8
-// elements: rho'_e (K_e z_e)_a + w_e b_{e,a} (b_e^T z_e), with b_e^T z_e = te
-// kept current by the passes themselves (after the update of the node, each
-// of its elements gets te += b_{e,a} . dz; every element has exactly one
-// node of each colour, so each te has one writer per pass).  K_e's rows are
-// the same for every thread of the launch (a = element offset o).
+// finest level without a stored stencil: one Gauss-Seidel colour pass, eight
+// lanes per node of the colour, lane o for the element at offset o (bit set =
+// element on the low side; the node is that element's corner a = o).  Lane o
+// forms its element's share of the node's row of S z,
+// rho'_e (K_e z_e)_a + w_e b_{e,a} (b_e^T z_e), with b_e^T z_e = te kept
+// current by the passes themselves; the eight shares meet in a butterfly
+// over the lane group (the same tree, hence the same sum, in every lane).
+// After the node's update each lane adds b_{e,a} . dz to its element's te;
+// every element has exactly one node of each colour, so each te has one
+// writer per pass.
 // ---------------------------------------------------------------------------
-constexpr int kMfBlock = 64;   // one wave per workgroup: many workgroups at every grid size
+constexpr int kMfBlock = 256;   // 32 nodes of 8 lanes
 
 // The rows of K_e at corner a follow from those at corner 0 by the cube's
 // reflections: K_e[3a+r][3b+c] = s_r(a) s_c(a) K0[a^b][r][c], s_r(a) = -1 if
 // bit r of a is set (reflecting axis r maps corner a to a ^ 2^r and flips the
 // r components).  K0[d][r][c] = K_e[r][3d+c]: 72 numbers for all corners.
+// With d = a ^ b the block K0[d] is the same for every lane, and node b of
+// the element sits at offset d_x (1 - 2 a_x) (and likewise in y, z) from the
+// node itself.
 template <typename T>
 struct KeRows0 {
     T v[8 * 9];
@@ -724,90 +730,87 @@ template <typename T>
 __global__ void __launch_bounds__(kMfBlock)
 k_gs_mf(Level<T> L, int col, KeRows0<T> K0, const T* __restrict__ r1, const T* __restrict__ w,
         const T* __restrict__ bc, T* __restrict__ te) {
-    const int64_t tl = gidx();
-    const int64_t cnt = L.coff[col + 1] - L.coff[col];
-    if (tl >= cnt) return;
+    const int64_t g = gidx();
+    const uint32_t tl = (uint32_t)(g >> 3);
+    const int o = (int)(g & 7);
+    const uint32_t cnt = (uint32_t)(L.coff[col + 1] - L.coff[col]);
+    if (tl >= cnt) return;   // whole lane groups leave together
     const int64_t tcm = L.coff[col] + tl;
-    int64_t q = tl;
-    const int i = 2 * (int)(q % L.cnx[col]) + (col & 1);
-    q /= L.cnx[col];
-    const int j = 2 * (int)(q % L.cny[col]) + ((col >> 1) & 1);
-    const int k = 2 * (int)(q / L.cny[col]) + (col >> 2);
+    const uint32_t cnx = (uint32_t)L.cnx[col], cny = (uint32_t)L.cny[col];
+    const uint32_t q1 = tl / cnx, q2 = q1 / cny;
+    const int i = 2 * (int)(tl - q1 * cnx) + (col & 1);
+    const int j = 2 * (int)(q1 - q2 * cny) + ((col >> 1) & 1);
+    const int k = 2 * (int)q2 + (col >> 2);
     const int64_t n = nat(i, j, k, L.NX, L.NY);
+    const int ax = o & 1, ay = (o >> 1) & 1, az = o >> 2;
+    const int ii = i - ax, jj = j - ay, kk = k - az;
+    const bool in = ii >= 0 && ii < L.nx && jj >= 0 && jj < L.ny && kk >= 0 && kk < L.nz;
+    const int64_t e = in ? ii + (int64_t)L.nx * (jj + (int64_t)L.ny * kk) : 0;
+    const T* __restrict__ bb = bc + tcm * 24 + 3 * o;
+    const T bb0 = bb[0], bb1 = bb[1], bb2 = bb[2];
+    const T rr = in ? r1[e] : T(0);
+    const T tv = in ? te[e] : T(0);
+    const T wt = in ? w[e] * tv : T(0);
     T* __restrict__ z = L.z;
-    const T za = z[3 * L.nn];
-    T b0 = L.r[3 * n] - L.acol[3 * n] * za;
-    T b1 = L.r[3 * n + 1] - L.acol[3 * n + 1] * za;
-    T b2 = L.r[3 * n + 2] - L.acol[3 * n + 2] * za;
-    // the 8 elements around the node (offset o: bit set = element on the low side;
-    // the node is the element's corner a = o): rho', and the rank-one terms
-    T rr[8], tv[8];
-    int64_t ei[8];
+    // K0[d] z_b summed over the element's nodes, per (row, column) pair
+    T A[9];
 #pragma unroll
-    for (int o = 0; o < 8; ++o) {
-        const int ii = i - (o & 1), jj = j - ((o >> 1) & 1), kk = k - (o >> 2);
-        const bool in = ii >= 0 && ii < L.nx && jj >= 0 && jj < L.ny && kk >= 0 && kk < L.nz;
-        const int64_t e = in ? ii + (int64_t)L.nx * (jj + (int64_t)L.ny * kk) : -1;
-        ei[o] = e;
-        rr[o] = in ? r1[e] : T(0);
-        tv[o] = in ? te[e] : T(0);
-        const T wt = (in ? w[e] : T(0)) * tv[o];
-        const T* bb = bc + tcm * 24 + 3 * o;
-        b0 -= wt * bb[0];
-        b1 -= wt * bb[1];
-        b2 -= wt * bb[2];
-    }
-    // K(rho') z at the node, neighbour by neighbour: neighbour at offset
-    // (dx, dy, dz) is node bn = a ^ d of element o when it lies in that element
+    for (int q = 0; q < 9; ++q) A[q] = T(0);
     T zc0 = 0, zc1 = 0, zc2 = 0;
+    if (in) {
+        const int64_t sy = L.NX, sz = (int64_t)L.NX * L.NY;
+        const int64_t ox = 1 - 2 * ax, oy = sy * (1 - 2 * ay), oz = sz * (1 - 2 * az);
 #pragma unroll
-    for (int s = 0; s < 27; ++s) {
-        const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
-        const int ii = i + dx, jj = j + dy, kk = k + dz;
-        const bool in = ii >= 0 && ii < L.NX && jj >= 0 && jj < L.NY && kk >= 0 && kk < L.NZ;
-        const int64_t mm = in ? nat(ii, jj, kk, L.NX, L.NY) : n;
-        const T x0 = in ? z[3 * mm] : T(0), x1 = in ? z[3 * mm + 1] : T(0),
-                x2 = in ? z[3 * mm + 2] : T(0);
-        if (s == 13) {
-            zc0 = x0;
-            zc1 = x1;
-            zc2 = x2;
-        }
+        for (int d = 0; d < 8; ++d) {
+            const int64_t mm = n + ((d & 1) ? ox : 0) + ((d & 2) ? oy : 0) + ((d & 4) ? oz : 0);
+            const T x0 = z[3 * mm], x1 = z[3 * mm + 1], x2 = z[3 * mm + 2];
+            if (d == 0) {
+                zc0 = x0;
+                zc1 = x1;
+                zc2 = x2;
+            }
 #pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            // element o spans offsets -(o bit) .. 1 - (o bit) along each axis
-            const int lx = -(o & 1), ly = -((o >> 1) & 1), lz = -(o >> 2);
-            if (dx < lx || dx > lx + 1 || dy < ly || dy > ly + 1 || dz < lz || dz > lz + 1)
-                continue;
-            const int bn = (dx - lx) | ((dy - ly) << 1) | ((dz - lz) << 2);
-            const int dd = o ^ bn;
-            // s_c(a) rho'_e z_c, then s_r(a) sum_c K0[d][r][c] (.)
-            const T p0 = ((o & 1) ? -rr[o] : rr[o]) * x0;
-            const T p1 = ((o & 2) ? -rr[o] : rr[o]) * x1;
-            const T p2 = ((o & 4) ? -rr[o] : rr[o]) * x2;
-            const T y0 = K0.v[dd * 9 + 0] * p0 + K0.v[dd * 9 + 1] * p1 + K0.v[dd * 9 + 2] * p2;
-            const T y1 = K0.v[dd * 9 + 3] * p0 + K0.v[dd * 9 + 4] * p1 + K0.v[dd * 9 + 5] * p2;
-            const T y2 = K0.v[dd * 9 + 6] * p0 + K0.v[dd * 9 + 7] * p1 + K0.v[dd * 9 + 8] * p2;
-            if (o & 1) b0 += y0; else b0 -= y0;
-            if (o & 2) b1 += y1; else b1 -= y1;
-            if (o & 4) b2 += y2; else b2 -= y2;
+            for (int r = 0; r < 3; ++r) {
+                A[3 * r] += K0.v[d * 9 + 3 * r] * x0;
+                A[3 * r + 1] += K0.v[d * 9 + 3 * r + 1] * x1;
+                A[3 * r + 2] += K0.v[d * 9 + 3 * r + 2] * x2;
+            }
         }
+    } else {
+        zc0 = z[3 * n];
+        zc1 = z[3 * n + 1];
+        zc2 = z[3 * n + 2];
     }
+    // this element's share of -(S z)_a: -rho' s_r(a) sum_c s_c(a) A[r][c] - w t b_a
+    const T sx = ax ? T(-1) : T(1), sy_ = ay ? T(-1) : T(1), sz_ = az ? T(-1) : T(1);
+    const T y0 = sx * A[0] + sy_ * A[1] + sz_ * A[2];
+    const T y1 = sx * A[3] + sy_ * A[4] + sz_ * A[5];
+    const T y2 = sx * A[6] + sy_ * A[7] + sz_ * A[8];
+    T p0 = -(rr * sx) * y0 - wt * bb0;
+    T p1 = -(rr * sy_) * y1 - wt * bb1;
+    T p2 = -(rr * sz_) * y2 - wt * bb2;
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+        p0 += __shfl_xor(p0, off, 8);
+        p1 += __shfl_xor(p1, off, 8);
+        p2 += __shfl_xor(p2, off, 8);
+    }
+    const T za = z[3 * L.nn];
+    const T b0 = (L.r[3 * n] - L.acol[3 * n] * za) + p0;
+    const T b1 = (L.r[3 * n + 1] - L.acol[3 * n + 1] * za) + p1;
+    const T b2 = (L.r[3 * n + 2] - L.acol[3 * n + 2] * za) + p2;
     T D[9];
 #pragma unroll
     for (int q9 = 0; q9 < 9; ++q9) D[q9] = L.dinv[(int64_t)q9 * L.nn + tcm];
     const T d0 = D[0] * b0 + D[1] * b1 + D[2] * b2;
     const T d1 = D[3] * b0 + D[4] * b1 + D[5] * b2;
     const T d2 = D[6] * b0 + D[7] * b1 + D[8] * b2;
-    z[3 * n] = zc0 + d0;
-    z[3 * n + 1] = zc1 + d1;
-    z[3 * n + 2] = zc2 + d2;
-#pragma unroll
-    for (int o = 0; o < 8; ++o) {
-        if (ei[o] < 0) continue;
-        const T* bb = bc + tcm * 24 + 3 * o;
-        te[ei[o]] = tv[o] + (bb[0] * d0 + bb[1] * d1 + bb[2] * d2);
+    if (o == 0) {
+        z[3 * n] = zc0 + d0;
+        z[3 * n + 1] = zc1 + d1;
+        z[3 * n + 2] = zc2 + d2;
     }
+    if (in) te[e] = tv + (bb0 * d0 + bb1 * d1 + bb2 * d2);
 }
 
 // finest level without a stored stencil: r (FP64 S-vector) into T, the first
@@ -1379,7 +1382,7 @@ static void gs_sweep_mf(Ctx& c, Hierarchy<T>& H, Level<T>& Lk, bool forward) {
         const int col = forward ? q : 7 - q;
         const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
         if (cnt == 0) continue;
-        hipLaunchKernelGGL(k_gs_mf<T>, dim3((unsigned)((cnt + kMfBlock - 1) / kMfBlock)),
+        hipLaunchKernelGGL(k_gs_mf<T>, dim3((unsigned)((8 * cnt + kMfBlock - 1) / kMfBlock)),
                            dim3(kMfBlock), 0, c.s, Lk, col, K0,
                            (const T*)H.r1f, (const T*)H.wf, (const T*)H.bc, H.te);
         bytes += gs_mf_color_bytes(Lk, col, sizeof(T));
