@@ -116,12 +116,9 @@ def kernel_roofline(torch, ctx, pr, reps=200):
     return bytes_per, res
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pmc_cant-64x32x32_fp64.md")
-
-
 def kernel_source_hash():
     """Hash of the multigrid kernels' source and of the level structure they
-    read (the counters stay valid while both are unchanged)."""
+    read (their counters stay valid while both are unchanged)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1904_06556_amd", "csrc")
     h = hashlib.sha256()
@@ -134,21 +131,38 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_name):
-    """HBM bytes per launch of the finest-level Gauss-Seidel pass from the
-    committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary (scaled by the copy
-    reference); None if it covers another workload or the kernel sources
+def operator_source_hash():
+    """Hash of the operator kernels' source (K(rho)u and the S-apply; their
+    counters stay valid while it is unchanged)."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1904_06556_amd", "csrc", "operator.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_file(workload_name):
+    return os.path.join(ROOT, "profiles", f"traffic_pmc_{workload_name}.md")
+
+
+def measured_traffic(workload_name, kernel):
+    """HBM bytes per launch of `kernel` on `workload_name` from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (each counter scaled by what it
+    reads for a plain copy); None if there is none or if the kernel's source
     changed since the counters were taken."""
-    if workload_name != "cant-64x32x32" or not os.path.exists(TRAFFIC_FILE):
+    path = traffic_file(workload_name)
+    if not os.path.exists(path):
         return None
-    val, src = None, None
-    with open(TRAFFIC_FILE) as fh:
+    val, hashes = None, {}
+    with open(path) as fh:
         for line in fh:
-            if line.startswith("traffic_bytes_per_launch k_gs_color9<double, true>"):
+            if line.startswith(f"traffic_bytes_per_launch {kernel} ="):
                 val = float(line.split("=")[1])
-            elif line.startswith("kernel_source_sha256_16"):
-                src = line.split("=")[1].strip()
-    return val if (val is not None and src == kernel_source_hash()) else None
+            elif "_source_sha256_16 =" in line:
+                k, v = line.split("=")
+                hashes[k.strip()] = v.strip()
+    key, now = (("operator_source_sha256_16", operator_source_hash())
+                if kernel.startswith(("k_apply_K", "k_S_plane"))
+                else ("kernel_source_sha256_16", kernel_source_hash()))
+    return val if (val is not None and hashes.get(key) == now) else None
 
 
 def profiled(ctx, kernel_class, run):
@@ -244,6 +258,7 @@ def kernels_only(a, torch, W, V):
     print(json.dumps({"mode": "kernels", "workload": pr.name, "reps": a.reps,
                       "k_sets": nsets, "k_launches": a.reps * nsets, "k_bytes": k_bytes,
                       "operator_source_sha256_16": operator_source_hash(),
+                      "kernel_source_sha256_16": kernel_source_hash(),
                       "n_dof": ctx.n_dof, "m": ctx.m,
                       "copy_bytes_read": copy_bytes, "copy_bytes_written": copy_bytes}),
           flush=True)
@@ -719,6 +734,7 @@ def solve_run(a, torch, W, V):
     mr_rate, mr_its = minres_rate(torch, ctx)
     bytes_per, kr = kernel_roofline(torch, ctx, pr)
     rot = kr["rotating"]
+    gs_kernel = "k_gs_mf<double>" if prec == V.VTS_FP64 else "k_gs_mf<float>"
     line = {
         "metric": METRIC,
         "value": 1e3 / ms_per_step,
@@ -738,12 +754,11 @@ def solve_run(a, torch, W, V):
         "outer": last["outer"], "newton": last["newton"], "minres": last["minres"],
         "k_apply_gdofs": rot["gdofs"], "k_apply_gdofs_hot_cache": kr["hot"]["gdofs"],
         "minres_mg_iters_per_s": mr_rate,
-        "roofline": {"kernel": "k_gs_color9<double, true> (finest-level multicolour "
-                               "block Gauss-Seidel pass)",
+        "roofline": {"kernel": f"{gs_kernel} (finest-level multicolour block "
+                               "Gauss-Seidel pass, matrix-free)",
                      "bound": "hbm", "achieved": gs["gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": gs["gbs"] / HBM_PEAK_GBS,
-                     "traffic": (measured_traffic(pr.name)
-                                 if prec == V.VTS_FP64 else None),
+                     "traffic": measured_traffic(pr.name, gs_kernel),
                      "bytes_per_launch": gs["bytes_per_launch"],
                      "avg_launch_ms": gs["avg_launch_ms"], "launches": gs["launches"]},
         "kernels": {
@@ -764,33 +779,6 @@ def solve_run(a, torch, W, V):
 
 HEADLINE_WORKLOAD = 3      # cantilever 192x96x96, three point loads, mixed precision
 K_SET_BYTES = 1.0e9        # rotating K(rho)u sets: more than the 256 MB Infinity Cache
-TRAFFIC_K_FILE = os.path.join(ROOT, "profiles", "traffic_pmc_k_apply_cant3pt-192x96x96.md")
-
-
-def operator_source_hash():
-    """Hash of the operator kernels' source (the K(rho)u counters stay valid
-    while it is unchanged)."""
-    import hashlib
-    with open(os.path.join(ROOT, "paper_1904_06556_amd", "csrc", "operator.hip"), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
-
-
-def measured_k_traffic():
-    """HBM bytes per K(rho)u launch at 192x96x96 from the committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (copy-scaled); None if the
-    operator source changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_K_FILE):
-        return None
-    val, src = None, None
-    with open(TRAFFIC_K_FILE) as fh:
-        for line in fh:
-            if line.startswith("traffic_bytes_per_launch k_apply_K_plane<double>"):
-                val = float(line.split("=")[1])
-            elif line.startswith("operator_source_sha256_16"):
-                src = line.split("=")[1].strip()
-    return val if (val is not None and src == operator_source_hash()) else None
-
-
 def cpu_baseline_k_apply(pr, budget_s):
     """The FP64 oracle's K(rho)u (element gather, dense 24x24 element
     products, scatter by bincount) on the same grid, repeated for about
@@ -848,9 +836,18 @@ def headline(a, torch, W, V):
         ys.append(torch.empty(nd, dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
 
+    # K(rho)u is timed by HIP events recorded on the stream both contexts
+    # launch on, around each step's back-to-back launches
+    k_events = []
+
     def k_batch():
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         for i in range(nsets):
             ctxk.apply_K_rho(rhos[i], xs[i], ys[i])
+        e1.record(stream)
+        k_events.append((e0, e1))
 
     def step():
         st = ctx.pbm_iterate()
@@ -862,14 +859,15 @@ def headline(a, torch, W, V):
         print(f"warmup {w}: outer iteration newton {st['newton_its']} minres "
               f"{st['minres_its']} ratio {st['ratio']:.2e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    ctxk.profile_start("apply_K")
+    k_events.clear()
     stats = []
     t0 = time.perf_counter()
     for _ in range(a.steps):
         stats.append(step())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kp = ctxk.profile_stop()
+    kp = {"launches": nsets * len(k_events),
+          "total_ms": sum(e0.elapsed_time(e1) for e0, e1 in k_events)}
     wall = t1 - t0
     k_ms = kp["total_ms"] / max(kp["launches"], 1)
     k_gdofs = nd / (k_ms * 1e-3) / 1e9
@@ -950,7 +948,8 @@ def headline(a, torch, W, V):
                    "parallelism": "1 GPU"},
         "roofline": {"kernel": "k_apply_K_plane<double> (K(rho)x, FP64)",
                      "bound": "hbm", "achieved": k_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": k_gbs / HBM_PEAK_GBS, "traffic": measured_k_traffic(),
+                     "frac": k_gbs / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(pr.name, "k_apply_K_plane<double>"),
                      "bytes_per_launch": k_bytes, "avg_launch_ms": k_ms,
                      "launches": kp["launches"]},
         "hot_path": {"outer_iterations_per_s": a.steps / wall,
@@ -960,12 +959,16 @@ def headline(a, torch, W, V):
                      "minres_mg_fixed_point_iters_per_s": {"mixed": mr_mixed, "fp64": mr_fp64,
                                                            "iterations": mr_its}},
         "kernels": {
-            "gs_fine": {"avg_launch_ms": gs["avg_launch_ms"], "gbs": gs["gbs"],
+            "gs_fine": {"kernel": "k_gs_mf<float>",
+                        "avg_launch_ms": gs["avg_launch_ms"], "gbs": gs["gbs"],
                         "bytes_per_launch": gs["bytes_per_launch"],
+                        "traffic": measured_traffic(pr.name, "k_gs_mf<float>"),
                         "launches_per_outer_iteration": gs["launches"],
                         "precision": "fp32"},
-            "apply_S": {"avg_launch_ms": sa["avg_launch_ms"], "gbs": sa["gbs"],
+            "apply_S": {"kernel": "k_S_plane<double, 0>",
+                        "avg_launch_ms": sa["avg_launch_ms"], "gbs": sa["gbs"],
                         "bytes_per_launch": sa["bytes_per_launch"],
+                        "traffic": measured_traffic(pr.name, "k_S_plane<double, 0>"),
                         "launches_per_outer_iteration": sa["launches"]}},
         "time_to_kkt_cant-64x32x32": ttk,
         "mixed_over_fp64_time_to_kkt": ttk["mixed"]["seconds"] / ttk["fp64"]["seconds"],
