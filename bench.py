@@ -76,6 +76,14 @@ def parse():
                     help="time-to-KKT of the benchmark cantilever family at refinement levels "
                          "--levels (n up to 12.8 M DOFs); one JSON line")
     ap.add_argument("--levels", type=int, nargs="+", default=[5, 6, 7])
+    ap.add_argument("--families", type=int, nargs="+", default=[2, 4, 6, 8],
+                    help="m_x of the CANT/BRIDGE-m_x-2-2-l problems (--paper)")
+    ap.add_argument("--cap-seconds", type=float, default=600.0,
+                    help="wall-time cap of one solve (--paper)")
+    ap.add_argument("--paper-only", action="store_true",
+                    help="--paper: only the paper's parameters, not the library's")
+    ap.add_argument("--library-rho-lo", type=float, default=1e-3,
+                    help="--paper: lower bound of rho for the library-option solve")
     ap.add_argument("--scale-kernels", action="store_true",
                     help="the dominant kernels (finest Gauss-Seidel pass, K(rho)x, S-apply) "
                          "timed at each of --levels, FP64 and mixed; one JSON line")
@@ -266,21 +274,24 @@ def kernels_only(a, torch, W, V):
     return 0
 
 
-# PBM iterations / Newton steps / MINRES iterations printed in Tables 3 and 4
-# (Section 7.2) for these problems, with the paper's parameters
-PAPER_COUNTS = {"CANT-4-2-2-5": (15, 57, 153), "CANT-4-2-2-6": (17, 59, 118),
-                "BRIDGE-4-2-2-5": (14, 45, 155), "BRIDGE-4-2-2-6": (15, 57, 317)}
+def paper_names(a):
+    """CANT-mx-2-2-l and BRIDGE-mx-2-2-l for the selected mx and l (Tables 3, 4)."""
+    return [f"{kind}-{mx}-2-2-{l}" for kind in ("CANT", "BRIDGE") for l in a.levels
+            for mx in a.families]
 
 
-# Tables 3 and 4, IP columns (IP iterations, MINRES), rho_lo = 1e-3
-PAPER_IP_COUNTS = {"CANT-4-2-2-5": (28, 570), "CANT-4-2-2-6": (42, 2465),
-                   "BRIDGE-4-2-2-5": (25, 590), "BRIDGE-4-2-2-6": (50, 2965)}
+def paper_problem(W, name):
+    kind, mx, my, mz, l = name.split("-")
+    gen = W.paper_cantilever if kind == "CANT" else W.paper_bridge
+    return gen(int(mx), int(my), int(mz), int(l))
 
 
 def paper_problems_ip(a, torch, W, V):
     """The interior point method with the paper's parameters (Algorithm 3:
     eps_IP = 1e-5, sigma = 0.2, r = s = 1e-2 initially; rho_lo = 1e-3 as in
-    Section 7 for IP) on the CANT and BRIDGE 4-2-2-l problems, FP64."""
+    Section 7 for IP) on the selected CANT and BRIDGE problems, FP64."""
+    from workloads import paper_tables as T
+
     def run(pr, name, eps_mr0):
         ctx = V.Context.from_problem(pr, precision=V.VTS_FP64)
         torch.cuda.synchronize()
@@ -301,19 +312,21 @@ def paper_problems_ip(a, torch, W, V):
             if s["converged"]:
                 status = V.VTS_OK
                 break
+            if time.perf_counter() - t0 > a.cap_seconds:
+                status = "time cap"
+                break
         torch.cuda.synchronize()
-        res = dict(seconds=time.perf_counter() - t0, status=int(status), iterations=its,
-                   minres=mr, compliance=s.get("compliance"), eps_mr0=eps_mr0)
+        res = dict(seconds=time.perf_counter() - t0,
+                   status=status if isinstance(status, str) else int(status),
+                   iterations=its, minres=mr, compliance=s.get("compliance"), eps_mr0=eps_mr0)
         ctx.close()
         return res
 
     out = {}
-    for name in PAPER_IP_COUNTS:
-        kind, mx, my, mz, l = name.split("-")
-        gen = W.paper_cantilever if kind == "CANT" else W.paper_bridge
-        pr = gen(int(mx), int(my), int(mz), int(l))
+    for name in paper_names(a):
+        pr = paper_problem(W, name)
         pr.rho_lo = 1e-3
-        res = dict(m=pr.m, n=pr.n, paper_ip_mr=PAPER_IP_COUNTS[name])
+        res = dict(m=pr.m, n=pr.n, paper_ip_its_mr=T.entry(name)["ip"])
         res["paper_eps_mr0"] = run(pr, name, 1e-2)
         if res["paper_eps_mr0"]["status"] != V.VTS_OK:
             # the paper's start value leaves the first directions too inexact
@@ -331,49 +344,98 @@ def paper_problems_ip(a, torch, W, V):
     return 0
 
 
+def paper_options(V, name, n):
+    """PBM with the parameter values stated after Algorithm 1 and in Section 7
+    (eps_PBM = 1e-5, eps_NWT_min = 1e-3, final eps_NWT = 10 eps_PBM, absolute
+    floors p_min = q_min = 1e-8, eps_MR0 = 1e-4 sqrt(n), no KKT test, u the
+    last Newton iterate) and the footnote overrides of Tables 3 and 4."""
+    from workloads import paper_tables as T
+    o = dict(eps_pbm=1e-5, eps_nwt_min=1e-3, eps_nwt_final=1e-4, final_res4=0, eps_stat=0.0,
+             accept_stall=0.0, p_min=1e-8, q_min=1e-8, p_min_relative=0, eps_mr0=0.0,
+             max_outer=100, kkt_tol=0.0, eps_state=0.0)
+    o.update(T.paper_overrides(name, n))
+    return V.default_options(**o), T.paper_overrides(name, n)
+
+
+def run_pbm_capped(torch, V, ctx, name, label, cap_s, max_outer):
+    """Outer PBM iterations one call at a time (progress on stderr), then the
+    final Newton call, rho update and KKT evaluation of vts_pbm_solve; stops
+    early at cap_s seconds."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, s = V.VTS_OK, {}
+    for k in range(max_outer):
+        try:
+            s = ctx.pbm_iterate()
+        except V.VtsError as e:
+            status = e.status
+            break
+        print(f"{name} [{label}]: outer {k + 1} ratio {s['ratio']:.2e} newton "
+              f"{s['newton_its']} minres {s['minres_its']} t {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+        if s["converged"]:
+            break
+        if time.perf_counter() - t0 > cap_s:
+            status = "time cap"
+            break
+    r = ctx.pbm_solve(check=False) if status == V.VTS_OK else None
+    torch.cuda.synchronize()
+    res = dict(seconds=time.perf_counter() - t0,
+               status=status if isinstance(status, str) else int(r["status"] if r else status),
+               last_gap_ratio=s.get("ratio"))
+    if r:
+        res.update({k: r[k] for k in ("outer", "newton", "minres", "compliance", "res_pbm",
+                                      "kkt", "r_eq", "r_vol", "r_box", "r_stat")})
+    else:
+        st = ctx.state_dict()
+        res.update(outer=int(st["outer"]), newton=int(st["newton"]), minres=int(st["minres"]))
+    return res
+
+
 def paper_problems(a, torch, W, V):
-    """PBM with the parameter values stated after Algorithm 1 and in Section
-    7 (eps_PBM = 1e-5, eps_NWT_min = 1e-3, final eps_NWT = 10 eps_PBM,
-    absolute floors p_min = q_min = 1e-8, eps_MR0 = 1e-4 sqrt(n), rho_lo = 0)
-    on the CANT and BRIDGE 4-2-2-l problems, FP64."""
+    """The CANT-mx-2-2-l and BRIDGE-mx-2-2-l problems of Tables 3 and 4 (the
+    selected mx and l): PBM with the paper's parameters and footnote
+    overrides (counts beside the tables'), then the same problem with this
+    library's options in mixed precision with rho_lo = --library-rho-lo
+    (time to KKT <= 1e-6)."""
+    from workloads import paper_tables as T
+    prec = V.VTS_MIXED if a.precision == "mixed" else V.VTS_FP64
     out = {}
-    for name in PAPER_COUNTS:
-        kind, mx, my, mz, l = name.split("-")
-        gen = W.paper_cantilever if kind == "CANT" else W.paper_bridge
-        pr = gen(int(mx), int(my), int(mz), int(l))
-        opts = V.default_options(eps_pbm=1e-5, eps_nwt_min=1e-3, eps_nwt_final=1e-4,
-                                 final_res4=0, eps_stat=0.0, accept_stall=0.0, p_min=1e-8,
-                                 q_min=1e-8, p_min_relative=0, eps_mr0=0.0, max_outer=100)
-        ctx = V.Context.from_problem(pr, precision=V.VTS_FP64, options=opts)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        status = V.VTS_OK
-        for k in range(opts.max_outer):
-            try:
-                s = ctx.pbm_iterate()
-            except V.VtsError as e:
-                status = e.status
-                break
-            print(f"{name}: outer {k + 1} ratio {s['ratio']:.2e} newton {s['newton_its']} "
-                  f"minres {s['minres_its']} t {time.perf_counter() - t0:.1f} s",
-                  file=sys.stderr, flush=True)
-            if s["converged"]:
-                break
-        r = ctx.pbm_solve(check=False) if status == V.VTS_OK else None
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        res = dict(m=pr.m, n=pr.n, seconds=dt, status=int(r["status"] if r else status))
-        if r:
-            res.update(outer=r["outer"], newton=r["newton"], minres=r["minres"],
-                       compliance=r["compliance"])
-        res["paper_pbm_nwt_mr"] = PAPER_COUNTS[name]
+    for name in paper_names(a):
+        pr = paper_problem(W, name)
+        e = T.entry(name)
+        res = dict(m=pr.m, n=pr.n, paper_pbm_outer_nwt_mr=e["pbm"],
+                   paper_flags=list(e["flags"]), paper_res_pbm=e["res_pbm"])
+        opts, over = paper_options(V, name, pr.n)
+        res["paper_overrides"] = over
+        ctx = V.Context.from_problem(pr, precision=prec, options=opts)
+        res["paper_parameters"] = run_pbm_capped(torch, V, ctx, name, "paper", a.cap_seconds,
+                                                 opts.max_outer)
+        res["paper_parameters"]["precision"] = "fp64" if prec == V.VTS_FP64 else "mixed"
+        ctx.close()
+        if not a.paper_only:
+            # this library's options target KKT <= 1e-6; its Gauss-Seidel
+            # multigrid (FP32 in mixed precision) needs a positive lower bound,
+            # here the one Section 7.2 uses for the interior point runs
+            lib = V.default_options()
+            if name.startswith("BRIDGE") and int(name.split("-")[-1]) >= 6:
+                # the point-supported bridge's relative penalty floor, as for
+                # the 128x64x64 bridge workload
+                lib.p_min = 3e-3
+            pr.rho_lo = a.library_rho_lo
+            ctx = V.Context.from_problem(pr, precision=V.VTS_MIXED, options=lib)
+            res["library_kkt"] = run_pbm_capped(torch, V, ctx, name, "library",
+                                                a.cap_seconds, lib.max_outer)
+            res["library_kkt"].update(precision="mixed", rho_lo=a.library_rho_lo, p_min=lib.p_min)
+            ctx.close()
         out[name] = res
         print(f"{name}: {json.dumps(res)}", file=sys.stderr, flush=True)
-        ctx.close()
     line = {"metric": METRIC, "value": None, "unit": "see problems", "n_gpus": 1,
             "steps": 1, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "paper problems (Section 7) with the paper's parameters"},
+            "config": {"workload": "paper problems (Section 7, Tables 3 and 4): the paper's "
+                                   "parameters, then this library's (KKT <= 1e-6, mixed)",
+                       "families": a.families, "levels": a.levels},
             "problems": out}
     print(json.dumps(line), flush=True)
     return 0

@@ -106,7 +106,11 @@ typedef struct {
     int32_t stall_steps;          /* final Newton stops after this many steps without a new best
                                      criterion below 0.9 x the best (0: never); then the
                                      accept_stall rule decides (the paper accepts stalled
-                                     near-optimal points, Section 7.2) */
+                                     near-optimal points, Section 7.2).  Also ends the outer loop
+                                     once the gap test holds and the stationarity term (eps_stat)
+                                     has gone this many outer iterations without a new value
+                                     below 0.9 x its best; the final Newton call and kkt_tol then
+                                     decide */
     int32_t use_graphs;           /* 1: replay each V-cycle from a captured HIP graph (the
                                      same kernels and arguments, bitwise equal results;
                                      recaptured after every multigrid setup; contexts built
@@ -125,7 +129,12 @@ typedef struct {
                                      with one V-cycle of blockdiag(K(rho), 1), stopping at this
                                      relative residual in the preconditioner norm), so that the
                                      returned u is the state of the returned density; <= 0: u is
-                                     the last Newton iterate.  Default 1e-10 */
+                                     the last Newton iterate.  Skipped when some lower bound
+                                     rho_lo is 0: K(rho) may then be singular on a void region,
+                                     where the state equation leaves u free, and the last Newton
+                                     iterate (the dual solution of problem (2.2)) is the
+                                     displacement that meets the optimality conditions.
+                                     Default 1e-10 */
 } vts_options;
 
 typedef struct {

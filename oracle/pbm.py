@@ -490,6 +490,7 @@ class Solver:
         if st is None:
             st = initial_state(P.grid.n_dof, P.grid.m, P.V)
         eps_nwt = o.eps_nwt0
+        stat_best, stat_since = 0.0, -1
         for k in range(o.max_outer):
             st, ev = self.newton(st, eps_nwt)
             delta = duality_gap(P, st, ev.e)
@@ -502,7 +503,18 @@ class Solver:
             self.log.outer[-1]["stat"] = stat
             if self.progress is not None:
                 self.progress(k, self.log.outer[-1])
-            if self.status != "ok" or (ratio < o.eps_pbm and stat < (o.eps_stat or 1.0)):
+            stat_ok = stat < (o.eps_stat or 1.0)
+            if ratio < o.eps_pbm and not stat_ok and o.stall_steps > 0:
+                # the stationarity test is an addition to Algorithm 1's gap test:
+                # once the gap test holds and the term stops decreasing (no new
+                # value below 0.9 x its best for stall_steps outer iterations),
+                # the loop ends and the final Newton call and the KKT check decide
+                if stat_since < 0 or stat < 0.9 * stat_best:
+                    stat_best, stat_since = stat, 0
+                else:
+                    stat_since += 1
+                    stat_ok = stat_since >= o.stall_steps
+            if self.status != "ok" or (ratio < o.eps_pbm and stat_ok):
                 break
             st.rho, st.mu_lo, st.mu_hi = rho_n, mul_n, muh_n
             st.p = np.maximum(o.gamma * st.p, p_floor(o, st.alpha))
@@ -519,8 +531,11 @@ class Solver:
                 self.status = "ok"          # near-optimal stall accepted
             if self.status == "ok" or (stalled and o.kkt_tol > 0):
                 st.rho, _, _ = update_multipliers(st, ev, o.beta, rho_only=True)
-                if o.final_state_solve:
+                if o.final_state_solve and np.min(P.rho_lo) > 0:
                     # the primal pair of problem (1.1): the state of the returned density
+                    # (with a zero lower bound K(rho) may be singular on a void region,
+                    # where the state equation leaves u free; the dual iterate is then
+                    # the displacement that meets the optimality conditions)
                     from .kkt import solve_state
                     st.u = solve_state(P.grid, P.Ke, st.rho, P.f)
                 from .kkt import kkt_residual

@@ -624,7 +624,20 @@ vts_status pbm_iterate(Ctx& c, vts_pbmstats* out) {
     const double ratio = std::fabs(gap / dual);
     const double stat = r[SL_STAT];
     c.outer += 1;
-    const bool stop = ratio < c.opt.eps_pbm && (c.opt.eps_stat <= 0 || stat < c.opt.eps_stat);
+    const bool gap_ok = ratio < c.opt.eps_pbm;
+    bool stat_ok = c.opt.eps_stat <= 0 || stat < c.opt.eps_stat;
+    if (gap_ok && !stat_ok && c.opt.stall_steps > 0) {
+        // the stationarity term is this library's addition to the gap test;
+        // once the gap test holds and the term stops decreasing, the outer
+        // loop ends and the final Newton call and the KKT check decide
+        if (c.stat_since < 0 || stat < 0.9 * c.stat_best) {
+            c.stat_best = stat;
+            c.stat_since = 0;
+        } else if (++c.stat_since >= c.opt.stall_steps) {
+            stat_ok = true;
+        }
+    }
+    const bool stop = gap_ok && stat_ok;
     if (out) {
         out->gap = gap;
         out->dual = dual;
@@ -816,7 +829,7 @@ struct HostData {
     std::vector<uint8_t> mask;
     std::vector<double> f, lo, hi;
     int64_t nfree = 0;
-    double norm_f = 0.0, norm_bounds = 0.0;
+    double norm_f = 0.0, norm_bounds = 0.0, lo_min = 0.0;
 };
 
 vts_status prepare_host(const vts_problem* pr, HostData& hd, std::string& err) {
@@ -850,6 +863,7 @@ vts_status prepare_host(const vts_problem* pr, HostData& hd, std::string& err) {
     }
     if (!(slo < pr->V && pr->V < shi)) { err = "volume not strictly feasible"; return VTS_EINVAL; }
     hd.norm_bounds = std::sqrt(nlo2) + std::sqrt(nhi2);
+    hd.lo_min = *std::min_element(hd.lo.begin(), hd.lo.end());
     std::vector<uint8_t> mk = hd.mask;
     Dims dk = d0;
     for (int k = pr->levels - 1; k > 0; --k) {
@@ -892,6 +906,7 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
     c.nfree = hd.nfree;
     c.norm_f = hd.norm_f;
     c.norm_bounds = hd.norm_bounds;
+    c.lo_min = hd.lo_min;
     HIPCHK(hipGetDevice(&c.device));
 
     // constants
@@ -1081,6 +1096,7 @@ vts_status vts_reset(vts_ctx* cp) {
     c.res_prev = -1.0;
     c.outer = c.newton_total = c.minres_total = 0;
     c.converged = false;
+    c.stat_since = -1;
     c.eval_valid = c.setup_valid = false;
     c.status = VTS_OK;
     HIPCHK(hipGetLastError());
@@ -1261,7 +1277,10 @@ vts_status vts_pbm_solve(vts_ctx* cp, vts_result* res) {
                 launch_round_rho(c);
                 c.eval_valid = false;
                 c.setup_valid = false;
-                if (c.opt.eps_state > 0) s2 = state_solve(c, c.opt.eps_state);
+                // with a zero lower bound K(rho) may be singular on a void region,
+                // where the state equation leaves u free; the dual iterate is then
+                // the displacement that meets the optimality conditions
+                if (c.opt.eps_state > 0 && c.lo_min > 0) s2 = state_solve(c, c.opt.eps_state);
             }
             if (s2 == VTS_OK) {
                 launch_kkt(c, c.alpha, c.g1);
@@ -1523,6 +1542,7 @@ vts_status vts_set_state(vts_ctx* cp, const void* buf, size_t bytes) {
     c.eval_valid = false;
     c.setup_valid = false;
     c.converged = false;
+    c.stat_since = -1;
     return VTS_OK;
 }
 

@@ -90,6 +90,7 @@ struct Ctx {
     double* rlo = nullptr;       // m
     double* rhi = nullptr;       // m
     double norm_f = 0, norm_bounds = 0;
+    double lo_min = 0;             // smallest lower bound of rho
 
     // PBM state (device)
     double* u = nullptr;         // ndof
@@ -145,6 +146,9 @@ struct Ctx {
     int outer = 0, newton_total = 0, minres_total = 0;
     int status = VTS_OK;
     bool converged = false;
+    double stat_best = 0;           // smallest stationarity term since the gap test first held
+    int stat_since = -1;            // outer iterations since it last fell below 0.9 x best
+                                    // (-1: the gap test has not held yet)
     std::string err;
 
     // interior point method (Algorithm 3): options, barrier parameters and

@@ -188,7 +188,10 @@ def lib():
 def default_options(**overrides) -> Options_t:
     o = Options_t()
     lib().vts_default_options(C.byref(o))
+    names = {f[0] for f in Options_t._fields_}
     for k, v in overrides.items():
+        if k not in names:
+            raise KeyError(f"vts_options has no field {k!r}")
         setattr(o, k, v)
     return o
 
