@@ -76,6 +76,8 @@ def parse():
                     help="time-to-KKT of the benchmark cantilever family at refinement levels "
                          "--levels (n up to 12.8 M DOFs); one JSON line")
     ap.add_argument("--levels", type=int, nargs="+", default=[5, 6, 7])
+    ap.add_argument("--kinds", nargs="+", default=["CANT", "BRIDGE"],
+                    choices=["CANT", "BRIDGE"], help="problem kinds (--paper)")
     ap.add_argument("--families", type=int, nargs="+", default=[2, 4, 6, 8],
                     help="m_x of the CANT/BRIDGE-m_x-2-2-l problems (--paper)")
     ap.add_argument("--cap-seconds", type=float, default=600.0,
@@ -87,7 +89,13 @@ def parse():
     ap.add_argument("--scale-kernels", action="store_true",
                     help="the dominant kernels (finest Gauss-Seidel pass, K(rho)x, S-apply) "
                          "timed at each of --levels, FP64 and mixed; one JSON line")
-    ap.add_argument("--requests", type=int, default=20, help="requests per rate (--serve)")
+    ap.add_argument("--requests", type=int, default=256, help="requests per rate (--serve)")
+    ap.add_argument("--rates", type=float, nargs="+", default=[0.5, 0.8, 1.2],
+                    help="--serve: arrival rates as multiples of 1 / mean alone service time")
+    ap.add_argument("--t-alone", type=float, default=None,
+                    help="--serve: mean alone service time to use (default: measured)")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="--serve: each request's launches on its own stream")
     ap.add_argument("--slots", type=int, default=4, help="concurrent requests (--serve)")
     ap.add_argument("--pool-gb", type=float, default=16.0, help="device pool (--serve)")
     return ap.parse_args()
@@ -276,7 +284,7 @@ def kernels_only(a, torch, W, V):
 
 def paper_names(a):
     """CANT-mx-2-2-l and BRIDGE-mx-2-2-l for the selected mx and l (Tables 3, 4)."""
-    return [f"{kind}-{mx}-2-2-{l}" for kind in ("CANT", "BRIDGE") for l in a.levels
+    return [f"{kind}-{mx}-2-2-{l}" for kind in a.kinds for l in a.levels
             for mx in a.families]
 
 
@@ -706,24 +714,26 @@ def serving(a, torch, W, V):
     for r, p in zip(alone, probs):
         print(f"alone {p.name} status {r['status']} service {r['service']:.2f} s",
               file=sys.stderr, flush=True)
-    t_alone = float(np.mean([r["service"] for r in alone]))
+    t_alone = a.t_alone if a.t_alone else float(np.mean([r["service"] for r in alone]))
     pool = int(a.pool_gb * (1 << 30))
     rates = {}
     same = True
-    for factor in (0.5, 0.8, 1.2):
+    for factor in a.rates:
         lam = factor / t_alone
         reqs = W.serving_requests(a.requests, rate=lam, seed=0)
-        srv = V.Server(a.slots, pool)
+        srv = V.Server(a.slots, pool, batching=not a.no_batching)
         recs = serve.run_stream(srv, reqs, precision=V.VTS_MIXED, options=opts,
                                 on_done=lambda r: print(
                                     f"  rate x{factor}: request {r['index']} status {r['status']} "
                                     f"latency {r['latency']:.2f} s", file=sys.stderr, flush=True))
+        gstats = srv.group_stats()
         srv.close()
         for k in range(n_alone):
             same &= (recs[k]["compliance"] == alone[k]["compliance"] and
                      recs[k]["minres"] == alone[k]["minres"])
-        rates[f"x{factor}"] = dict(rate_per_s=lam, **serve.summarize(recs))
-    mid = rates["x0.8"]
+        rates[f"x{factor}"] = dict(rate_per_s=lam, **serve.summarize(recs),
+                                   batching=gstats if not a.no_batching else None)
+    mid = rates.get("x0.8") or rates[f"x{a.rates[0]}"]
     line = {
         "metric": METRIC, "value": mid["throughput_per_s"],
         "unit": "VTS solves/s (served stream at 0.8 x capacity of one-at-a-time service)",
@@ -733,7 +743,8 @@ def serving(a, torch, W, V):
         "dtype": "f64+f32mg", "data": "synthetic",
         "config": {"workload": "serving stream", "grids": [list(g) for g in W.SERVING_GRIDS],
                    "requests_per_rate": a.requests, "slots": a.slots, "pool_gb": a.pool_gb,
-                   "precision": "mixed", "p_min": opts.p_min, "max_outer": opts.max_outer},
+                   "precision": "mixed", "p_min": opts.p_min, "max_outer": opts.max_outer,
+                   "batching": not a.no_batching, "rates": a.rates},
         "p50_s": mid["p50_s"], "p99_s": mid["p99_s"],
         "mean_service_alone_s": t_alone, "rates": rates,
         "mix_equals_alone": bool(same),

@@ -438,13 +438,18 @@ vts_status vts_ip_step(vts_ctx* ctx, vts_ipstats* stats);
  * (VTS_OK) or max_iter iterations (VTS_ENOTCONV).  stats may be NULL. */
 vts_status vts_ip_solve(vts_ctx* ctx, const vts_ip_options* opt, vts_ipstats* stats);
 
-/* Advances each of the k contexts by one outer iteration of Algorithm 1
- * (as vts_pbm_iterate), their device work overlapping: one host thread per
- * context, each driving its own context's stream (the contexts should be
- * created on different streams).  stats (NULL, or k entries) receives each
- * context's statistics.  Returns VTS_OK, or the status of the first context
- * (in index order) that failed; the others still complete their iteration.
- * Each context's result is the same as with vts_pbm_iterate alone. */
+/* Advances each of the k (distinct) contexts by one outer iteration of
+ * Algorithm 1 (as vts_pbm_iterate): one host thread per context for the
+ * element-wise steps, and the Newton systems' preconditioned MINRES solves
+ * (Section 6) of all k advanced together on one stream, step by step: the
+ * launches of contexts with the same grid, levels and precision (V-cycle
+ * smoother, transfer and coarse kernels, S-apply, vector updates and
+ * reductions) go out as one launch per kernel over those contexts, with
+ * one synchronization per MINRES step for all.  stats (NULL, or k entries)
+ * receives each context's statistics.  Returns VTS_OK, or the status of the
+ * first context (in index order) that failed; the others still complete
+ * their iteration.  Each context's result is bitwise the same as with
+ * vts_pbm_iterate alone (same kernel bodies, blocks and reduction orders). */
 vts_status vts_group_step(vts_ctx** ctxs, int32_t k, vts_pbmstats* stats);
 
 /* ---------------------------------------------------------------------
@@ -456,9 +461,16 @@ vts_status vts_group_step(vts_ctx** ctxs, int32_t k, vts_pbmstats* stats);
  * bypass, as soon as a slot is idle and a contiguous range of the pool
  * holds its vts_footprint_bytes; its context is built inside that range (no
  * hipMalloc or hipFree while serving), solved, and its range returned.
- * Admitted problems run concurrently on the device, each on its own stream;
- * every problem's arithmetic is the same as in a context of its own (fixed
- * reduction orders, no atomics), so results do not depend on the mix.
+ * Admitted problems run concurrently on the device, each on its own stream.
+ * With batching on (the default), the Newton-system MINRES solves of
+ * admitted problems with the same grid, levels and precision join a group
+ * runner for that shape (one thread and stream each, created on first use
+ * with a small staging buffer): the solves in it advance step by step
+ * together, and each kernel of a step is one launch over all of them
+ * (problem = blockIdx.y), as in vts_group_step; solves join and leave
+ * between steps.  Every problem's arithmetic is the same as in a context of
+ * its own (same kernel bodies, blocks, fixed reduction orders, no
+ * atomics), so results do not depend on the mix.
  * --------------------------------------------------------------------- */
 typedef struct vts_server vts_server;
 
@@ -498,7 +510,19 @@ double vts_server_clock(const vts_server* srv);
 void vts_server_counts(const vts_server* srv, int32_t* pending, int32_t* running,
                        int32_t* finished);
 
-/* Finishes the running requests, drops the pending ones, frees the pool. */
+/* Batching of same-shape MINRES solves across requests: on (1, the
+ * default) or off (0: each request's launches go out on its own stream).
+ * Only before the first vts_server_submit: VTS_ESTATE afterwards. */
+vts_status vts_server_batching(vts_server* srv, int32_t on);
+
+/* Counters of the group runners, summed over shapes: out[0] synchronized
+ * MINRES steps, out[1] solves completed, out[2] kernel launches the solves
+ * asked for, out[3] launches issued for them (out[2] / out[3] is the mean
+ * batch), out[4] the largest batch. */
+void vts_server_group_stats(vts_server* srv, int64_t out[5]);
+
+/* Finishes the running requests, drops the pending ones, frees the pool and
+ * the group runners. */
 void vts_server_destroy(vts_server* srv);
 
 #ifdef __cplusplus

@@ -416,7 +416,7 @@ bool precond_graph(Ctx& c, const double* r, double* z) {
 void precond(Ctx& c, const double* r, double* z) {
     // graphs only outside server pools (instantiation may allocate) and
     // while no kernel class is being timed
-    if (c.opt.use_graphs && !c.arena && c.prof_class == 0 && precond_graph(c, r, z)) return;
+    if (c.opt.use_graphs && !c.arena && !c.rec && c.prof_class == 0 && precond_graph(c, r, z)) return;
     vcycle_launches(c, r, z);
 }
 
@@ -425,92 +425,165 @@ void precond(Ctx& c, const double* r, double* z) {
 // M^{-1}-norm estimate phi_bar of the residual is <= eps * beta_1.  A
 // negative M^{-1}-norm means the V-cycle is not positive definite in floating
 // point: VTS_ENONSPD, or with stop_indef the iterate reached so far is kept.
-vts_status minres(Ctx& c, double eps, vts_linstats* out, int maxit = -1,
-                  bool stop_indef = false) {
-    if (maxit < 0) maxit = c.opt.max_minres;
-    const int64_t n = c.ndof + 1;
-    double *x = c.mv[0], *r1 = c.mv[1], *r2 = c.mv[2], *y = c.mv[3], *v = c.mv[4];
-    double* wb[3] = {c.mv[5], c.mv[6], c.mv[7]};   // w, w1(k-2), w2(k-1) rotate
-    launch_fill(c, x, 0.0, n);
-    HIPCHK(hipMemcpyAsync(r1, c.rhs, n * sizeof(double), hipMemcpyDeviceToDevice, c.s));
-    precond(c, r1, y);
-    launch_dot(c, r1, y, n, SL_DOT);
-    vts_status st = sync_red(c);
-    if (st != VTS_OK) return st;
+//
+// The solve is split into steps between its synchronizations so that a group
+// runner can advance several solves together: mr_issue_* queue the device
+// work of one step (issued on c.s, or recorded while c.rec is set), the
+// reductions land in c.red_host after the stream is synchronized, and
+// mr_after_* read them.  minres() runs the steps for one context.
+}  // namespace
+
+namespace vts {
+
+void mr_init(Ctx& c, MrState& m, double eps, int maxit, bool stop_indef) {
+    m = MrState{};
+    m.eps = eps;
+    m.maxit = maxit < 0 ? c.opt.max_minres : maxit;
+    m.stop_indef = stop_indef;
+    m.n = c.ndof + 1;
+    m.x = c.mv[0];
+    m.r1 = c.mv[1];
+    m.r2 = c.mv[2];
+    m.y = c.mv[3];
+    m.v = c.mv[4];
+    m.wb[0] = c.mv[5];
+    m.wb[1] = c.mv[6];
+    m.wb[2] = c.mv[7];
+}
+
+static void mr_red_copy(Ctx& c) {
+    (void)vmemcpy(c, c.red_host, c.red, kRedSlots * sizeof(double), hipMemcpyDeviceToHost);
+}
+
+void mr_issue_start(Ctx& c, MrState& m) {
+    launch_fill(c, m.x, 0.0, m.n);
+    (void)vmemcpy(c, m.r1, c.rhs, m.n * sizeof(double), hipMemcpyDeviceToDevice);
+    precond(c, m.r1, m.y);
+    launch_dot(c, m.r1, m.y, m.n, SL_DOT);
+    mr_red_copy(c);
+}
+
+void mr_after_start(Ctx& c, MrState& m) {
     const double b1sq = c.red_host[SL_DOT];
-    const bool indef0 = stop_indef && b1sq < 0;
+    const bool indef0 = m.stop_indef && b1sq < 0;
     if (!indef0 && (!(b1sq >= 0) || !std::isfinite(b1sq))) {
         c.err = "MINRES: preconditioner not positive definite";
-        return VTS_ENONSPD;
+        m.st = VTS_ENONSPD;
+        m.phase = MrState::kDone;
+        return;
     }
-    int it = 0;
-    double rel = indef0 ? 1.0 : 0.0;
-    if (b1sq > 0) {
-        const double beta1 = std::sqrt(b1sq);
-        double beta = beta1, beta_old = 0.0;
-        HIPCHK(hipMemcpyAsync(r2, r1, n * sizeof(double), hipMemcpyDeviceToDevice, c.s));
-        launch_fill(c, wb[0], 0.0, n);
-        launch_fill(c, wb[1], 0.0, n);
-        launch_fill(c, wb[2], 0.0, n);
-        int iw = 0, iw1 = 1, iw2 = 2;                 // buffers holding w_k-1 ... as in the recurrence
-        double cs = -1.0, sn = 0.0, dbar = 0.0, eps_l = 0.0, phibar = beta1;
-        for (it = 1; it <= maxit; ++it) {
-            launch_scale(c, v, y, 1.0 / beta, n);
-            launch_apply_S(c, v, y);
-            if (it >= 2) launch_axpy(c, y, -beta / beta_old, r1, n);
-            // alpha = v . S v stays on the device for the next update; the
-            // host reads it with beta^2 after one synchronization
-            launch_dot(c, v, y, n, SL_MRALPHA);
-            launch_axpy_red(c, y, SL_MRALPHA, beta, r2, n);
-            std::swap(r1, r2);
-            std::swap(r2, y);
-            precond(c, r2, y);
-            launch_dot(c, r2, y, n, SL_DOT);
-            if ((st = sync_red(c)) != VTS_OK) return st;
-            const double alpha = c.red_host[SL_MRALPHA];
-            const double bsq = c.red_host[SL_DOT];
-            if (stop_indef && bsq < 0) {
-                rel = phibar / beta1;
-                break;
-            }
-            if (!(bsq >= 0) || !std::isfinite(bsq)) {
-                c.err = "MINRES: preconditioner not positive definite";
-                return VTS_ENONSPD;
-            }
-            beta_old = beta;
-            beta = std::sqrt(bsq);
-            const double eps_old = eps_l;
-            const double delta = cs * dbar + sn * alpha;
-            const double gbar = sn * dbar - cs * alpha;
-            eps_l = sn * beta;
-            dbar = -cs * beta;
-            double gamma = std::hypot(gbar, beta);
-            gamma = std::max(gamma, 2.220446049250313e-16);
-            cs = gbar / gamma;
-            sn = beta / gamma;
-            const double phi = cs * phibar;
-            phibar = sn * phibar;
-            // w1 <- w2, w2 <- w, w <- (v - eps_old w1 - delta w2)/gamma
-            const int old_w1 = iw1;
-            iw1 = iw2;
-            iw2 = iw;
-            iw = old_w1;
-            launch_minres_w(c, wb[iw], v, wb[iw1], wb[iw2], eps_old, delta, 1.0 / gamma, x, phi, n);
-            rel = phibar / beta1;
-            if (phibar <= eps * beta1) break;
-        }
-        if (it > maxit) it = maxit;
+    m.rel = indef0 ? 1.0 : 0.0;
+    if (!(b1sq > 0) || m.maxit <= 0) {
+        m.phase = MrState::kFinish;
+        return;
     }
-    HIPCHK(hipMemcpyAsync(c.dy, x, n * sizeof(double), hipMemcpyDeviceToDevice, c.s));
-    // keep the rotated buffers consistent for the next call
-    c.mv[1] = r1; c.mv[2] = r2; c.mv[3] = y;
-    HIPCHK(hipGetLastError());
-    c.minres_total += it;
+    m.beta1 = std::sqrt(b1sq);
+    m.beta = m.beta1;
+    m.beta_old = 0.0;
+    (void)vmemcpy(c, m.r2, m.r1, m.n * sizeof(double), hipMemcpyDeviceToDevice);
+    launch_fill(c, m.wb[0], 0.0, m.n);
+    launch_fill(c, m.wb[1], 0.0, m.n);
+    launch_fill(c, m.wb[2], 0.0, m.n);
+    m.iw = 0;
+    m.iw1 = 1;
+    m.iw2 = 2;
+    m.cs = -1.0;
+    m.sn = 0.0;
+    m.dbar = 0.0;
+    m.eps_l = 0.0;
+    m.phibar = m.beta1;
+    m.phase = MrState::kIterate;
+}
+
+void mr_issue_iter(Ctx& c, MrState& m) {
+    ++m.it;
+    launch_scale(c, m.v, m.y, 1.0 / m.beta, m.n);
+    launch_apply_S(c, m.v, m.y);
+    if (m.it >= 2) launch_axpy(c, m.y, -m.beta / m.beta_old, m.r1, m.n);
+    // alpha = v . S v stays on the device for the next update; the host
+    // reads it with beta^2 after one synchronization
+    launch_dot(c, m.v, m.y, m.n, SL_MRALPHA);
+    launch_axpy_red(c, m.y, SL_MRALPHA, m.beta, m.r2, m.n);
+    std::swap(m.r1, m.r2);
+    std::swap(m.r2, m.y);
+    precond(c, m.r2, m.y);
+    launch_dot(c, m.r2, m.y, m.n, SL_DOT);
+    mr_red_copy(c);
+}
+
+void mr_after_iter(Ctx& c, MrState& m) {
+    const double alpha = c.red_host[SL_MRALPHA];
+    const double bsq = c.red_host[SL_DOT];
+    if (m.stop_indef && bsq < 0) {
+        m.rel = m.phibar / m.beta1;
+        m.phase = MrState::kFinish;
+        return;
+    }
+    if (!(bsq >= 0) || !std::isfinite(bsq)) {
+        c.err = "MINRES: preconditioner not positive definite";
+        m.st = VTS_ENONSPD;
+        m.phase = MrState::kDone;
+        return;
+    }
+    m.beta_old = m.beta;
+    m.beta = std::sqrt(bsq);
+    const double eps_old = m.eps_l;
+    const double delta = m.cs * m.dbar + m.sn * alpha;
+    const double gbar = m.sn * m.dbar - m.cs * alpha;
+    m.eps_l = m.sn * m.beta;
+    m.dbar = -m.cs * m.beta;
+    double gamma = std::hypot(gbar, m.beta);
+    gamma = std::max(gamma, 2.220446049250313e-16);
+    m.cs = gbar / gamma;
+    m.sn = m.beta / gamma;
+    const double phi = m.cs * m.phibar;
+    m.phibar = m.sn * m.phibar;
+    // w1 <- w2, w2 <- w, w <- (v - eps_old w1 - delta w2)/gamma
+    const int old_w1 = m.iw1;
+    m.iw1 = m.iw2;
+    m.iw2 = m.iw;
+    m.iw = old_w1;
+    launch_minres_w(c, m.wb[m.iw], m.v, m.wb[m.iw1], m.wb[m.iw2], eps_old, delta, 1.0 / gamma,
+                    m.x, phi, m.n);
+    m.rel = m.phibar / m.beta1;
+    if (m.phibar <= m.eps * m.beta1 || m.it >= m.maxit) m.phase = MrState::kFinish;
+}
+
+// the result into c.dy, counters; c.mv keeps the rotated buffers for the next call
+void mr_finish(Ctx& c, MrState& m, vts_linstats* out) {
+    (void)vmemcpy(c, c.dy, m.x, m.n * sizeof(double), hipMemcpyDeviceToDevice);
+    c.mv[1] = m.r1;
+    c.mv[2] = m.r2;
+    c.mv[3] = m.y;
+    c.minres_total += m.it;
     if (out) {
-        out->iterations = it;
-        out->rel_residual = rel;
+        out->iterations = m.it;
+        out->rel_residual = m.rel;
     }
-    return VTS_OK;
+    m.phase = MrState::kDone;
+}
+
+}  // namespace vts
+
+namespace {
+
+vts_status minres(Ctx& c, double eps, vts_linstats* out, int maxit = -1,
+                  bool stop_indef = false) {
+    if (c.group && !stop_indef && c.prof_class == 0 && tile_ok(c))
+        return group_minres(c, eps, out, maxit < 0 ? c.opt.max_minres : maxit);
+    MrState m;
+    mr_init(c, m, eps, maxit, stop_indef);
+    mr_issue_start(c, m);
+    HIPCHK(hipStreamSynchronize(c.s));
+    mr_after_start(c, m);
+    while (m.phase == MrState::kIterate) {
+        mr_issue_iter(c, m);
+        HIPCHK(hipStreamSynchronize(c.s));
+        mr_after_iter(c, m);
+    }
+    if (m.phase == MrState::kFinish) mr_finish(c, m, out);
+    HIPCHK(hipGetLastError());
+    return m.st;
 }
 
 vts_status newton_step(Ctx& c, vts_newtonstats* out, bool final_call) {

@@ -84,8 +84,9 @@ static inline int grid1d(int64_t n) {
 }
 
 // Sum (or max) of partials[slot*kRedBlocks + b] over b < nb, fixed order.
-__global__ void k_finalize(const double* __restrict__ partials, int nb, int slot0,
-                           uint32_t maxmask, double* __restrict__ out) {
+__device__ __forceinline__ void finalize_body(const double* __restrict__ partials, int nb,
+                                              int slot0, uint32_t maxmask,
+                                              double* __restrict__ out) {
     const int q = slot0 + blockIdx.x;
     const bool mx = (maxmask >> blockIdx.x) & 1u;
     double x = mx ? -DBL_MAX : 0.0;
@@ -102,6 +103,11 @@ __global__ void k_finalize(const double* __restrict__ partials, int nb, int slot
         __syncthreads();
     }
     if (threadIdx.x == 0) out[q] = sh[0];
+}
+
+__global__ void k_finalize(const double* __restrict__ partials, int nb, int slot0,
+                           uint32_t maxmask, double* __restrict__ out) {
+    finalize_body(partials, nb, slot0, maxmask, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -704,19 +710,37 @@ void launch_round_rho(Ctx& c) {
 // ---------------------------------------------------------------------------
 // vector kernels (MINRES)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads)
-k_dot(const double* __restrict__ x, const double* __restrict__ y, int64_t n, int slot,
-      double* partials) {
+struct DotArgs {
+    const double* x;
+    const double* y;
+    int64_t n;
+    int slot;
+    double* partials;
+};
+__device__ __forceinline__ void dot_body(const DotArgs& a) {
     double acc[1] = {0.0};
-    for (int64_t t = gid(); t < n; t += (int64_t)gridDim.x * blockDim.x) acc[0] += x[t] * y[t];
-    block_sum_store<1>(acc, partials, slot);
+    for (int64_t t = gid(); t < a.n; t += (int64_t)gridDim.x * blockDim.x)
+        acc[0] += a.x[t] * a.y[t];
+    block_sum_store<1>(acc, a.partials, a.slot);
 }
+VTS_KERNEL_PAIR(, kThreads, k_dot, DotArgs, dot_body)
+
+struct FinArgs {
+    const double* partials;
+    int nb, slot;
+    double* out;
+};
+__device__ __forceinline__ void fin_body(const FinArgs& a) {
+    finalize_body(a.partials, a.nb, a.slot, 0u, a.out);
+}
+VTS_KERNEL_PAIR(, kThreads, k_dot_fin, FinArgs, fin_body)
 
 void launch_dot(Ctx& c, const double* x, const double* y, int64_t n, int slot) {
     const int g = red_grid(n);
-    hipLaunchKernelGGL(k_dot, dim3(g), dim3(kThreads), 0, c.s, x, y, n, slot, c.partials);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c.s, c.partials, g, slot, 0u,
-                       c.red);
+    vlaunch(c, (const void*)&k_dot, (const void*)&k_dot_b, dim3(g), dim3(kThreads),
+            DotArgs{x, y, n, slot, c.partials});
+    vlaunch(c, (const void*)&k_dot_fin, (const void*)&k_dot_fin_b, dim3(1), dim3(kThreads),
+            FinArgs{c.partials, g, slot, c.red});
 }
 
 __global__ void k_copy1(const double* __restrict__ src, double* __restrict__ dst) {
@@ -733,41 +757,70 @@ void launch_set(Ctx& c, double* dst, double v) {
     hipLaunchKernelGGL(k_set, dim3(1), dim3(64), 0, c.s, dst, v);
 }
 
-__global__ void k_fill(double* __restrict__ d, double v, int64_t n) {
+struct FillArgs {
+    double* d;
+    double v;
+    int64_t n;
+};
+__device__ __forceinline__ void fill_body(const FillArgs& a) {
     const int64_t t = gid();
-    if (t < n) d[t] = v;
+    if (t < a.n) a.d[t] = a.v;
 }
+VTS_KERNEL_PAIR(, kThreads, k_fill, FillArgs, fill_body)
 void launch_fill(Ctx& c, double* dst, double v, int64_t n) {
-    hipLaunchKernelGGL(k_fill, dim3(grid1d(n)), dim3(kThreads), 0, c.s, dst, v, n);
+    vlaunch(c, (const void*)&k_fill, (const void*)&k_fill_b, dim3(grid1d(n)), dim3(kThreads),
+            FillArgs{dst, v, n});
 }
 
-__global__ void k_scale(double* __restrict__ d, const double* __restrict__ s, double a,
-                        int64_t n) {
+struct ScaleArgs {
+    double* d;
+    const double* s;
+    double a;
+    int64_t n;
+};
+__device__ __forceinline__ void scale_body(const ScaleArgs& a) {
     const int64_t t = gid();
-    if (t < n) d[t] = a * s[t];
+    if (t < a.n) a.d[t] = a.a * a.s[t];
 }
+VTS_KERNEL_PAIR(, kThreads, k_scale, ScaleArgs, scale_body)
 void launch_scale(Ctx& c, double* dst, const double* src, double a, int64_t n) {
-    hipLaunchKernelGGL(k_scale, dim3(grid1d(n)), dim3(kThreads), 0, c.s, dst, src, a, n);
+    vlaunch(c, (const void*)&k_scale, (const void*)&k_scale_b, dim3(grid1d(n)), dim3(kThreads),
+            ScaleArgs{dst, src, a, n});
 }
 
-__global__ void k_axpy(double* __restrict__ y, double a, const double* __restrict__ x,
-                       int64_t n) {
+struct AxpyArgs {
+    double* y;
+    double a;
+    const double* x;
+    int64_t n;
+};
+__device__ __forceinline__ void axpy_body(const AxpyArgs& a) {
     const int64_t t = gid();
-    if (t < n) y[t] += a * x[t];
+    if (t < a.n) a.y[t] += a.a * a.x[t];
 }
+VTS_KERNEL_PAIR(, kThreads, k_axpy, AxpyArgs, axpy_body)
 void launch_axpy(Ctx& c, double* y, double a, const double* x, int64_t n) {
-    hipLaunchKernelGGL(k_axpy, dim3(grid1d(n)), dim3(kThreads), 0, c.s, y, a, x, n);
+    vlaunch(c, (const void*)&k_axpy, (const void*)&k_axpy_b, dim3(grid1d(n)), dim3(kThreads),
+            AxpyArgs{y, a, x, n});
 }
 
-__global__ void k_axpy_red(double* __restrict__ y, const double* __restrict__ red, int slot,
-                           double div, const double* __restrict__ x, int64_t n) {
+struct AxpyRedArgs {
+    double* y;
+    const double* red;
+    int slot;
+    double div;
+    const double* x;
+    int64_t n;
+};
+__device__ __forceinline__ void axpy_red_body(const AxpyRedArgs& a) {
     const int64_t t = gid();
-    const double a = -(red[slot] / div);
-    if (t < n) y[t] += a * x[t];
+    const double f = -(a.red[a.slot] / a.div);
+    if (t < a.n) a.y[t] += f * a.x[t];
 }
+VTS_KERNEL_PAIR(, kThreads, k_axpy_red, AxpyRedArgs, axpy_red_body)
 void launch_axpy_red(Ctx& c, double* y, int slot, double div, const double* x, int64_t n) {
-    hipLaunchKernelGGL(k_axpy_red, dim3(grid1d(n)), dim3(kThreads), 0, c.s, y, c.red, slot, div,
-                       x, n);
+    vlaunch(c, (const void*)&k_axpy_red, (const void*)&k_axpy_red_b, dim3(grid1d(n)),
+            dim3(kThreads), AxpyRedArgs{y, c.red, slot, div, x, n});
 }
 
 // ---------------------------------------------------------------------------
@@ -997,21 +1050,29 @@ void launch_ip_update(Ctx& c, double ku, double kl, double kh) {
 }
 
 // w = (v - eps_old w1 - delta w2) / gamma ; x += phi w
-__global__ void k_minres_w(double* __restrict__ w, const double* __restrict__ v,
-                           const double* __restrict__ w1, const double* __restrict__ w2,
-                           double eps_old, double delta, double inv_gamma,
-                           double* __restrict__ x, double phi, int64_t n) {
+struct MinresWArgs {
+    double* w;
+    const double* v;
+    const double* w1;
+    const double* w2;
+    double eps_old, delta, inv_gamma;
+    double* x;
+    double phi;
+    int64_t n;
+};
+__device__ __forceinline__ void minres_w_body(const MinresWArgs& a) {
     const int64_t t = gid();
-    if (t >= n) return;
-    const double wn = (v[t] - eps_old * w1[t] - delta * w2[t]) * inv_gamma;
-    w[t] = wn;
-    x[t] += phi * wn;
+    if (t >= a.n) return;
+    const double wn = (a.v[t] - a.eps_old * a.w1[t] - a.delta * a.w2[t]) * a.inv_gamma;
+    a.w[t] = wn;
+    a.x[t] += a.phi * wn;
 }
+VTS_KERNEL_PAIR(, kThreads, k_minres_w, MinresWArgs, minres_w_body)
 void launch_minres_w(Ctx& c, double* w, const double* v, const double* w1, const double* w2,
                      double eps_old, double delta, double inv_gamma, double* x, double phi,
                      int64_t n) {
-    hipLaunchKernelGGL(k_minres_w, dim3(grid1d(n)), dim3(kThreads), 0, c.s, w, v, w1, w2,
-                       eps_old, delta, inv_gamma, x, phi, n);
+    vlaunch(c, (const void*)&k_minres_w, (const void*)&k_minres_w_b, dim3(grid1d(n)),
+            dim3(kThreads), MinresWArgs{w, v, w1, w2, eps_old, delta, inv_gamma, x, phi, n});
 }
 
 }  // namespace vts

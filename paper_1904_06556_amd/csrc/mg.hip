@@ -343,8 +343,17 @@ __global__ void __launch_bounds__(kThreads) k_elem_stencil(Level<T> L) {
 // ---------------------------------------------------------------------------
 // partial sums of acol . z
 template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_acol_dot(Level<T> L, const T* __restrict__ z, double* partials) {
+struct AcolDotArgs {
+    Level<T> L;
+    const T* z;
+    double* partials;
+};
+
+template <typename T>
+__device__ __forceinline__ void acol_dot_body(const AcolDotArgs<T>& a_) {
+    const Level<T>& L = a_.L;
+    const T* const z = a_.z;
+    double* const partials = a_.partials;
     double acc = 0.0;
     for (int64_t q = gidx(); q < 3 * L.nn; q += (int64_t)gridDim.x * blockDim.x)
         acc += (double)L.acol[q] * (double)z[q];
@@ -357,6 +366,8 @@ k_acol_dot(Level<T> L, const T* __restrict__ z, double* partials) {
     }
     if (threadIdx.x == 0) partials[SL_AUX * kRedBlocks + blockIdx.x] = sh[0];
 }
+
+VTS_KERNEL_PAIR(template <typename T>, kThreads, k_acol_dot, AcolDotArgs<T>, acol_dot_body<T>)
 
 // The alpha step of k_alpha_fin inside another kernel, by the first kThreads
 // threads of the block (every thread of the block must call it: it holds
@@ -386,9 +397,27 @@ __device__ __forceinline__ T alpha_residual(const double* __restrict__ parts, in
 // (mode 0: z_a += (r_a - acol.z - d z_a)/d) or the alpha residual
 // (mode 1: res_a = r_a - acol.z - d z_a).
 template <typename T>
-__global__ void k_alpha_fin(const double* __restrict__ partials, int nb, int64_t nn, double d,
-                            const T* __restrict__ r, T* __restrict__ z, T* __restrict__ res,
-                            int mode) {
+struct AlphaFinArgs {
+    const double* partials;
+    int nb;
+    int64_t nn;
+    double d;
+    const T* r;
+    T* z;
+    T* res;
+    int mode;
+};
+
+template <typename T>
+__device__ __forceinline__ void alpha_fin_body(const AlphaFinArgs<T>& a_) {
+    const double* const partials = a_.partials;
+    const int nb = a_.nb;
+    const int64_t nn = a_.nn;
+    const double d = a_.d;
+    const T* const r = a_.r;
+    T* const z = a_.z;
+    T* const res = a_.res;
+    const int mode = a_.mode;
     __shared__ double sh[kThreads];
     double x = 0.0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) x += partials[SL_AUX * kRedBlocks + b];
@@ -409,6 +438,8 @@ __global__ void k_alpha_fin(const double* __restrict__ partials, int nb, int64_t
     }
 }
 
+VTS_KERNEL_PAIR(template <typename T>, kThreads, k_alpha_fin, AlphaFinArgs<T>, alpha_fin_body<T>)
+
 // ---------------------------------------------------------------------------
 // transfers (Section 6.2): trilinear prolongation P, restriction P^T,
 // identity on alpha
@@ -418,9 +449,27 @@ __global__ void k_alpha_fin(const double* __restrict__ partials, int nb, int64_t
 // (block 0, from the nb partial sums parts of acol . z of the residual kernel) and
 // becomes the coarse alpha entry.
 template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_restrict(Level<T> F, Level<T> C, const T* __restrict__ rf, T* __restrict__ rc, int with_alpha,
-           const double* __restrict__ parts, int nb, double d) {
+struct RestrictArgs {
+    Level<T> F;
+    Level<T> C;
+    const T* rf;
+    T* rc;
+    int with_alpha;
+    const double* parts;
+    int nb;
+    double d;
+};
+
+template <typename T>
+__device__ __forceinline__ void restrict_body(const RestrictArgs<T>& a_) {
+    const Level<T>& F = a_.F;
+    const Level<T>& C = a_.C;
+    const T* const rf = a_.rf;
+    T* const rc = a_.rc;
+    const int with_alpha = a_.with_alpha;
+    const double* const parts = a_.parts;
+    const int nb = a_.nb;
+    const double d = a_.d;
     __shared__ double sh[kThreads];
     if (nb > 0 && blockIdx.x == 0) {
         const T v = alpha_residual<T>(parts, nb, d, F.r[3 * F.nn], F.z[3 * F.nn], sh);
@@ -460,9 +509,22 @@ k_restrict(Level<T> F, Level<T> C, const T* __restrict__ rf, T* __restrict__ rc,
     if (with_alpha && nb <= 0 && N == 0) rc[3 * C.nn] = rf[3 * F.nn];
 }
 
+VTS_KERNEL_PAIR(template <typename T>, kThreads, k_restrict, RestrictArgs<T>, restrict_body<T>)
+
 template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_prolong_add(Level<T> C, Level<T> F, const T* __restrict__ zc, T* __restrict__ zf) {
+struct ProlongArgs {
+    Level<T> C;
+    Level<T> F;
+    const T* zc;
+    T* zf;
+};
+
+template <typename T>
+__device__ __forceinline__ void prolong_add_body(const ProlongArgs<T>& a_) {
+    const Level<T>& C = a_.C;
+    const Level<T>& F = a_.F;
+    const T* const zc = a_.zc;
+    T* const zf = a_.zf;
     const int64_t n = gidx();
     if (n >= F.nn) return;
     const int i = (int)(n % F.NX);
@@ -489,6 +551,8 @@ k_prolong_add(Level<T> C, Level<T> F, const T* __restrict__ zc, T* __restrict__ 
     if (!F.fixed[3 * n + 2]) zf[3 * n + 2] += a2;
     if (n == 0) zf[3 * F.nn] += zc[3 * C.nn];
 }
+
+VTS_KERNEL_PAIR(template <typename T>, kThreads, k_prolong_add, ProlongArgs<T>, prolong_add_body<T>)
 
 // ---------------------------------------------------------------------------
 // coarsest level: dense S_1 on (free DOFs, alpha), Cholesky, solve (FP64)
@@ -564,9 +628,23 @@ __global__ void __launch_bounds__(1024) k_cholesky(double* __restrict__ A, int n
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024)
-k_coarse_solve(const double* __restrict__ A, int nc, const int* __restrict__ cmap, int64_t nn,
-               const T* __restrict__ r, T* __restrict__ z) {
+struct CoarseSolveArgs {
+    const double* A;
+    int nc;
+    const int* cmap;
+    int64_t nn;
+    const T* r;
+    T* z;
+};
+
+template <typename T>
+__device__ __forceinline__ void coarse_solve_body(const CoarseSolveArgs<T>& a_) {
+    const double* const A = a_.A;
+    const int nc = a_.nc;
+    const int* const cmap = a_.cmap;
+    const int64_t nn = a_.nn;
+    const T* const r = a_.r;
+    T* const z = a_.z;
     __shared__ double x[kMaxCoarse];
     for (int64_t q = threadIdx.x; q < 3 * nn; q += blockDim.x) {
         const int c = cmap[q];
@@ -594,6 +672,8 @@ k_coarse_solve(const double* __restrict__ A, int nc, const int* __restrict__ cma
     }
     if (threadIdx.x == 0) z[3 * nn] = (T)x[nc - 1];
 }
+
+VTS_KERNEL_PAIR(template <typename T>, 1024, k_coarse_solve, CoarseSolveArgs<T>, coarse_solve_body<T>)
 
 
 // ---------------------------------------------------------------------------
@@ -631,8 +711,15 @@ __device__ __forceinline__ void first_colour(const Level<T>& L, int64_t N, int i
 
 // finest level: r (FP64 S-vector) into the level's precision, then the first colour
 template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_top_init(Level<T> L, const double* __restrict__ rin) {
+struct TopInitArgs {
+    Level<T> L;
+    const double* rin;
+};
+
+template <typename T>
+__device__ __forceinline__ void top_init_body(const TopInitArgs<T>& a_) {
+    const Level<T>& L = a_.L;
+    const double* const rin = a_.rin;
     const int64_t N = gidx();
     if (N < L.nn) {
         const int i = (int)(N % L.NX);
@@ -650,12 +737,28 @@ k_top_init(Level<T> L, const double* __restrict__ rin) {
     }
 }
 
+VTS_KERNEL_PAIR(template <typename T>, kThreads, k_top_init, TopInitArgs<T>, top_init_body<T>)
+
 // restriction P^T of the parent's residual (alpha by identity), then the
 // child's first colour
 template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_restrict_init(Level<T> F, Level<T> C, const T* __restrict__ rf,
-                const double* __restrict__ parts, int nb, double d) {
+struct RestrictInitArgs {
+    Level<T> F;
+    Level<T> C;
+    const T* rf;
+    const double* parts;
+    int nb;
+    double d;
+};
+
+template <typename T>
+__device__ __forceinline__ void restrict_init_body(const RestrictInitArgs<T>& a_) {
+    const Level<T>& F = a_.F;
+    const Level<T>& C = a_.C;
+    const T* const rf = a_.rf;
+    const double* const parts = a_.parts;
+    const int nb = a_.nb;
+    const double d = a_.d;
     __shared__ double sh[kThreads];
     T va = T(0);
     if (blockIdx.x == 0)
@@ -700,6 +803,8 @@ k_restrict_init(Level<T> F, Level<T> C, const T* __restrict__ rf,
     }
 }
 
+VTS_KERNEL_PAIR(template <typename T>, kThreads, k_restrict_init, RestrictInitArgs<T>, restrict_init_body<T>)
+
 // ---------------------------------------------------------------------------
 // finest level without a stored stencil: one Gauss-Seidel colour pass, eight
 // lanes per node of the colour, lane o for the element at offset o (bit set =
@@ -727,9 +832,25 @@ struct KeRows0 {
 };
 
 template <typename T>
-__global__ void __launch_bounds__(kMfBlock)
-k_gs_mf(Level<T> L, int col, KeRows0<T> K0, const T* __restrict__ r1, const T* __restrict__ w,
-        const T* __restrict__ bc, T* __restrict__ te) {
+struct GsMfArgs {
+    Level<T> L;
+    int col;
+    KeRows0<T> K0;
+    const T* r1;
+    const T* w;
+    const T* bc;
+    T* te;
+};
+
+template <typename T>
+__device__ __forceinline__ void gs_mf_body(const GsMfArgs<T>& a_) {
+    const Level<T>& L = a_.L;
+    const int col = a_.col;
+    const KeRows0<T>& K0 = a_.K0;
+    const T* const r1 = a_.r1;
+    const T* const w = a_.w;
+    const T* const bc = a_.bc;
+    T* const te = a_.te;
     const int64_t g = gidx();
     const uint32_t tl = (uint32_t)(g >> 3);
     const int o = (int)(g & 7);
@@ -813,13 +934,25 @@ k_gs_mf(Level<T> L, int col, KeRows0<T> K0, const T* __restrict__ r1, const T* _
     if (in) te[e] = tv + (bb0 * d0 + bb1 * d1 + bb2 * d2);
 }
 
+VTS_KERNEL_PAIR(template <typename T>, kMfBlock, k_gs_mf, GsMfArgs<T>, gs_mf_body<T>)
+
 // finest level without a stored stencil: r (FP64 S-vector) into T, the first
 // colour (z = D^-1 r on colour-0 nodes, zero elsewhere), and te = b_e^T z_e,
 // written by each element's colour-0 node
 template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_top_init_mf(Level<T> L, const double* __restrict__ rin, const T* __restrict__ bc,
-              T* __restrict__ te) {
+struct TopInitMfArgs {
+    Level<T> L;
+    const double* rin;
+    const T* bc;
+    T* te;
+};
+
+template <typename T>
+__device__ __forceinline__ void top_init_mf_body(const TopInitMfArgs<T>& a_) {
+    const Level<T>& L = a_.L;
+    const double* const rin = a_.rin;
+    const T* const bc = a_.bc;
+    T* const te = a_.te;
     const int64_t N = gidx();
     if (N < L.nn) {
         const int i = (int)(N % L.NX);
@@ -847,6 +980,8 @@ k_top_init_mf(Level<T> L, const double* __restrict__ rin, const T* __restrict__ 
         L.z[3 * L.nn] = T(0);
     }
 }
+
+VTS_KERNEL_PAIR(template <typename T>, kThreads, k_top_init_mf, TopInitMfArgs<T>, top_init_mf_body<T>)
 
 // ---------------------------------------------------------------------------
 // large levels: one colour pass / residual with 9 waves per 64 nodes; wave g
@@ -878,9 +1013,20 @@ __device__ __forceinline__ void row_partial(const Level<T>& L, int64_t t, int i,
 }
 
 // TOP = finest level (a separate instantiation so profiles tell them apart)
-template <typename T, bool TOP>
-__global__ void __launch_bounds__(kBlk9)
-k_gs_color9(Level<T> L, int col, const T* __restrict__ r, T* __restrict__ z) {
+template <typename T>
+struct GsColor9Args {
+    Level<T> L;
+    int col;
+    const T* r;
+    T* z;
+};
+
+template <typename T>
+__device__ __forceinline__ void gs_color9_body(const GsColor9Args<T>& a_) {
+    const Level<T>& L = a_.L;
+    const int col = a_.col;
+    const T* const r = a_.r;
+    T* const z = a_.z;
     __shared__ T part[kRowWaves][3][64];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int64_t cnt = L.coff[col + 1] - L.coff[col];
@@ -931,6 +1077,16 @@ k_gs_color9(Level<T> L, int col, const T* __restrict__ r, T* __restrict__ z) {
     }
 }
 
+// TOP = finest level (a separate instantiation so profiles tell them apart)
+template <typename T, bool TOP>
+__global__ void __launch_bounds__(kBlk9) k_gs_color9(GsColor9Args<T> a) {
+    gs_color9_body<T>(a);
+}
+template <typename T, bool TOP>
+__global__ void __launch_bounds__(kBlk9) k_gs_color9_b(const GsColor9Args<T>* __restrict__ tab) {
+    gs_color9_body<T>(tab[blockIdx.y]);
+}
+
 // res = r - S z (displacement part, masked) and per-block partial sums of
 // acol . z (slot SL_STAT).  First the alpha step that ends the forward sweep,
 // z_a += (r_a - acol.z - d z_a)/d from the nb partial sums of k_acol_dot
@@ -938,10 +1094,26 @@ k_gs_color9(Level<T> L, int col, const T* __restrict__ r, T* __restrict__ z) {
 // block 0 stores it.  The level entered the sweep with z = 0 and the colour
 // passes leave z_a alone, so z_a is 0 before this step and the blocks never
 // read the location block 0 writes.
-template <typename T, bool TOP>
-__global__ void __launch_bounds__(kBlk9)
-k_resid9(Level<T> L, const T* __restrict__ r, T* __restrict__ z, T* __restrict__ res,
-         double* partials, int nb, double d) {
+template <typename T>
+struct Resid9Args {
+    Level<T> L;
+    const T* r;
+    T* z;
+    T* res;
+    double* partials;
+    int nb;
+    double d;
+};
+
+template <typename T>
+__device__ __forceinline__ void resid9_body(const Resid9Args<T>& a_) {
+    const Level<T>& L = a_.L;
+    const T* const r = a_.r;
+    T* const z = a_.z;
+    T* const res = a_.res;
+    double* const partials = a_.partials;
+    const int nb = a_.nb;
+    const double d = a_.d;
     // row partial sums, double-buffered: the buffer of chunk q is rewritten
     // in chunk q + 2, after every wave has passed the barrier of chunk q + 1,
     // which wave 0 reaches only once it has read chunk q's sums
@@ -992,6 +1164,15 @@ k_resid9(Level<T> L, const T* __restrict__ r, T* __restrict__ z, T* __restrict__
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
         if (lane == 0) partials[SL_STAT * kRedBlocks + blockIdx.x] = acc;
     }
+}
+
+template <typename T, bool TOP>
+__global__ void __launch_bounds__(kBlk9) k_resid9(Resid9Args<T> a) {
+    resid9_body<T>(a);
+}
+template <typename T, bool TOP>
+__global__ void __launch_bounds__(kBlk9) k_resid9_b(const Resid9Args<T>* __restrict__ tab) {
+    resid9_body<T>(tab[blockIdx.y]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1199,7 +1380,13 @@ __device__ void blk_prolong(const Level<T>& C, const Level<T>& F, const T* zc, T
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024) k_vcycle_small(SmallArgs<T> a) {
+struct VSmallArgs {
+    SmallArgs<T> a;
+};
+
+template <typename T>
+__device__ __forceinline__ void vcycle_small_body(const VSmallArgs<T>& a_) {
+    const SmallArgs<T>& a = a_.a;
     __shared__ double red[kSmallThreads / 64];
     __shared__ double xs[kSmallCoarse];
     __shared__ SmallShared<T> sh;
@@ -1251,6 +1438,8 @@ __global__ void __launch_bounds__(1024) k_vcycle_small(SmallArgs<T> a) {
     }
 }
 
+VTS_KERNEL_PAIR(template <typename T>, 1024, k_vcycle_small, VSmallArgs<T>, vcycle_small_body<T>)
+
 // column j of the inverse of L L^T (Cholesky factor in A), one block per column
 __global__ void __launch_bounds__(256)
 k_chol_inverse(const double* __restrict__ A, int nc, double* __restrict__ Ainv) {
@@ -1276,9 +1465,28 @@ k_chol_inverse(const double* __restrict__ A, int nc, double* __restrict__ Ainv) 
 }
 
 template <typename Tin, typename Tout>
-__global__ void k_convert(const Tin* __restrict__ a, Tout* __restrict__ b, int64_t n) {
+struct ConvertArgs {
+    const Tin* a;
+    Tout* b;
+    int64_t n;
+};
+
+template <typename Tin, typename Tout>
+__device__ __forceinline__ void convert_body(const ConvertArgs<Tin, Tout>& a_) {
+    const Tin* const a = a_.a;
+    Tout* const b = a_.b;
+    const int64_t n = a_.n;
     const int64_t t = gidx();
     if (t < n) b[t] = (Tout)a[t];
+}
+
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(kThreads) k_convert(ConvertArgs<Tin, Tout> a) {
+    convert_body<Tin, Tout>(a);
+}
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(kThreads) k_convert_b(const ConvertArgs<Tin, Tout>* __restrict__ tab) {
+    convert_body<Tin, Tout>(tab[blockIdx.y]);
 }
 
 template <typename T>
@@ -1326,8 +1534,8 @@ void mg_build(Ctx& c, Hierarchy<T>& H) {
             Level<T>& Lk = H.lev[k];
             hipLaunchKernelGGL(k_elem_stencil<T>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s, Lk);
             hipLaunchKernelGGL(k_restrict<T>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s,
-                               H.lev[k + 1], Lk, H.lev[k + 1].acol, Lk.acol, 0,
-                               (const double*)nullptr, 0, 0.0);
+                               RestrictArgs<T>{H.lev[k + 1], Lk, H.lev[k + 1].acol, Lk.acol, 0,
+                                               (const double*)nullptr, 0, 0.0});
         }
     }
     Level<T>& L0 = H.lev[0];
@@ -1346,6 +1554,12 @@ void mg_build(Ctx& c, Hierarchy<T>& H) {
 // colours 7..0.  On the finest level the colour passes are optionally
 // bracketed by the profiling events of the context (kernel class
 // VTS_PROF_GS_FINE), one event pair per sweep.
+// a launch through vlaunch (issued, or recorded for a group launch)
+template <class A, class K1, class K2>
+static inline void vl(Ctx& c, K1 k, K2 kb, dim3 g, dim3 b, const A& a) {
+    vlaunch(c, reinterpret_cast<const void*>(k), reinterpret_cast<const void*>(kb), g, b, a);
+}
+
 template <typename T>
 static void gs_sweep(Ctx& c, Level<T>& Lk, bool forward, bool top) {
     const bool prof = top && prof_begin(c, VTS_PROF_GS_FINE);
@@ -1356,12 +1570,11 @@ static void gs_sweep(Ctx& c, Level<T>& Lk, bool forward, bool top) {
         const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
         if (cnt == 0) continue;
         const dim3 grid((unsigned)((cnt + 63) / 64));
+        const GsColor9Args<T> a{Lk, col, (const T*)Lk.r, Lk.z};
         if (top)
-            hipLaunchKernelGGL((k_gs_color9<T, true>), grid, dim3(kBlk9), 0, c.s, Lk, col,
-                               (const T*)Lk.r, Lk.z);
+            vl(c, k_gs_color9<T, true>, k_gs_color9_b<T, true>, grid, dim3(kBlk9), a);
         else
-            hipLaunchKernelGGL((k_gs_color9<T, false>), grid, dim3(kBlk9), 0, c.s, Lk, col,
-                               (const T*)Lk.r, Lk.z);
+            vl(c, k_gs_color9<T, false>, k_gs_color9_b<T, false>, grid, dim3(kBlk9), a);
         bytes += gs_color_bytes(Lk, col, sizeof(T));
         ++launches;
     }
@@ -1382,9 +1595,9 @@ static void gs_sweep_mf(Ctx& c, Hierarchy<T>& H, Level<T>& Lk, bool forward) {
         const int col = forward ? q : 7 - q;
         const int64_t cnt = Lk.coff[col + 1] - Lk.coff[col];
         if (cnt == 0) continue;
-        hipLaunchKernelGGL(k_gs_mf<T>, dim3((unsigned)((8 * cnt + kMfBlock - 1) / kMfBlock)),
-                           dim3(kMfBlock), 0, c.s, Lk, col, K0,
-                           (const T*)H.r1f, (const T*)H.wf, (const T*)H.bc, H.te);
+        vl(c, k_gs_mf<T>, k_gs_mf_b<T>, dim3((unsigned)((8 * cnt + kMfBlock - 1) / kMfBlock)),
+           dim3(kMfBlock),
+           GsMfArgs<T>{Lk, col, K0, (const T*)H.r1f, (const T*)H.wf, (const T*)H.bc, H.te});
         bytes += gs_mf_color_bytes(Lk, col, sizeof(T));
         ++launches;
     }
@@ -1395,8 +1608,8 @@ static void gs_sweep_mf(Ctx& c, Hierarchy<T>& H, Level<T>& Lk, bool forward) {
 template <typename T>
 static int acol_partials(Ctx& c, Level<T>& Lk) {
     const int gr = red_grid_of(3 * Lk.nn);
-    hipLaunchKernelGGL(k_acol_dot<T>, dim3(gr), dim3(kThreads), 0, c.s, Lk, (const T*)Lk.z,
-                       c.partials);
+    vl(c, k_acol_dot<T>, k_acol_dot_b<T>, dim3(gr), dim3(kThreads),
+       AcolDotArgs<T>{Lk, (const T*)Lk.z, c.partials});
     return gr;
 }
 
@@ -1404,8 +1617,8 @@ static int acol_partials(Ctx& c, Level<T>& Lk) {
 template <typename T>
 static void alpha_update(Ctx& c, Level<T>& Lk) {
     const int gr = acol_partials(c, Lk);
-    hipLaunchKernelGGL(k_alpha_fin<T>, dim3(1), dim3(kThreads), 0, c.s, c.partials, gr, Lk.nn,
-                       c.sum_w, (const T*)Lk.r, Lk.z, Lk.res, 0);
+    vl(c, k_alpha_fin<T>, k_alpha_fin_b<T>, dim3(1), dim3(kThreads),
+       AlphaFinArgs<T>{c.partials, gr, Lk.nn, c.sum_w, (const T*)Lk.r, Lk.z, Lk.res, 0});
 }
 
 // V-cycle below level k.  On entry a multi-workgroup level (k > ksmall,
@@ -1422,12 +1635,12 @@ static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
         a.Ainv = H.Ainv;
         a.nc = H.nc;
         a.cinv = H.cinv;
-        hipLaunchKernelGGL(k_vcycle_small<T>, dim3(1), dim3(1024), 0, c.s, a);
+        vl(c, k_vcycle_small<T>, k_vcycle_small_b<T>, dim3(1), dim3(1024), VSmallArgs<T>{a});
         return;
     }
     if (k == 0) {
-        hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(1024), 0, c.s, H.A, H.nc, H.cmap,
-                           Lk.nn, Lk.r, Lk.z);
+        vl(c, k_coarse_solve<T>, k_coarse_solve_b<T>, dim3(1), dim3(1024),
+           CoarseSolveArgs<T>{H.A, H.nc, H.cmap, Lk.nn, Lk.r, Lk.z});
         return;
     }
     const double d = c.sum_w;
@@ -1442,14 +1655,14 @@ static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
         const int nbr = fine_resid_blocks(c);
         Level<T>& Lc = H.lev[k - 1];
         if (k - 1 <= H.ksmall || k - 1 == 0)
-            hipLaunchKernelGGL(k_restrict<T>, dim3(grid_of(Lc.nn)), dim3(kThreads), 0, c.s, Lk, Lc,
-                               (const T*)Lk.res, Lc.r, 1, (const double*)c.spart, nbr, d);
+            vl(c, k_restrict<T>, k_restrict_b<T>, dim3(grid_of(Lc.nn)), dim3(kThreads),
+               RestrictArgs<T>{Lk, Lc, (const T*)Lk.res, Lc.r, 1, (const double*)c.spart, nbr, d});
         else
-            hipLaunchKernelGGL(k_restrict_init<T>, dim3(grid_of(Lc.nn)), dim3(kThreads), 0, c.s, Lk,
-                               Lc, (const T*)Lk.res, (const double*)c.spart, nbr, d);
+            vl(c, k_restrict_init<T>, k_restrict_init_b<T>, dim3(grid_of(Lc.nn)), dim3(kThreads),
+               RestrictInitArgs<T>{Lk, Lc, (const T*)Lk.res, (const double*)c.spart, nbr, d});
         vcycle_level(c, H, k - 1);
-        hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s, Lc, Lk,
-                           (const T*)Lc.z, Lk.z);
+        vl(c, k_prolong_add<T>, k_prolong_add_b<T>, dim3(grid_of(Lk.nn)), dim3(kThreads),
+           ProlongArgs<T>{Lc, Lk, (const T*)Lc.z, Lk.z});
         launch_fine_tdot<T>(c, Lk, H.uf, H.r1f, H.wf, H.te);
         alpha_update(c, Lk);
         gs_sweep_mf(c, H, Lk, false);
@@ -1462,24 +1675,23 @@ static void vcycle_level(Ctx& c, Hierarchy<T>& H, int k) {
     // correction; prolongation
     int64_t chunks = (Lk.nn + 63) / 64;
     const int grr = (int)(chunks < kRedBlocks ? chunks : kRedBlocks);
+    const Resid9Args<T> ra{Lk, (const T*)Lk.r, Lk.z, Lk.res, c.partials, gr, d};
     if (top)
-        hipLaunchKernelGGL((k_resid9<T, true>), dim3(grr), dim3(kBlk9), 0, c.s, Lk, (const T*)Lk.r,
-                           Lk.z, Lk.res, c.partials, gr, d);
+        vl(c, k_resid9<T, true>, k_resid9_b<T, true>, dim3(grr), dim3(kBlk9), ra);
     else
-        hipLaunchKernelGGL((k_resid9<T, false>), dim3(grr), dim3(kBlk9), 0, c.s, Lk, (const T*)Lk.r,
-                           Lk.z, Lk.res, c.partials, gr, d);
+        vl(c, k_resid9<T, false>, k_resid9_b<T, false>, dim3(grr), dim3(kBlk9), ra);
     Level<T>& Lc = H.lev[k - 1];
     if (k - 1 <= H.ksmall || k - 1 == 0)
-        hipLaunchKernelGGL(k_restrict<T>, dim3(grid_of(Lc.nn)), dim3(kThreads), 0, c.s, Lk, Lc,
-                           (const T*)Lk.res, Lc.r, 1,
-                           (const double*)c.partials + SL_STAT * kRedBlocks, grr, d);
+        vl(c, k_restrict<T>, k_restrict_b<T>, dim3(grid_of(Lc.nn)), dim3(kThreads),
+           RestrictArgs<T>{Lk, Lc, (const T*)Lk.res, Lc.r, 1,
+                           (const double*)c.partials + SL_STAT * kRedBlocks, grr, d});
     else
-        hipLaunchKernelGGL(k_restrict_init<T>, dim3(grid_of(Lc.nn)), dim3(kThreads), 0, c.s, Lk,
-                           Lc, (const T*)Lk.res, (const double*)c.partials + SL_STAT * kRedBlocks,
-                           grr, d);
+        vl(c, k_restrict_init<T>, k_restrict_init_b<T>, dim3(grid_of(Lc.nn)), dim3(kThreads),
+           RestrictInitArgs<T>{Lk, Lc, (const T*)Lk.res,
+                               (const double*)c.partials + SL_STAT * kRedBlocks, grr, d});
     vcycle_level(c, H, k - 1);
-    hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s, Lc, Lk,
-                       (const T*)Lc.z, Lk.z);
+    vl(c, k_prolong_add<T>, k_prolong_add_b<T>, dim3(grid_of(Lk.nn)), dim3(kThreads),
+       ProlongArgs<T>{Lc, Lk, (const T*)Lc.z, Lk.z});
     // backward sweep: alpha, then colours 7..0
     alpha_update(c, Lk);
     gs_sweep(c, Lk, false, top);
@@ -1491,17 +1703,17 @@ void mg_vcycle(Ctx& c, Hierarchy<T>& H, const double* r, double* z) {
     Level<T>& fine = H.lev[L - 1];
     const int64_t nv = 3 * fine.nn + 1;
     if (L - 1 <= H.ksmall || L == 1)
-        hipLaunchKernelGGL((k_convert<double, T>), dim3(grid_of(nv)), dim3(kThreads), 0, c.s, r,
-                           fine.r, nv);
+        vl(c, k_convert<double, T>, k_convert_b<double, T>, dim3(grid_of(nv)), dim3(kThreads),
+           ConvertArgs<double, T>{r, fine.r, nv});
     else if (H.mf)
-        hipLaunchKernelGGL(k_top_init_mf<T>, dim3(grid_of(fine.nn)), dim3(kThreads), 0, c.s, fine,
-                           r, (const T*)H.bc, H.te);
+        vl(c, k_top_init_mf<T>, k_top_init_mf_b<T>, dim3(grid_of(fine.nn)), dim3(kThreads),
+           TopInitMfArgs<T>{fine, r, (const T*)H.bc, H.te});
     else
-        hipLaunchKernelGGL(k_top_init<T>, dim3(grid_of(fine.nn)), dim3(kThreads), 0, c.s, fine,
-                           r);
+        vl(c, k_top_init<T>, k_top_init_b<T>, dim3(grid_of(fine.nn)), dim3(kThreads),
+           TopInitArgs<T>{fine, r});
     vcycle_level(c, H, L - 1);
-    hipLaunchKernelGGL((k_convert<T, double>), dim3(grid_of(nv)), dim3(kThreads), 0, c.s,
-                       (const T*)fine.z, z, nv);
+    vl(c, k_convert<T, double>, k_convert_b<T, double>, dim3(grid_of(nv)), dim3(kThreads),
+       ConvertArgs<T, double>{(const T*)fine.z, z, nv});
 }
 
 template <typename T>

@@ -519,12 +519,36 @@ __device__ __forceinline__ void s_step(SMarch<T>& M, const PlaneGeom& g, const K
 // The march over (x, u) for the S-apply (S_APPLY), the finest-level residual
 // of the V-cycle (S_RESID: x = z, beta = z_alpha, r_in = r) and the element
 // products b_e^T x_e (S_TDOT).  beta is x[ndof].
+template <typename T>
+struct SPlaneArgs {
+    PlaneGeom g;
+    KhVals<T> kh;
+    const T* x;
+    const T* u;
+    const T* r1;
+    const T* w;
+    const uint8_t* nmask;
+    int64_t ndof;
+    const T* r_in;
+    T* y;
+    T* te;
+    double* partials;
+};
+
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kTileThreads)
-k_S_plane(PlaneGeom g, KhVals<T> kh, const T* __restrict__ x, const T* __restrict__ u,
-          const T* __restrict__ r1, const T* __restrict__ w, const uint8_t* __restrict__ nmask,
-          int64_t ndof, const T* __restrict__ r_in, T* __restrict__ y, T* __restrict__ te,
-          double* __restrict__ partials) {
+__device__ __forceinline__ void s_plane_body(const SPlaneArgs<T>& a) {
+    const PlaneGeom g = a.g;
+    const KhVals<T> kh = a.kh;
+    const T* __restrict__ x = a.x;
+    const T* __restrict__ u = a.u;
+    const T* __restrict__ r1 = a.r1;
+    const T* __restrict__ w = a.w;
+    const uint8_t* __restrict__ nmask = a.nmask;
+    const int64_t ndof = a.ndof;
+    const T* __restrict__ r_in = a.r_in;
+    T* __restrict__ y = a.y;
+    T* __restrict__ te = a.te;
+    double* __restrict__ partials = a.partials;
     __shared__ T rx[kRing][kPV];
     __shared__ T ru[kRing][kPV];
     __shared__ uint8_t mring[kRing][kPN];
@@ -606,18 +630,41 @@ k_S_plane(PlaneGeom g, KhVals<T> kh, const T* __restrict__ x, const T* __restric
     }
 }
 
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kTileThreads) k_S_plane(SPlaneArgs<T> a) {
+    s_plane_body<T, MODE>(a);
+}
+
+// the same for problem blockIdx.y of a group launch
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kTileThreads) k_S_plane_b(const SPlaneArgs<T>* __restrict__ tab) {
+    s_plane_body<T, MODE>(tab[blockIdx.y]);
+}
+
 // deterministic sum of nb partials into dst (negated: the alpha row of S)
-__global__ void k_sum_neg(const double* __restrict__ partials, int nb, double* __restrict__ dst) {
+struct SumNegArgs {
+    const double* partials;
+    int nb;
+    double* dst;
+};
+__device__ __forceinline__ void sum_neg_body(const SumNegArgs& a) {
     __shared__ double sh[256];
     double s = 0.0;
-    for (int q = threadIdx.x; q < nb; q += blockDim.x) s += partials[q];
+    for (int q = threadIdx.x; q < a.nb; q += blockDim.x) s += a.partials[q];
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
         if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) dst[0] = -sh[0];
+    if (threadIdx.x == 0) a.dst[0] = -sh[0];
+}
+VTS_KERNEL_PAIR(, 256, k_sum_neg, SumNegArgs, sum_neg_body)
+
+template <typename T, int MODE>
+void launch_s_plane(Ctx& c, dim3 grid, const SPlaneArgs<T>& a) {
+    vlaunch(c, (const void*)&k_S_plane<T, MODE>, (const void*)&k_S_plane_b<T, MODE>, grid,
+            dim3(kTileThreads), a);
 }
 
 PlaneGeom plane_geom(const Ctx& c, int zblocks) {
@@ -673,10 +720,12 @@ void launch_apply_S_tile_ws(Ctx& c, const double* x, double* y, double* partials
     const PlaneGeom g = plane_geom(c, choose_zblocks(c));
     const KhVals<double> kh{c.kh8[0], c.kh8[1], c.kh8[2], c.kh8[3],
                             c.kh8[4], c.kh8[5], c.kh8[6], c.kh8[7]};
-    hipLaunchKernelGGL((k_S_plane<double, S_APPLY>), dim3(8 * g.per_xcd), dim3(kTileThreads), 0,
-                       c.s, g, kh, x, c.u, c.r1, c.w, c.nmask, c.ndof, (const double*)nullptr, y,
-                       (double*)nullptr, partials);
-    hipLaunchKernelGGL(k_sum_neg, dim3(1), dim3(256), 0, c.s, partials, g.nblocks, y + c.ndof);
+    launch_s_plane<double, S_APPLY>(
+        c, dim3(8 * g.per_xcd),
+        SPlaneArgs<double>{g, kh, x, c.u, c.r1, c.w, c.nmask, c.ndof, (const double*)nullptr, y,
+                           (double*)nullptr, partials});
+    vlaunch(c, (const void*)&k_sum_neg, (const void*)&k_sum_neg_b, dim3(1), dim3(256),
+            SumNegArgs{partials, g.nblocks, y + c.ndof});
 }
 
 void launch_apply_S_tile(Ctx& c, const double* x, double* y) {
@@ -692,9 +741,9 @@ void launch_fine_resid(Ctx& c, const Level<T>& L, const T* u, const T* r1, const
     const PlaneGeom g = plane_geom(c, choose_zblocks(c));
     const KhVals<T> kh{(T)c.kh8[0], (T)c.kh8[1], (T)c.kh8[2], (T)c.kh8[3],
                        (T)c.kh8[4], (T)c.kh8[5], (T)c.kh8[6], (T)c.kh8[7]};
-    hipLaunchKernelGGL((k_S_plane<T, S_RESID>), dim3(8 * g.per_xcd), dim3(kTileThreads), 0, c.s,
-                       g, kh, (const T*)L.z, u, r1, w, c.nmask, 3 * L.nn, (const T*)L.r, L.res,
-                       (T*)nullptr, parts);
+    launch_s_plane<T, S_RESID>(c, dim3(8 * g.per_xcd),
+                               SPlaneArgs<T>{g, kh, (const T*)L.z, u, r1, w, c.nmask, 3 * L.nn,
+                                             (const T*)L.r, L.res, (T*)nullptr, parts});
 }
 
 template <typename T>
@@ -702,9 +751,10 @@ void launch_fine_tdot(Ctx& c, const Level<T>& L, const T* u, const T* r1, const 
     const PlaneGeom g = plane_geom(c, choose_zblocks(c));
     const KhVals<T> kh{(T)c.kh8[0], (T)c.kh8[1], (T)c.kh8[2], (T)c.kh8[3],
                        (T)c.kh8[4], (T)c.kh8[5], (T)c.kh8[6], (T)c.kh8[7]};
-    hipLaunchKernelGGL((k_S_plane<T, S_TDOT>), dim3(8 * g.per_xcd), dim3(kTileThreads), 0, c.s,
-                       g, kh, (const T*)L.z, u, r1, w, c.nmask, 3 * L.nn, (const T*)nullptr,
-                       (T*)nullptr, te, (double*)nullptr);
+    launch_s_plane<T, S_TDOT>(c, dim3(8 * g.per_xcd),
+                              SPlaneArgs<T>{g, kh, (const T*)L.z, u, r1, w, c.nmask, 3 * L.nn,
+                                            (const T*)nullptr, (T*)nullptr, te,
+                                            (double*)nullptr});
 }
 
 int fine_resid_blocks(const Ctx& c) { return plane_geom(c, choose_zblocks(c)).nblocks; }

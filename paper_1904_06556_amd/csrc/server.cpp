@@ -4,6 +4,10 @@
 // builds the request's context inside its range, runs Algorithm 1 to the
 // request's tolerances, copies rho and u to host memory and returns the
 // range; admitted requests overlap on the device through their streams.
+// The Newton-system MINRES solves of admitted requests with the same grid,
+// levels and precision run together in one group runner per such shape:
+// their smoother, transfer, operator and vector launches go out as one
+// launch per kernel over the group.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -97,6 +101,23 @@ struct vts_server {
     int32_t running = 0;
     int64_t next_id = 1;
     bool stop = false;
+    bool batch = true;
+    std::mutex rmu;
+    std::map<std::string, GroupRunner*> runners;   // one per shape, created on first use
+
+    // the group runner for problems of c's shape (nullptr: run alone)
+    GroupRunner* runner_for(const Ctx& c) {
+        const std::string key = std::to_string(c.prec) + ":" + std::to_string(c.nx) + "x" +
+                                std::to_string(c.ny) + "x" + std::to_string(c.nz) + ":" +
+                                std::to_string(c.L);
+        std::lock_guard<std::mutex> lk(rmu);
+        auto it = runners.find(key);
+        if (it != runners.end()) return it->second;
+        std::string err;
+        GroupRunner* g = group_runner_create(device, err);
+        runners.emplace(key, g);   // nullptr remembered too: that shape runs alone
+        return g;
+    }
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
     double now() const {
@@ -140,6 +161,7 @@ struct vts_server {
             std::string err;
             vts_status st = create_in(&r.pr, &r.opt, s, pool + off, r.footprint, &ctx, err);
             if (st == VTS_OK) {
+                if (batch) ctx->group = runner_for(*ctx);
                 vts_result res{};
                 st = vts_pbm_solve(ctx, &res);
                 in.outer = res.outer;
@@ -159,6 +181,7 @@ struct vts_server {
                 hipError_t e3 = hipStreamSynchronize(s);
                 if ((e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) && st == VTS_OK)
                     st = VTS_EDEVICE;
+                ctx->group = nullptr;
                 vts_destroy(ctx);
             }
             in.status = st;
@@ -277,21 +300,55 @@ vts_status vts_server_fetch(vts_server* S, int64_t id, double* rho_host, double*
 
 vts_status vts_group_step(vts_ctx** ctxs, int32_t k, vts_pbmstats* stats) {
     if (!ctxs || k < 0) return VTS_EINVAL;
-    for (int32_t q = 0; q < k; ++q)
+    for (int32_t q = 0; q < k; ++q) {
         if (!ctxs[q]) return VTS_EINVAL;
+        for (int32_t p = 0; p < q; ++p)
+            if (ctxs[p] == ctxs[q]) return VTS_EINVAL;
+    }
     std::vector<vts_status> st(k, VTS_OK);
     std::vector<std::thread> th;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return VTS_EDEVICE;
+    // one group runner for the call: the contexts' Newton-system MINRES
+    // solves advance together, one launch per kernel for contexts of one shape
+    std::string err;
+    GroupRunner* g = k > 1 ? group_runner_create(dev, err) : nullptr;
+    for (int32_t q = 0; q < k; ++q) ctxs[q]->group = g;
     for (int32_t q = 0; q < k; ++q)
         th.emplace_back([&, q] {
             hipSetDevice(dev);
             st[q] = vts_pbm_iterate(ctxs[q], stats ? &stats[q] : nullptr);
         });
     for (std::thread& t : th) t.join();
+    for (int32_t q = 0; q < k; ++q) ctxs[q]->group = nullptr;
+    group_runner_destroy(g);
     for (int32_t q = 0; q < k; ++q)
         if (st[q] != VTS_OK) return st[q];
     return VTS_OK;
+}
+
+vts_status vts_server_batching(vts_server* S, int32_t on) {
+    if (!S) return VTS_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->next_id != 1) return VTS_ESTATE;   // only before the first submit
+    S->batch = on != 0;
+    return VTS_OK;
+}
+
+void vts_server_group_stats(vts_server* S, int64_t out[5]) {
+    if (!S || !out) return;
+    for (int q = 0; q < 5; ++q) out[q] = 0;
+    std::lock_guard<std::mutex> lk(S->rmu);
+    for (auto& kv : S->runners) {
+        if (!kv.second) continue;
+        GroupStats gs;
+        group_runner_stats(kv.second, &gs);
+        out[0] += gs.cycles;
+        out[1] += gs.solves;
+        out[2] += gs.kernel_ops;
+        out[3] += gs.launches;
+        out[4] = std::max(out[4], gs.max_batch);
+    }
 }
 
 double vts_server_clock(const vts_server* S) { return S ? S->now() : 0.0; }
@@ -314,6 +371,7 @@ void vts_server_destroy(vts_server* S) {
     }
     S->cv_work.notify_all();
     for (std::thread& t : S->workers) t.join();
+    for (auto& kv : S->runners) group_runner_destroy(kv.second);
     for (hipStream_t s : S->streams) hipStreamDestroy(s);
     hipFree(S->pool);
     delete S;

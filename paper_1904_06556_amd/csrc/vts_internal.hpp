@@ -39,6 +39,47 @@ struct Level {
     T* res;
 };
 
+// Device operations of one context recorded instead of issued: a group of
+// contexts with the same launch sequence then runs each recorded launch as
+// one launch over all of them (problem = blockIdx.y, arguments from a table).
+struct RecOp {
+    const void* kb = nullptr;   // batched kernel: takes const Args* table
+    dim3 grid, block;
+    uint32_t asize = 0;         // bytes of the argument struct (0: a copy)
+    size_t aoff = 0;            // offset of the argument bytes in Recorder::bytes
+    void* dst = nullptr;        // copy
+    const void* src = nullptr;
+    size_t nbytes = 0;
+    hipMemcpyKind kind = hipMemcpyDeviceToDevice;
+};
+
+struct Recorder {
+    std::vector<RecOp> ops;
+    std::vector<uint8_t> bytes;
+    void clear() {
+        ops.clear();
+        bytes.clear();
+    }
+    void kernel(const void* kb, dim3 g, dim3 b, const void* args, uint32_t n) {
+        RecOp o;
+        o.kb = kb;
+        o.grid = g;
+        o.block = b;
+        o.asize = n;
+        o.aoff = bytes.size();
+        bytes.insert(bytes.end(), (const uint8_t*)args, (const uint8_t*)args + n);
+        ops.push_back(o);
+    }
+    void copy(void* dst, const void* src, size_t n, hipMemcpyKind k) {
+        RecOp o;
+        o.dst = dst;
+        o.src = src;
+        o.nbytes = n;
+        o.kind = k;
+        ops.push_back(o);
+    }
+};
+
 template <typename T>
 struct Hierarchy {
     std::vector<Level<T>> lev;   // 0 = coarsest
@@ -71,6 +112,8 @@ struct Ctx {
     int prec;
     vts_options opt;
     hipStream_t s = nullptr;
+    Recorder* rec = nullptr;        // non-null: device operations are recorded (group solves)
+    struct GroupRunner* group = nullptr;  // non-null: Newton-system MINRES runs in this group
     int device = 0;
 
     // constants (device)
@@ -196,6 +239,76 @@ vts_status create_in(const vts_problem* pr, const vts_options* opt, void* stream
                      size_t arena_bytes, vts_ctx** out, std::string& err);
 
 // profiling hooks (capi.cpp); prof_begin returns true if this launch is timed
+// A kernel and its batched twin from one device body: NAME(ARGS a) runs
+// BODY(a); NAME_b(const ARGS* tab) runs BODY(tab[blockIdx.y]), problem
+// blockIdx.y of a group launch (its blockIdx.x, gridDim.x as alone).
+#define VTS_KERNEL_PAIR(TPL, BOUNDS, NAME, ARGS, BODY)                                      \
+    TPL __global__ void __launch_bounds__(BOUNDS) NAME(ARGS a) { BODY(a); }                 \
+    TPL __global__ void __launch_bounds__(BOUNDS) NAME##_b(const ARGS* __restrict__ tab) {   \
+        BODY(tab[blockIdx.y]);                                                              \
+    }
+
+// One kernel launch with its arguments in a struct: issued on c.s, or
+// recorded (with the batched twin kb) while c.rec is set.
+template <class A>
+inline void vlaunch(Ctx& c, const void* k, const void* kb, dim3 g, dim3 b, const A& a) {
+    if (c.rec) {
+        c.rec->kernel(kb, g, b, &a, (uint32_t)sizeof(A));
+        return;
+    }
+    void* args[] = {const_cast<A*>(&a)};
+    (void)hipLaunchKernel(k, g, b, args, 0, c.s);
+}
+
+inline hipError_t vmemcpy(Ctx& c, void* dst, const void* src, size_t n, hipMemcpyKind kind) {
+    if (c.rec) {
+        c.rec->copy(dst, src, n, kind);
+        return hipSuccess;
+    }
+    return hipMemcpyAsync(dst, src, n, kind, c.s);
+}
+
+// Preconditioned MINRES as steps between synchronizations (capi.cpp)
+struct MrState {
+    enum Phase { kStart, kIterate, kFinish, kDone };
+    double eps = 0;
+    int maxit = 0;
+    bool stop_indef = false;
+    int64_t n = 0;
+    double *x = nullptr, *r1 = nullptr, *r2 = nullptr, *y = nullptr, *v = nullptr;
+    double* wb[3] = {nullptr, nullptr, nullptr};
+    int iw = 0, iw1 = 1, iw2 = 2;
+    double beta1 = 0, beta = 0, beta_old = 0, cs = -1, sn = 0, dbar = 0, eps_l = 0, phibar = 0;
+    double rel = 0;
+    int it = 0;
+    Phase phase = kStart;
+    vts_status st = VTS_OK;
+};
+void mr_init(Ctx& c, MrState& m, double eps, int maxit, bool stop_indef);
+void mr_issue_start(Ctx& c, MrState& m);
+void mr_after_start(Ctx& c, MrState& m);
+void mr_issue_iter(Ctx& c, MrState& m);
+void mr_after_iter(Ctx& c, MrState& m);
+void mr_finish(Ctx& c, MrState& m, vts_linstats* out);
+
+// Group runner (group.cpp): a thread with its own stream that advances the
+// MINRES solves handed to it one step at a time, all of them together; the
+// device work of solves with the same launch sequence goes out as one launch
+// per kernel over all of them.  Solves join and leave between steps.
+struct GroupRunner;
+struct GroupStats {
+    int64_t cycles = 0;          // synchronized steps
+    int64_t solves = 0;          // MINRES solves completed
+    int64_t kernel_ops = 0;      // kernel launches the solves recorded
+    int64_t launches = 0;        // launches issued for them
+    int64_t max_batch = 0;       // largest number of solves in one launch
+};
+GroupRunner* group_runner_create(int device, std::string& err);
+void group_runner_destroy(GroupRunner* g);
+void group_runner_stats(const GroupRunner* g, GroupStats* out);
+// MINRES of c's Newton system through c.group (blocks the calling thread)
+vts_status group_minres(Ctx& c, double eps, vts_linstats* out, int maxit);
+
 bool prof_begin(Ctx& c, int cls);
 void prof_end(Ctx& c, double bytes, int launches = 1);
 

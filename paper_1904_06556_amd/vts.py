@@ -162,6 +162,8 @@ SIGNATURES = {
     "vts_server_poll": (C.c_int32, [_P, C.POINTER(RequestInfo_t), C.c_int32, C.c_double]),
     "vts_server_fetch": (C.c_int, [_P, C.c_int64, _P, _P]),
     "vts_server_clock": (C.c_double, [_P]),
+    "vts_server_batching": (C.c_int, [_P, C.c_int32]),
+    "vts_server_group_stats": (None, [_P, C.POINTER(C.c_int64)]),
     "vts_server_counts": (None, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                  C.POINTER(C.c_int32)]),
     "vts_server_destroy": (None, [_P]),
@@ -502,12 +504,23 @@ class Server:
     of hbm_bytes, `slots` workers with one stream each, admission by
     footprint."""
 
-    def __init__(self, slots: int, hbm_bytes: int):
+    def __init__(self, slots: int, hbm_bytes: int, batching: bool = True):
         h_ = C.c_void_p()
         st = lib().vts_server_create(int(slots), int(hbm_bytes), C.byref(h_))
         if st != VTS_OK:
             raise VtsError(st, "vts_server_create")
         self.h = h_
+        if not batching:
+            st = lib().vts_server_batching(self.h, 0)
+            if st != VTS_OK:
+                raise VtsError(st, "vts_server_batching")
+
+    def group_stats(self):
+        """Counters of the same-shape MINRES group runners (summed)."""
+        a = (C.c_int64 * 5)()
+        lib().vts_server_group_stats(self.h, a)
+        return dict(steps=a[0], solves=a[1], kernel_ops=a[2], launches=a[3], max_batch=a[4],
+                    mean_batch=(a[2] / a[3]) if a[3] else None)
 
     def submit(self, pr, precision=None, options: Optional[Options_t] = None) -> int:
         if precision is None:

@@ -133,3 +133,50 @@ def test_fetch_before_poll():
         srv.fetch(ids[0], probs[0].m, probs[0].n_dof)
     srv.fetch(ids[1], probs[1].m, probs[1].n_dof)
     srv.close()
+
+
+def test_same_shape_requests_share_launches_and_match_unbatched():
+    # four requests of one grid (two loads, two volumes) admitted together:
+    # their MINRES steps go out as shared launches, and every result is
+    # bitwise the one the server gives with batching off
+    probs = [W.cantilever_edge(16, 8, 8, 3, vol_frac=0.25), W.bridge_top(16, 8, 8, 3, vol_frac=0.2, h=0.25),
+             W.cantilever_edge(16, 8, 8, 3, vol_frac=0.35), W.bridge_top(16, 8, 8, 3, vol_frac=0.3, h=0.25)]
+    runs = {}
+    for batching in (False, True):
+        say("same-shape requests, batching", batching)
+        srv = V.Server(4, 1 << 30, batching=batching)
+        runs[batching] = serve.run_stream(srv, [(0.0, p) for p in probs], precision=V.VTS_MIXED,
+                                          keep_fields=True)
+        stats = srv.group_stats()
+        srv.close()
+        say("  group stats", stats)
+        if batching:
+            assert stats["solves"] > 0 and stats["max_batch"] >= 2
+            assert stats["mean_batch"] > 1.0
+        else:
+            assert stats["launches"] == 0
+    for a, b in zip(runs[False], runs[True]):
+        assert a["status"] == V.VTS_OK and b["status"] == V.VTS_OK
+        assert (a["outer"], a["newton"], a["minres"]) == (b["outer"], b["newton"], b["minres"])
+        assert a["compliance"] == b["compliance"]
+        assert np.array_equal(a["rho"], b["rho"]) and np.array_equal(a["u"], b["u"])
+
+
+def test_group_step_batches_a_same_shape_pair_bitwise():
+    # vts_group_step with two contexts of one shape and one of another
+    probs = [W.cantilever_edge(32, 16, 16, 4, vol_frac=0.15),
+             W.bridge_top(32, 16, 16, 4, vol_frac=0.25, h=0.125),
+             W.cantilever_edge(16, 8, 8, 3, vol_frac=0.3)]
+    streams = [torch.cuda.Stream() for _ in probs]
+    grouped = [V.Context.from_problem(p, precision=V.VTS_MIXED, stream=s)
+               for p, s in zip(probs, streams)]
+    single = [V.Context.from_problem(p, precision=V.VTS_MIXED) for p in probs]
+    for it in range(4):
+        say("group step (same-shape pair)", it)
+        gs = V.group_step(grouped)
+        for k, c in enumerate(single):
+            assert c.pbm_iterate() == gs[k]
+    for g, c in zip(grouped, single):
+        assert np.array_equal(g.get_state(), c.get_state())
+        g.close()
+        c.close()
