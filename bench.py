@@ -94,6 +94,9 @@ def parse():
                     help="--serve: arrival rates as multiples of 1 / mean alone service time")
     ap.add_argument("--t-alone", type=float, default=None,
                     help="--serve: mean alone service time to use (default: measured)")
+    ap.add_argument("--burst", type=int, default=None,
+                    help="--serve: --requests requests of serving grid index BURST at once, "
+                         "batching on and off")
     ap.add_argument("--no-batching", action="store_true",
                     help="--serve: each request's launches on its own stream")
     ap.add_argument("--slots", type=int, default=4, help="concurrent requests (--serve)")
@@ -706,7 +709,9 @@ def serving(a, torch, W, V):
     from paper_1904_06556_amd import serve
     # serving policy: a penalty floor and outer budget that also carry the
     # larger bridges to KKT 1e-6
-    opts = V.default_options(p_min=2e-3, max_outer=300)
+    opts = V.default_options(p_min=3e-3, max_outer=500)
+    if a.burst is not None:
+        return serving_burst(a, torch, W, V, opts)
     base = W.serving_requests(a.requests, rate=1.0, seed=0)
     probs = [p for _, p in base]
     n_alone = min(8, len(probs))
@@ -749,6 +754,53 @@ def serving(a, torch, W, V):
         "mean_service_alone_s": t_alone, "rates": rates,
         "mix_equals_alone": bool(same),
     }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def serving_burst(a, torch, W, V, opts):
+    """--burst G: a.requests requests of serving grid G (cantilever edge and
+    bridge face loads, V/m ~ U[0.1, 0.4]) all submitted at once, served by
+    a.slots workers with batching on and then off: time until the last
+    result, and the group runners' mean batch."""
+    from paper_1904_06556_amd import serve
+    nx, ny, nz, l = W.SERVING_GRIDS[a.burst]
+    rng = np.random.default_rng(1)
+    probs = []
+    for k in range(a.requests):
+        frac = float(rng.uniform(0.1, 0.4))
+        probs.append(W.cantilever_edge(nx, ny, nz, l, vol_frac=frac) if k % 2 == 0 else
+                     W.bridge_top(nx, ny, nz, l, vol_frac=frac, h=2.0 ** (1 - l)))
+    pool = int(a.pool_gb * (1 << 30))
+    out, results = {}, {}
+    for batching in (True, False):
+        srv = V.Server(a.slots, pool, batching=batching)
+        t0 = time.perf_counter()
+        recs = serve.run_stream(srv, [(0.0, p) for p in probs], precision=V.VTS_MIXED,
+                                options=opts, keep_fields=True)
+        wall = time.perf_counter() - t0
+        g = srv.group_stats()
+        srv.close()
+        lat = np.array([r["latency"] for r in recs])
+        key = "batching" if batching else "no_batching"
+        out[key] = dict(wall_s=wall, solves_per_s=len(recs) / wall,
+                        ok=int(sum(r["status"] == V.VTS_OK for r in recs)),
+                        p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                        group_stats=g if batching else None)
+        results[key] = recs
+        print(f"burst {key}: {json.dumps(out[key])}", file=sys.stderr, flush=True)
+    same = all(x["compliance"] == y["compliance"] and np.array_equal(x["rho"], y["rho"])
+               for x, y in zip(results["batching"], results["no_batching"]))
+    line = {"metric": METRIC, "value": out["batching"]["solves_per_s"],
+            "unit": "VTS solves/s (burst of same-grid requests, batching on)",
+            "n_gpus": 1, "steps": a.requests, "warmup": 0,
+            "ms_per_step": 1e3 * out["batching"]["wall_s"] / a.requests,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64+f32mg", "data": "synthetic",
+            "config": {"workload": f"burst of {a.requests} requests on {nx}x{ny}x{nz} l{l}",
+                       "slots": a.slots, "precision": "mixed", "p_min": opts.p_min},
+            "burst": out, "batched_equals_unbatched": bool(same),
+            "speedup": out["no_batching"]["wall_s"] / out["batching"]["wall_s"]}
     print(json.dumps(line), flush=True)
     return 0
 

@@ -112,6 +112,17 @@ def test_stored_benchmark_oracle_run_is_certified():
     assert abs(g["compliance_half_fu"] - g["compliance_exact"]) <= 1e-6 * g["compliance_exact"]
     assert g["kkt"] <= 1e-6
     assert abs(g["sum_rho"] - g["V"]) <= 1e-6 * g["V"]
+    # the stored iteration record is that of the totals, and its last outer
+    # iteration met the outer tests of the options it was run with
+    o = g["options"]
+    assert len(g["outer_log"]) == g["outer"] and len(g["newton_log"]) == g["newton"]
+    assert sum(d["minres"] for d in g["newton_log"]) == g["minres"]
+    last = g["outer_log"][-1]
+    assert last["ratio"] < o["eps_pbm"] and last["stat"] < o["eps_stat"]
+    assert all(d["ratio"] >= o["eps_pbm"] or d["stat"] >= o["eps_stat"]
+               for d in g["outer_log"][:-1])
+    # the final Newton call (Algorithm 1, last step) met its tolerance
+    assert g["newton_log"][-1]["res"] <= o["eps_nwt_final"]
 
 
 def test_paper_parameters_reach_the_paper_accuracy():
