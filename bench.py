@@ -400,6 +400,7 @@ def run_pbm_capped(torch, V, ctx, name, label, cap_s, max_outer):
     else:
         st = ctx.state_dict()
         res.update(outer=int(st["outer"]), newton=int(st["newton"]), minres=int(st["minres"]))
+    print(f"{name} [{label}] result: {json.dumps(res)}", file=sys.stderr, flush=True)
     return res
 
 

@@ -103,10 +103,12 @@ typedef struct {
     int32_t max_outer, max_newton, max_minres;
     int32_t final_res4;           /* final Newton also requires the res_4 term */
     int32_t p_min_relative;       /* 1: floors p_min |alpha|, q_min |alpha|; 0: p_min, q_min */
-    int32_t stall_steps;          /* final Newton stops after this many steps without a new best
-                                     criterion below 0.9 x the best (0: never); then the
-                                     accept_stall rule decides (the paper accepts stalled
-                                     near-optimal points, Section 7.2).  Also ends the outer loop
+    int32_t stall_steps;          /* a Newton call stops after this many steps without a new best
+                                     criterion below 0.9 x the best (0: never).  A call before
+                                     the final one that stalls is taken as the minimizer and the
+                                     outer loop goes on; a stalled final call goes to the KKT
+                                     check (kkt_tol) or the accept_stall rule (the paper accepts
+                                     stalled near-optimal points, Section 7.2).  Also ends the outer loop
                                      once the gap test holds and the stationarity term (eps_stat)
                                      has gone this many outer iterations without a new value
                                      below 0.9 x its best; the final Newton call and kkt_tol then

@@ -423,9 +423,9 @@ class Solver:
     def newton(self, st: State, eps_nwt: float, final=False):
         """Algorithm 2.  The MINRES tolerance rule of Section 6.2 compares
         res_PBM of consecutive steps of this call.  Status "newton_limit" if
-        max_newton steps do not meet eps_nwt; in the final call also
-        "stalled" once stall_steps steps in a row bring no new best value
-        below 0.9 times the best so far."""
+        max_newton steps do not meet eps_nwt; "stalled" once stall_steps
+        steps in a row bring no new best value below 0.9 times the best so
+        far (the outer loop accepts a stalled call before the final one)."""
         P, o = self.P, self.opts
         ev = evaluate(P, st)
         self.res_prev = None
@@ -478,7 +478,7 @@ class Solver:
                 best, since = crit, 0
             else:
                 since += 1
-            if final and o.stall_steps > 0 and since >= o.stall_steps:
+            if o.stall_steps > 0 and since >= o.stall_steps:
                 self.status = "stalled"
                 return st, ev
         else:
@@ -493,6 +493,11 @@ class Solver:
         stat_best, stat_since = 0.0, -1
         for k in range(o.max_outer):
             st, ev = self.newton(st, eps_nwt)
+            if self.status == "stalled":
+                # a call before the final one that stalls is taken as the
+                # minimizer (the rounding floor of res_PBM lies above its
+                # tolerance); the multiplier update and the tests go on
+                self.status = "ok"
             delta = duality_gap(P, st, ev.e)
             d = dual_objective(P, st)
             ratio = abs(delta / d)

@@ -663,13 +663,17 @@ vts_status newton(Ctx& c, double eps_nwt, bool final_call, vts_newtonstats* last
         } else {
             ++since;
         }
-        if (final_call && c.opt.stall_steps > 0 && since >= c.opt.stall_steps) {
+        if (c.opt.stall_steps > 0 && since >= c.opt.stall_steps) {
             stalled = true;
             break;
         }
     }
     if (last) *last = ns;
     if (its) *its = k + (st == VTS_OK ? 1 : 0);
+    // a call before the last one that stalls is taken as the minimizer (the
+    // rounding floor of res_PBM lies above its tolerance); the outer loop's
+    // multiplier update and tests go on from there
+    if (st == VTS_OK && stalled && !final_call) return VTS_OK;
     if (st == VTS_OK && stalled) {
         c.err = "Newton stalled";
         return VTS_ENOTCONV;
