@@ -109,10 +109,10 @@ typedef struct {
                                      outer loop goes on; a stalled final call goes to the KKT
                                      check (kkt_tol) or the accept_stall rule (the paper accepts
                                      stalled near-optimal points, Section 7.2).  Also ends the outer loop
-                                     once the gap test holds and the stationarity term (eps_stat)
-                                     has gone this many outer iterations without a new value
-                                     below 0.9 x its best; the final Newton call and kkt_tol then
-                                     decide */
+                                     once the gap test holds and the stationarity term, below
+                                     10 x eps_stat, has gone this many outer iterations without a
+                                     new value below 0.9 x its best; the final Newton call and
+                                     kkt_tol then decide */
     int32_t use_graphs;           /* 1: replay each V-cycle from a captured HIP graph (the
                                      same kernels and arguments, bitwise equal results;
                                      recaptured after every multigrid setup; contexts built

@@ -509,11 +509,13 @@ class Solver:
             if self.progress is not None:
                 self.progress(k, self.log.outer[-1])
             stat_ok = stat < (o.eps_stat or 1.0)
-            if ratio < o.eps_pbm and not stat_ok and o.stall_steps > 0:
+            if ratio < o.eps_pbm and not stat_ok and o.stall_steps > 0 and \
+                    stat < 10.0 * (o.eps_stat or 1.0):
                 # the stationarity test is an addition to Algorithm 1's gap test:
-                # once the gap test holds and the term stops decreasing (no new
-                # value below 0.9 x its best for stall_steps outer iterations),
-                # the loop ends and the final Newton call and the KKT check decide
+                # once the gap test holds and the term, within 10x of its target,
+                # stops decreasing (no new value below 0.9 x its best for
+                # stall_steps outer iterations), the loop ends and the final
+                # Newton call and the KKT check decide
                 if stat_since < 0 or stat < 0.9 * stat_best:
                     stat_best, stat_since = stat, 0
                 else:

@@ -703,10 +703,11 @@ vts_status pbm_iterate(Ctx& c, vts_pbmstats* out) {
     c.outer += 1;
     const bool gap_ok = ratio < c.opt.eps_pbm;
     bool stat_ok = c.opt.eps_stat <= 0 || stat < c.opt.eps_stat;
-    if (gap_ok && !stat_ok && c.opt.stall_steps > 0) {
+    if (gap_ok && !stat_ok && c.opt.stall_steps > 0 && stat < 10.0 * c.opt.eps_stat) {
         // the stationarity term is this library's addition to the gap test;
-        // once the gap test holds and the term stops decreasing, the outer
-        // loop ends and the final Newton call and the KKT check decide
+        // once the gap test holds and the term, within 10x of its target,
+        // stops decreasing, the outer loop ends and the final Newton call
+        // and the KKT check decide
         if (c.stat_since < 0 || stat < 0.9 * c.stat_best) {
             c.stat_best = stat;
             c.stat_since = 0;

@@ -21,7 +21,8 @@ def run_stream(server: "V.Server", requests: Sequence[Tuple[float, object]],
                on_done: Optional[Callable[[dict], None]] = None,
                keep_fields: bool = False) -> List[dict]:
     """Submits request r at its arrival time (seconds after the first call)
-    and collects every result.  Returns one record per request in arrival
+    and collects every result.  options: one vts_options for all requests,
+    or a function of the problem that returns its options.  Returns one record per request in arrival
     order: id, arrival, status, latency (= done - arrival), service (= done -
     admit), queue (= admit - arrival), iteration counts, compliance and sizes;
     with keep_fields also the final rho and u."""
@@ -33,7 +34,9 @@ def run_stream(server: "V.Server", requests: Sequence[Tuple[float, object]],
         now = server.clock() - t_base
         while nxt < len(order) and requests[order[nxt]][0] <= now:
             k = order[nxt]
-            rid = server.submit(requests[k][1], precision=precision, options=options)
+            pr = requests[k][1]
+            rid = server.submit(pr, precision=precision,
+                                options=options(pr) if callable(options) else options)
             by_id[rid] = k
             nxt += 1
         wait = (requests[order[nxt]][0] - now) if nxt < len(order) else 1.0
