@@ -12,6 +12,7 @@
 // between steps.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -53,7 +54,8 @@ struct GroupRunner {
     uint8_t* host_stage = nullptr;   // pinned
     uint8_t* dev_stage = nullptr;
     size_t cap = 0;
-    GroupStats stats;
+    GroupStats stats;    // published under mu
+    GroupStats step;     // this step's counts (runner thread only)
 
     bool grow(size_t need, std::string& err) {
         if (need <= cap) return true;
@@ -137,9 +139,9 @@ struct GroupRunner {
                         err = "group runner: launch failed";
                         return false;
                     }
-                    stats.kernel_ops += B;
-                    stats.launches += 1;
-                    if ((int64_t)B > stats.max_batch) stats.max_batch = B;
+                    step.kernel_ops += B;
+                    step.launches += 1;
+                    if ((int64_t)B > step.max_batch) step.max_batch = B;
                 } else {
                     for (Job* j : g) {
                         const RecOp& oc = j->rec.ops[q];
@@ -201,14 +203,14 @@ struct GroupRunner {
                 finish_all(active, VTS_EDEVICE, err);
                 continue;
             }
-            ++stats.cycles;
+            ++step.cycles;
             // read the step's reductions; the next step's leading work is recorded
             std::vector<Job*> left, ended;
             for (Job* j : active) {
                 Ctx& c = *j->c;
                 j->rec.clear();
                 if (j->finishing) {
-                    ++stats.solves;
+                    ++step.solves;
                     ended.push_back(j);
                     continue;
                 }
@@ -224,6 +226,15 @@ struct GroupRunner {
                     left.push_back(j);
             }
             active.swap(left);
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                stats.cycles += step.cycles;
+                stats.solves += step.solves;
+                stats.kernel_ops += step.kernel_ops;
+                stats.launches += step.launches;
+                stats.max_batch = std::max(stats.max_batch, step.max_batch);
+            }
+            step = GroupStats{};
             if (!ended.empty()) finish_all(ended, VTS_OK, std::string());
         }
     }
@@ -265,8 +276,10 @@ void group_runner_destroy(GroupRunner* g) {
     delete g;
 }
 
-void group_runner_stats(const GroupRunner* g, GroupStats* out) {
-    if (g && out) *out = g->stats;
+void group_runner_stats(GroupRunner* g, GroupStats* out) {
+    if (!g || !out) return;
+    std::lock_guard<std::mutex> lk(g->mu);
+    *out = g->stats;
 }
 
 vts_status group_minres(Ctx& c, double eps, vts_linstats* out, int maxit) {

@@ -305,7 +305,7 @@ struct GroupStats {
 };
 GroupRunner* group_runner_create(int device, std::string& err);
 void group_runner_destroy(GroupRunner* g);
-void group_runner_stats(const GroupRunner* g, GroupStats* out);
+void group_runner_stats(GroupRunner* g, GroupStats* out);   // thread-safe
 // MINRES of c's Newton system through c.group (blocks the calling thread)
 vts_status group_minres(Ctx& c, double eps, vts_linstats* out, int maxit);
 
