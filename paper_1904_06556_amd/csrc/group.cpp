@@ -95,10 +95,13 @@ struct GroupRunner {
         std::map<std::string, std::vector<Job*>> groups;
         for (Job* j : jobs)
             if (!j->rec.ops.empty()) groups[signature(j->rec)].push_back(j);
-        // tables: for each group, for each kernel op, the members' argument structs
+        // tables: for each group of two or more, for each kernel op, the
+        // members' argument structs (a group of one launches the single-problem
+        // kernels with the recorded arguments: no table, no copy)
         size_t total = 0;
         for (auto& kv : groups) {
             const std::vector<Job*>& g = kv.second;
+            if (g.size() < 2) continue;
             for (const RecOp& o : g[0]->rec.ops)
                 if (o.kb) total += (o.asize * g.size() + kTableAlign - 1) / kTableAlign * kTableAlign;
         }
@@ -107,6 +110,7 @@ struct GroupRunner {
         std::vector<size_t> offs;
         for (auto& kv : groups) {
             const std::vector<Job*>& g = kv.second;
+            if (g.size() < 2) continue;
             const std::vector<RecOp>& ops = g[0]->rec.ops;
             for (size_t q = 0; q < ops.size(); ++q) {
                 if (!ops[q].kb) continue;
@@ -131,7 +135,16 @@ struct GroupRunner {
             const unsigned B = (unsigned)g.size();
             for (size_t q = 0; q < ops.size(); ++q) {
                 const RecOp& o = ops[q];
-                if (o.kb) {
+                if (o.kb && B == 1) {
+                    void* args[] = {(void*)(g[0]->rec.bytes.data() + o.aoff)};
+                    if (hipLaunchKernel(o.k, o.grid, o.block, args, 0, s) != hipSuccess) {
+                        err = "group runner: launch failed";
+                        return false;
+                    }
+                    step.kernel_ops += 1;
+                    step.launches += 1;
+                    if (step.max_batch < 1) step.max_batch = 1;
+                } else if (o.kb) {
                     const void* tab = dev_stage + offs[t++];
                     void* args[] = {(void*)&tab};
                     if (hipLaunchKernel(o.kb, dim3(o.grid.x, B, 1), o.block, args, 0, s) !=

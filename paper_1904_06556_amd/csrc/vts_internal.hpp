@@ -43,6 +43,7 @@ struct Level {
 // contexts with the same launch sequence then runs each recorded launch as
 // one launch over all of them (problem = blockIdx.y, arguments from a table).
 struct RecOp {
+    const void* k = nullptr;    // single-problem kernel: takes Args by value
     const void* kb = nullptr;   // batched kernel: takes const Args* table
     dim3 grid, block;
     uint32_t asize = 0;         // bytes of the argument struct (0: a copy)
@@ -60,8 +61,9 @@ struct Recorder {
         ops.clear();
         bytes.clear();
     }
-    void kernel(const void* kb, dim3 g, dim3 b, const void* args, uint32_t n) {
+    void kernel(const void* k, const void* kb, dim3 g, dim3 b, const void* args, uint32_t n) {
         RecOp o;
+        o.k = k;
         o.kb = kb;
         o.grid = g;
         o.block = b;
@@ -253,7 +255,7 @@ vts_status create_in(const vts_problem* pr, const vts_options* opt, void* stream
 template <class A>
 inline void vlaunch(Ctx& c, const void* k, const void* kb, dim3 g, dim3 b, const A& a) {
     if (c.rec) {
-        c.rec->kernel(kb, g, b, &a, (uint32_t)sizeof(A));
+        c.rec->kernel(k, kb, g, b, &a, (uint32_t)sizeof(A));
         return;
     }
     void* args[] = {const_cast<A*>(&a)};
