@@ -764,6 +764,35 @@ def serving(a, torch, W, V):
     return 0
 
 
+def burst_problems(W, grid, n):
+    """n requests of serving grid `grid` (loads alternating, V/m ~ U[0.1, 0.4], seed 1)."""
+    nx, ny, nz, l = W.SERVING_GRIDS[grid]
+    rng = np.random.default_rng(1)
+    probs = []
+    for k in range(n):
+        frac = float(rng.uniform(0.1, 0.4))
+        probs.append(W.cantilever_edge(nx, ny, nz, l, vol_frac=frac) if k % 2 == 0 else
+                     W.bridge_top(nx, ny, nz, l, vol_frac=frac, h=2.0 ** (1 - l)))
+    return probs
+
+
+def burst_once(V, serve, probs, slots, pool, batching, opts):
+    """All of probs submitted at once to a server; latency percentiles,
+    throughput and the group runners' counters."""
+    srv = V.Server(slots, pool, batching=batching)
+    t0 = time.perf_counter()
+    recs = serve.run_stream(srv, [(0.0, p) for p in probs], precision=V.VTS_MIXED,
+                            options=opts, keep_fields=True)
+    wall = time.perf_counter() - t0
+    g = srv.group_stats()
+    srv.close()
+    lat = np.array([r["latency"] for r in recs])
+    return recs, dict(wall_s=wall, solves_per_s=len(recs) / wall,
+                      ok=int(sum(r["status"] == V.VTS_OK for r in recs)),
+                      p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                      group_stats=g if batching else None)
+
+
 def serving_burst(a, torch, W, V, opts):
     """--burst G: a.requests requests of serving grid G (cantilever edge and
     bridge face loads, V/m ~ U[0.1, 0.4]) all submitted at once, served by
@@ -771,29 +800,12 @@ def serving_burst(a, torch, W, V, opts):
     result, and the group runners' mean batch."""
     from paper_1904_06556_amd import serve
     nx, ny, nz, l = W.SERVING_GRIDS[a.burst]
-    rng = np.random.default_rng(1)
-    probs = []
-    for k in range(a.requests):
-        frac = float(rng.uniform(0.1, 0.4))
-        probs.append(W.cantilever_edge(nx, ny, nz, l, vol_frac=frac) if k % 2 == 0 else
-                     W.bridge_top(nx, ny, nz, l, vol_frac=frac, h=2.0 ** (1 - l)))
+    probs = burst_problems(W, a.burst, a.requests)
     pool = int(a.pool_gb * (1 << 30))
     out, results = {}, {}
     for batching in (True, False):
-        srv = V.Server(a.slots, pool, batching=batching)
-        t0 = time.perf_counter()
-        recs = serve.run_stream(srv, [(0.0, p) for p in probs], precision=V.VTS_MIXED,
-                                options=opts, keep_fields=True)
-        wall = time.perf_counter() - t0
-        g = srv.group_stats()
-        srv.close()
-        lat = np.array([r["latency"] for r in recs])
         key = "batching" if batching else "no_batching"
-        out[key] = dict(wall_s=wall, solves_per_s=len(recs) / wall,
-                        ok=int(sum(r["status"] == V.VTS_OK for r in recs)),
-                        p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
-                        group_stats=g if batching else None)
-        results[key] = recs
+        results[key], out[key] = burst_once(V, serve, probs, a.slots, pool, batching, opts)
         print(f"burst {key}: {json.dumps(out[key])}", file=sys.stderr, flush=True)
     same = all(x["compliance"] == y["compliance"] and np.array_equal(x["rho"], y["rho"])
                for x, y in zip(results["batching"], results["no_batching"]))
@@ -1104,6 +1116,15 @@ def headline(a, torch, W, V):
         "time_to_kkt_cant-64x32x32": ttk,
         "mixed_over_fp64_time_to_kkt": ttk["mixed"]["seconds"] / ttk["fp64"]["seconds"],
     }
+    # serving latency: a burst of 32 requests of the 16x8x8 serving grid
+    # through the request loop, 16 slots, batching on
+    from paper_1904_06556_amd import serve
+    sopts = V.default_options(max_outer=500)
+    _, sb = burst_once(V, serve, burst_problems(W, 0, 32), 16, 4 << 30, True,
+                       lambda p: V.default_options(p_min=5e-3, max_outer=500)
+                       if p.name.startswith("bridge") else sopts)
+    line["serving_burst_32x16x8x8"] = sb
+    print(f"serving burst: {json.dumps(sb)}", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_k_apply(pr, a.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -137,6 +137,16 @@ typedef struct {
                                      iterate (the dual solution of problem (2.2)) is the
                                      displacement that meets the optimality conditions.
                                      Default 1e-10 */
+    const char* log_path;         /* NULL (default): no log.  Otherwise a file to which the
+                                     context appends one JSON object per line: every Newton
+                                     step of Algorithm 2 ("newton": outer index, step, res_PBM,
+                                     res_4, Armijo step, slope, MINRES tolerance and count),
+                                     every outer iteration of Algorithm 1 ("outer": gap ratio,
+                                     stationarity, eps_NWT, sum of rho, Newton and MINRES
+                                     counts, stop) and every vts_pbm_solve result ("result").
+                                     The string is copied at vts_create; the file is opened on
+                                     the first line and closed by vts_destroy.  A file that
+                                     cannot be opened disables the log (the solve goes on). */
 } vts_options;
 
 typedef struct {

@@ -4,6 +4,8 @@
 // mg.hip; the host only reads the scalars that decide the next branch.
 #include <hip/hip_runtime.h>
 
+#include <cstdarg>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -644,6 +646,24 @@ vts_status newton_step(Ctx& c, vts_newtonstats* out, bool final_call) {
     return VTS_OK;
 }
 
+// one line of the context's JSON-lines log (no-op without a log path)
+void log_line(Ctx& c, const char* fmt, ...) {
+    if (c.log_path.empty()) return;
+    if (!c.log) {
+        c.log = std::fopen(c.log_path.c_str(), "a");
+        if (!c.log) {
+            c.log_path.clear();   // cannot be opened: no log
+            return;
+        }
+    }
+    va_list ap;
+    va_start(ap, fmt);
+    std::vfprintf(c.log, fmt, ap);
+    va_end(ap);
+    std::fputc('\n', c.log);
+    std::fflush(c.log);
+}
+
 vts_status newton(Ctx& c, double eps_nwt, bool final_call, vts_newtonstats* last, int* its) {
     c.res_prev = -1.0;
     vts_newtonstats ns{};
@@ -655,6 +675,12 @@ vts_status newton(Ctx& c, double eps_nwt, bool final_call, vts_newtonstats* last
     for (k = 0; k < c.opt.max_newton; ++k) {
         st = newton_step(c, &ns, final_call);
         if (st != VTS_OK) break;
+        log_line(c,
+                 "{\"event\": \"newton\", \"outer\": %d, \"final\": %d, \"step\": %d, "
+                 "\"res_pbm\": %.17g, \"res4\": %.17g, \"kappa\": %.17g, \"slope\": %.17g, "
+                 "\"eps_mr\": %.17g, \"minres\": %d}",
+                 c.outer, final_call ? 1 : 0, k, ns.res_pbm, ns.res4, ns.kappa, ns.slope,
+                 ns.eps_mr, ns.minres_its);
         const double crit = (final_call && c.opt.final_res4) ? ns.res_pbm + ns.res4 : ns.res_pbm;
         if (crit < eps_nwt) break;
         if (crit < 0.9 * best) {
@@ -716,6 +742,12 @@ vts_status pbm_iterate(Ctx& c, vts_pbmstats* out) {
         }
     }
     const bool stop = gap_ok && stat_ok;
+    log_line(c,
+             "{\"event\": \"outer\", \"outer\": %d, \"ratio\": %.17g, \"gap\": %.17g, "
+             "\"stat\": %.17g, \"eps_nwt\": %.17g, \"sum_rho\": %.17g, \"newton\": %d, "
+             "\"minres\": %d, \"stop\": %d}",
+             c.outer, ratio, gap, stat, c.eps_nwt, r[SL_SUM_RHO], nits, c.minres_total - mr0,
+             stop ? 1 : 0);
     if (out) {
         out->gap = gap;
         out->dual = dual;
@@ -970,6 +1002,9 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
     c.E = pr->E; c.nu = pr->nu; c.h = pr->h; c.V = pr->V;
     c.prec = pr->precision;
     if (opt) c.opt = *opt; else vts_default_options(&c.opt);
+    // the log path is the caller's string: keep a copy, not the pointer
+    c.log_path = c.opt.log_path ? c.opt.log_path : "";
+    c.opt.log_path = nullptr;
     c.s = (hipStream_t)stream;
 
     HostData hd;
@@ -1053,6 +1088,8 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
 }
 
 void ctx_free(Ctx& c) {
+    if (c.log) fclose(c.log);
+    c.log = nullptr;
     if (c.s) hipStreamSynchronize(c.s);
     else hipDeviceSynchronize();
     drop_graphs(c);
@@ -1152,6 +1189,7 @@ void vts_default_options(vts_options* o) {
     o->use_graphs = 0;
     o->kkt_tol = 1e-6;
     o->eps_state = 1e-10;
+    o->log_path = nullptr;
 }
 
 vts_status vts_create(const vts_problem* pr, const vts_options* opt, void* stream, vts_ctx** out) {
@@ -1400,6 +1438,13 @@ vts_status vts_pbm_solve(vts_ctx* cp, vts_result* res) {
         res->r_box = kkt_done ? kk[3] : 0.0;
         res->r_stat = kkt_done ? kk[4] : 0.0;
     }
+    log_line(c,
+             "{\"event\": \"result\", \"status\": %d, \"outer\": %d, \"newton\": %d, "
+             "\"minres\": %d, \"res_pbm\": %.17g, \"kkt\": %.17g, \"r_eq\": %.17g, "
+             "\"r_vol\": %.17g, \"r_box\": %.17g, \"r_stat\": %.17g}",
+             (int)st, c.outer, c.newton_total, c.minres_total, c.res_prev, kkt_done ? kk[0] : 0.0,
+             kkt_done ? kk[1] : 0.0, kkt_done ? kk[2] : 0.0, kkt_done ? kk[3] : 0.0,
+             kkt_done ? kk[4] : 0.0);
     c.status = st;
     return st;
 }

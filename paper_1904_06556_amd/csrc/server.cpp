@@ -36,6 +36,7 @@ struct Request {
     vts_options opt{};
     std::vector<uint8_t> fixed;
     std::vector<double> f, lo, hi;
+    std::string log_path;
     size_t footprint = 0;
     double t_submit = 0.0;
 };
@@ -159,6 +160,7 @@ struct vts_server {
             in.footprint = r.footprint;
             vts_ctx* ctx = nullptr;
             std::string err;
+            if (!r.log_path.empty()) r.opt.log_path = r.log_path.c_str();
             vts_status st = create_in(&r.pr, &r.opt, s, pool + off, r.footprint, &ctx, err);
             if (st == VTS_OK) {
                 if (batch) ctx->group = runner_for(*ctx);
@@ -239,6 +241,10 @@ vts_status vts_server_submit(vts_server* S, const vts_problem* pr, const vts_opt
     Request r;
     r.pr = *pr;
     if (opt) r.opt = *opt; else vts_default_options(&r.opt);
+    if (r.opt.log_path) {
+        r.log_path = r.opt.log_path;   // the caller's string need not outlive the call
+        r.opt.log_path = nullptr;
+    }
     const int64_t nn = (int64_t)(pr->nx + 1) * (pr->ny + 1) * (pr->nz + 1), m =
         (int64_t)pr->nx * pr->ny * pr->nz;
     r.fixed.assign(pr->fixed_host, pr->fixed_host + 3 * nn);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdio>
 #include <string>
 #include <vector>
 
@@ -115,6 +116,8 @@ struct Ctx {
     vts_options opt;
     hipStream_t s = nullptr;
     Recorder* rec = nullptr;        // non-null: device operations are recorded (group solves)
+    std::string log_path;           // JSON-lines log of Newton steps, outer iterations, results
+    FILE* log = nullptr;
     struct GroupRunner* group = nullptr;  // non-null: Newton-system MINRES runs in this group
     int device = 0;
 

@@ -55,7 +55,7 @@ class Options_t(C.Structure):
                 ("max_newton", C.c_int32), ("max_minres", C.c_int32),
                 ("final_res4", C.c_int32), ("p_min_relative", C.c_int32),
                 ("stall_steps", C.c_int32), ("use_graphs", C.c_int32),
-                ("kkt_tol", C.c_double), ("eps_state", C.c_double)]
+                ("kkt_tol", C.c_double), ("eps_state", C.c_double), ("log_path", C.c_char_p)]
 
 
 class LinStats_t(C.Structure):
@@ -194,6 +194,8 @@ def default_options(**overrides) -> Options_t:
     for k, v in overrides.items():
         if k not in names:
             raise KeyError(f"vts_options has no field {k!r}")
+        if k == "log_path" and isinstance(v, str):
+            v = v.encode()
         setattr(o, k, v)
     return o
 
