@@ -16,6 +16,12 @@ Cholesky factorization.
 
 Everything here is assembled sparse linear algebra on the free DOFs: the
 smoother recomputes the full residual r - S z before each colour.
+
+With k load cases (the multi-load extension, `nload` = k) the unknowns are
+the stacked free displacements (u_1, ..., u_k) followed by alpha; the
+prolongation acts on each load case's block as above, and the smoother's
+node block holds the 3k DOFs of a node over all load cases, since the
+rank-one element terms of S couple the load cases.
 """
 from __future__ import annotations
 
@@ -82,29 +88,35 @@ def node_colors(g: fe.Grid) -> np.ndarray:
 
 
 class Level:
-    def __init__(self, grid: fe.Grid, S: sp.csr_matrix):
+    def __init__(self, grid: fe.Grid, S: sp.csr_matrix, nload: int = 1):
         self.grid = grid
         self.S = S.tocsr()
-        self.n = grid.free.size                      # u unknowns on this level
+        self.nload = nload
+        self.n = nload * grid.free.size              # u unknowns on this level
         self._blocks()
 
     def _blocks(self):
-        """Per colour: node list, 3x3 inverse of the free sub-block of S on the
-        node (identity on fixed components), free index per component."""
+        """Per colour: node list, inverse of the free sub-block of S on the
+        node's 3 nload DOFs (identity on fixed components), index of each
+        component in the stacked free vector (-1 if fixed)."""
         g = self.grid
+        nf = g.free.size
         fidx = -np.ones(g.n_dof, dtype=np.int64)
-        fidx[g.free] = np.arange(g.free.size)
+        fidx[g.free] = np.arange(nf)
         col = node_colors(g)
         Sd = self.S
+        nb = 3 * self.nload
         self.colors = []
         for c in range(8):
             nodes = np.nonzero(col == c)[0]
-            comp = fidx[3 * nodes[:, None] + np.arange(3)[None, :]]   # k x 3
+            comp1 = fidx[3 * nodes[:, None] + np.arange(3)[None, :]]   # k x 3
+            comp = np.concatenate([np.where(comp1 >= 0, comp1 + l * nf, -1)
+                                   for l in range(self.nload)], axis=1)
             keep = (comp >= 0).any(axis=1)
             nodes, comp = nodes[keep], comp[keep]
-            D = np.zeros((nodes.size, 3, 3))
-            for a in range(3):
-                for b in range(3):
+            D = np.zeros((nodes.size, nb, nb))
+            for a in range(nb):
+                for b in range(nb):
                     ok = (comp[:, a] >= 0) & (comp[:, b] >= 0)
                     ia, ib = comp[ok, a], comp[ok, b]
                     D[ok, a, b] = np.asarray(Sd[ia, ib]).ravel()
@@ -142,9 +154,10 @@ class Level:
 
 
 class Hierarchy:
-    """Levels k = 1..L (index 0 = coarsest) for S on the grid `fine`."""
+    """Levels k = 1..L (index 0 = coarsest) for S on the grid `fine`, with
+    `nload` stacked load cases."""
 
-    def __init__(self, fine: fe.Grid, S: sp.csr_matrix, L: int):
+    def __init__(self, fine: fe.Grid, S: sp.csr_matrix, L: int, nload: int = 1):
         grids = [fine]
         for _ in range(L - 1):
             g = grids[-1]
@@ -159,12 +172,12 @@ class Hierarchy:
             if not check_nested(Pa, grids[k], grids[k - 1]):
                 raise ValueError("fixed DOFs are not nested across levels")
             Pf = Pa[grids[k].free][:, grids[k - 1].free]
-            self.P.append(sp.block_diag([Pf, sp.identity(1)], format="csr"))
+            self.P.append(sp.block_diag([Pf] * nload + [sp.identity(1)], format="csr"))
         Ss = [None] * L
         Ss[L - 1] = S.tocsr()
         for k in range(L - 1, 0, -1):
             Ss[k - 1] = (self.P[k].T @ Ss[k] @ self.P[k]).tocsr()
-        self.levels = [Level(grids[k], Ss[k]) for k in range(L)]
+        self.levels = [Level(grids[k], Ss[k], nload) for k in range(L)]
         self.chol = sla.cho_factor(Ss[0].toarray(), lower=True)
 
     def vcycle(self, r, k=None):

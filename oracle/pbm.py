@@ -393,11 +393,25 @@ class Log:
 
 class Solver:
     """Oracle PBM solver.  `linsolve(S, rhs, eps)` may be replaced (tests use
-    a direct solve); the default is MINRES preconditioned by one V-cycle."""
+    a direct solve); the default is MINRES preconditioned by one V-cycle.
+
+    The problem-specific steps (evaluation, Schur matrix, right-hand side,
+    gap, the split of a Newton solution, the final checks) are the class
+    attributes and small methods below; the multi-load solver replaces them
+    and keeps Algorithms 1 and 2 as written here."""
+
+    problem_class = VTS
+    evaluate = staticmethod(evaluate)
+    schur_matrix = staticmethod(schur_matrix)
+    reduced_rhs = staticmethod(reduced_rhs)
+    lagrangian_change = staticmethod(lagrangian_change)
+    res_pbm = staticmethod(res_pbm)
+    duality_gap = staticmethod(duality_gap)
+    dual_objective = staticmethod(dual_objective)
 
     def __init__(self, problem, opts: Optional[Options] = None, linsolve=None):
         from . import mg, minres
-        self.P = VTS(problem)
+        self.P = self.problem_class(problem)
         self.opts = opts or Options()
         self.levels_count = problem.levels
         self.mg = mg
@@ -415,10 +429,46 @@ class Solver:
     def linsolve(self, ev, S, rhs):
         if self._linsolve is not None:
             return self._linsolve(S, rhs, self.eps_mr), 0
-        h = self.mg.Hierarchy(self.P.grid, S, self.levels_count)
+        h = self.hierarchy(S)
         x, its, _ = self.minres.minres(lambda v: S @ v, rhs, h.vcycle,
                                        self.eps_mr, self.opts.max_minres)
         return x, its
+
+    def hierarchy(self, S):
+        return self.mg.Hierarchy(self.P.grid, S, self.levels_count)
+
+    def initial(self) -> State:
+        P = self.P
+        return initial_state(P.grid.n_dof, P.grid.m, P.V)
+
+    def split(self, dy):
+        """(du in the all-DOF layout, dalpha) from a solution of (3.13)."""
+        P = self.P
+        du = np.zeros(P.grid.n_dof)
+        du[P.free] = dy[:-1]
+        return du, float(dy[-1])
+
+    def tau(self, ev, du, da):
+        """tau_i = b_i^T du_i - dalpha of eq. (3.14)."""
+        return np.einsum("ei,ei->e", ev.be, du[self.P.grid.dofs]) - da
+
+    def slope(self, ev, du, da, dnl, dnh):
+        """Directional derivative of (3.9) along the Newton direction."""
+        return float(ev.g1 @ du + ev.g2 * da + ev.g3 @ dnl + ev.g4 @ dnh)
+
+    def final_checks(self, st):
+        """The state of the returned density and the KKT residual."""
+        P, o = self.P, self.opts
+        if o.final_state_solve and np.min(P.rho_lo) > 0:
+            # the primal pair of problem (1.1): the state of the returned density
+            # (with a zero lower bound K(rho) may be singular on a void region,
+            # where the state equation leaves u free; the dual iterate is then
+            # the displacement that meets the optimality conditions)
+            from .kkt import solve_state
+            st.u = solve_state(P.grid, P.Ke, st.rho, P.f)
+        from .kkt import kkt_residual
+        return kkt_residual(P.grid, P.Ke, P.f, P.V, P.rho_lo, P.rho_hi, st.rho,
+                            st.u, st.alpha)
 
     def newton(self, st: State, eps_nwt: float, final=False):
         """Algorithm 2.  The MINRES tolerance rule of Section 6.2 compares
@@ -427,21 +477,19 @@ class Solver:
         steps in a row bring no new best value below 0.9 times the best so
         far (the outer loop accepts a stalled call before the final one)."""
         P, o = self.P, self.opts
-        ev = evaluate(P, st)
+        ev = self.evaluate(P, st)
         self.res_prev = None
         best, since = np.inf, 0
         for it in range(o.max_newton):
-            S = schur_matrix(P, ev)
-            rhs = reduced_rhs(P, ev)
+            S = self.schur_matrix(P, ev)
+            rhs = self.reduced_rhs(P, ev)
             tries = 0
             while True:
                 dy, mr_its = self.linsolve(ev, S, rhs)
-                du = np.zeros(P.grid.n_dof)
-                du[P.free] = dy[:-1]
-                da = float(dy[-1])
-                tau = np.einsum("ei,ei->e", ev.be, du[P.grid.dofs]) - da
+                du, da = self.split(dy)
+                tau = self.tau(ev, du, da)
                 dnl, dnh = delta_nu(ev, tau)
-                slope = float(ev.g1 @ du + ev.g2 * da + ev.g3 @ dnl + ev.g4 @ dnh)
+                slope = self.slope(ev, du, da, dnl, dnh)
                 if slope < 0 or tries >= 1 or self._linsolve is not None:
                     break
                 # a non-descent direction: tighten the MINRES tolerance once
@@ -451,7 +499,7 @@ class Solver:
                 self.status = "nondescent"
                 return st, ev
             kappa = 1.0
-            while lagrangian_change(P, st, ev, du, da, dnl, dnh, kappa) > \
+            while self.lagrangian_change(P, st, ev, du, da, dnl, dnh, kappa) > \
                     o.armijo_c1 * kappa * slope:
                 kappa *= 0.5
                 if kappa < o.armijo_min:
@@ -463,8 +511,8 @@ class Solver:
             new.nu_lo = st.nu_lo + kappa * dnl
             new.nu_hi = st.nu_hi + kappa * dnh
             st = new
-            ev = evaluate(P, st)
-            res = res_pbm(P, ev)
+            ev = self.evaluate(P, st)
+            res = self.res_pbm(P, ev)
             r4 = res4_term(P, ev)
             self.log.newton.append(dict(res=res, res4=r4, kappa=kappa,
                                         minres=mr_its, eps_mr=self.eps_mr))
@@ -488,7 +536,7 @@ class Solver:
     def solve(self, st: Optional[State] = None):
         P, o = self.P, self.opts
         if st is None:
-            st = initial_state(P.grid.n_dof, P.grid.m, P.V)
+            st = self.initial()
         eps_nwt = o.eps_nwt0
         stat_best, stat_since = 0.0, -1
         for k in range(o.max_outer):
@@ -498,8 +546,8 @@ class Solver:
                 # minimizer (the rounding floor of res_PBM lies above its
                 # tolerance); the multiplier update and the tests go on
                 self.status = "ok"
-            delta = duality_gap(P, st, ev.e)
-            d = dual_objective(P, st)
+            delta = self.duality_gap(P, st, ev.e)
+            d = self.dual_objective(P, st)
             ratio = abs(delta / d)
             self.log.outer.append(dict(gap=delta, dual=d, ratio=ratio, eps_nwt=eps_nwt,
                                        sum_rho=float(st.rho.sum())))
@@ -538,16 +586,7 @@ class Solver:
                 self.status = "ok"          # near-optimal stall accepted
             if self.status == "ok" or (stalled and o.kkt_tol > 0):
                 st.rho, _, _ = update_multipliers(st, ev, o.beta, rho_only=True)
-                if o.final_state_solve and np.min(P.rho_lo) > 0:
-                    # the primal pair of problem (1.1): the state of the returned density
-                    # (with a zero lower bound K(rho) may be singular on a void region,
-                    # where the state equation leaves u free; the dual iterate is then
-                    # the displacement that meets the optimality conditions)
-                    from .kkt import solve_state
-                    st.u = solve_state(P.grid, P.Ke, st.rho, P.f)
-                from .kkt import kkt_residual
-                self.kkt = kkt_residual(P.grid, P.Ke, P.f, P.V, P.rho_lo, P.rho_hi, st.rho,
-                                        st.u, st.alpha)
+                self.kkt = self.final_checks(st)
                 if o.kkt_tol > 0:
                     self.status = "ok" if self.kkt["kkt"] <= o.kkt_tol else "kkt"
         else:

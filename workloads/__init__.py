@@ -33,6 +33,7 @@ __all__ = [
     "Problem", "cantilever_edge", "bar_rollers", "cantilever_points", "bridge_top",
     "paper_cantilever", "paper_bridge", "mg_levels", "config",
     "random_rho", "random_vector", "serving_requests", "CONFIGS",
+    "load_cases", "with_load_cases", "cantilever_two_loads", "multi_config",
 ]
 
 
@@ -149,7 +150,65 @@ def cantilever_points(nx, ny, nz, levels, npoints=3, seed=0, V=None,
     pr = Problem(name or f"cant-points-{nx}x{ny}x{nz}-l{levels}", nx, ny, nz,
                  levels, fixed, f, float(V), rho_lo, rho_hi)
     pr.extra["load_nodes_jk"] = picked
+    # the same point loads as separate load cases (the multi-load reading)
+    cases = np.zeros((npoints, fixed.size))
+    for c, (j, k) in enumerate(picked):
+        cases[c, 3 * (nx + (nx + 1) * (j + (ny + 1) * k)) + 2] = -1.0
+    pr.extra["load_cases"] = cases
     return pr
+
+
+def load_cases(pr: Problem) -> np.ndarray:
+    """The load cases of a problem as a (k, n_dof) array: the cases a
+    multi-load problem carries, else its one load f."""
+    cases = pr.extra.get("load_cases")
+    if cases is None:
+        return pr.f[None, :].copy()
+    return np.asarray(cases, dtype=np.float64)
+
+
+def with_load_cases(pr: Problem, cases, name=None) -> Problem:
+    """A copy of `pr` with the given load cases (zeroed at fixed DOFs); its
+    single load f is their sum."""
+    cases = np.array(cases, dtype=np.float64).reshape(-1, pr.n_dof)
+    cases[:, pr.fixed == 1] = 0.0
+    out = Problem(name or pr.name + f"-k{cases.shape[0]}", pr.nx, pr.ny, pr.nz,
+                  pr.levels, pr.fixed.copy(), cases.sum(axis=0), pr.V, pr.rho_lo,
+                  pr.rho_hi, pr.E, pr.nu, pr.h, dict(pr.extra))
+    out.extra["load_cases"] = cases
+    return out
+
+
+def cantilever_two_loads(nx, ny, nz, levels, vol_frac=0.3, rho_lo=1e-3,
+                         rho_hi=1.0, name=None) -> Problem:
+    """Cantilever (face x=0 clamped) with two load cases on its free end:
+    f_z = -1 at every node of the edge (x = nx, z = 0), and f_y = -1 at
+    every node of the edge (x = nx, z = nz)."""
+    pr = cantilever_edge(nx, ny, nz, levels, vol_frac=vol_frac, rho_lo=rho_lo,
+                         rho_hi=rho_hi)
+    i, j, k = _node_grid(nx, ny, nz)
+    second = np.zeros(pr.n_dof)
+    edge = np.nonzero((i == nx) & (k == nz))[0]
+    second[3 * edge + 1] = -1.0
+    return with_load_cases(pr, [pr.f, second],
+                           name or f"cant2load-{nx}x{ny}x{nz}-l{levels}")
+
+
+def multi_config(idx: int) -> Problem:
+    """Multi-load workloads (a sum of compliances over load cases):
+    0: cantilever 16x8x8, 3 levels, the two end-edge load cases, V = 0.3 m
+    1: cantilever 64x32x32, 5 levels, the two end-edge load cases, V = 0.2 m
+    2: cantilever 192x96x96, 6 levels, the three seeded point loads of the
+       benchmark's three-point cantilever as separate load cases, V = 0.1 m
+    """
+    if idx == 0:
+        return cantilever_two_loads(16, 8, 8, 3, vol_frac=0.3, name="cant2load-16x8x8")
+    if idx == 1:
+        return cantilever_two_loads(64, 32, 32, 5, vol_frac=0.2, name="cant2load-64x32x32")
+    if idx == 2:
+        return cantilever_points(192, 96, 96, 6, npoints=3, seed=0, vol_frac=0.1,
+                                 name="cant3case-192x96x96")
+    raise ValueError(idx)
 
 
 def bridge_top(nx, ny, nz, levels, V=None, vol_frac=0.15, rho_lo=1e-3,
