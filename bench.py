@@ -86,6 +86,12 @@ def parse():
                     help="--paper: only the paper's parameters, not the library's")
     ap.add_argument("--library-rho-lo", type=float, default=1e-3,
                     help="--paper: lower bound of rho for the library-option solve")
+    ap.add_argument("--multiload", action="store_true",
+                    help="several load cases: batched K(rho) on the three point-load cases of "
+                         "the 192x96x96 cantilever, the stacked S-apply, V-cycle and MINRES-MG "
+                         "there, and time-to-KKT of the two-case 64x32x32 cantilever")
+    ap.add_argument("--ml-no-solve", action="store_true",
+                    help="--multiload without the time-to-KKT solve (counter passes)")
     ap.add_argument("--scale-kernels", action="store_true",
                     help="the dominant kernels (finest Gauss-Seidel pass, K(rho)x, S-apply) "
                          "timed at each of --levels, FP64 and mixed; one JSON line")
@@ -158,6 +164,13 @@ def operator_source_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
+def multiload_source_hash():
+    """Hash of the multi-load kernels' source."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1904_06556_amd", "csrc", "multiload.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
 def traffic_file(workload_name):
     return os.path.join(ROOT, "profiles", f"traffic_pmc_{workload_name}.md")
 
@@ -178,9 +191,12 @@ def measured_traffic(workload_name, kernel):
             elif "_source_sha256_16 =" in line:
                 k, v = line.split("=")
                 hashes[k.strip()] = v.strip()
-    key, now = (("operator_source_sha256_16", operator_source_hash())
-                if kernel.startswith(("k_apply_K", "k_S_plane"))
-                else ("kernel_source_sha256_16", kernel_source_hash()))
+    if kernel.startswith("k_ml_"):
+        key, now = "multiload_source_sha256_16", multiload_source_hash()
+    elif kernel.startswith(("k_apply_K", "k_S_plane")):
+        key, now = "operator_source_sha256_16", operator_source_hash()
+    else:
+        key, now = "kernel_source_sha256_16", kernel_source_hash()
     return val if (val is not None and hashes.get(key) == now) else None
 
 
@@ -549,6 +565,186 @@ def scaling_kernels(a, torch, W, V):
             "config": {"workload": "cantilever 4*2^(l-1) x 2^l x 2^l, initial Newton point",
                        "levels": a.levels, "reps": a.reps},
             "kernels_by_level": out}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def _timed(torch, fn, reps):
+    """Average milliseconds of fn() over reps calls, HIP events on the
+    current stream (the library's default stream)."""
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def multiload_ttk(torch, W, V, pr2):
+    """Time-to-KKT (FP64) of a multi-load problem from the initial point (the
+    second of two solves), and the KKT residual of the returned state on the
+    device: equilibrium of every case, volume, stationarity with the summed
+    energies."""
+    import numpy as np
+    c2 = V.Context.from_problem(pr2, precision=V.VTS_FP64,
+                                options=V.default_options(eps_mr0=1e-2))
+    c2.pbm_solve()
+    c2.reset()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res = c2.pbm_solve()
+    torch.cuda.synchronize()
+    ttk = time.perf_counter() - t
+    d = c2.state_dict()
+    cases = W.load_cases(pr2)
+    F = np.where(np.tile(pr2.fixed, len(cases)) == 1, 0.0, cases.ravel())
+    u = torch.as_tensor(d["u"], device="cuda")
+    y = torch.empty_like(u)
+    c2.apply_K(u, y)
+    e = torch.empty(pr2.m, dtype=torch.float64, device="cuda")
+    c2.element_energy(u, e)
+    torch.cuda.synchronize()
+    Ft = torch.as_tensor(F, device="cuda")
+    rho = torch.as_tensor(d["rho"], device="cuda")
+    lam = d["alpha"]
+    proj = torch.clamp(rho + (e - lam) / lam, pr2.rho_lo, pr2.rho_hi)
+    r_box = float(torch.clamp(torch.maximum(pr2.rho_lo - rho, rho - pr2.rho_hi), min=0.0).max())
+    kkt = max(float(torch.linalg.norm(y - Ft) / torch.linalg.norm(Ft)),
+              float(abs(rho.sum() - pr2.V) / pr2.V), r_box / pr2.rho_hi,
+              float(((rho - proj).abs() / pr2.rho_hi).max()))
+    c2.close()
+    print(f"time-to-KKT {pr2.name}: {ttk:.2f} s, outer {res['outer']} newton {res['newton']} "
+          f"minres {res['minres']} KKT {kkt:.2e}", file=sys.stderr, flush=True)
+    return {"workload": pr2.name, "seconds": ttk, "outer": res["outer"],
+            "newton": res["newton"], "minres": res["minres"], "kkt": kkt,
+            "status": res["status"], "compliance": res["compliance"]}
+
+
+def multiload_run(a, torch, W, V):
+    """Several load cases (the stacked problem, summed compliance), FP64.
+    (1) The three point loads of the 192x96x96 cantilever as three cases:
+    K(rho) on the three vectors in one launch over rotating (x, y) sets, with
+    its roofline against the compulsory bytes (read x and rho, write y);
+    the same three products by the single-load kernel, one launch per case;
+    at the initial Newton point the multigrid setup, the stacked S-apply,
+    one V-cycle and MINRES-MG iterations per second.  (2) Time-to-KKT of
+    the two-case 64x32x32 cantilever, KKT from the returned state on the
+    device.  (3) The CPU oracle's K(rho)u on one case of workload (1)."""
+    import numpy as np
+    pr = W.multi_config(2)
+    opts = V.default_options(max_minres=40)
+    ctx = V.Context.from_problem(pr, precision=V.VTS_FP64, options=opts)
+    k, nvec, m = ctx.nload, ctx.n_vec, ctx.m
+    g = torch.Generator(device="cpu").manual_seed(1)
+    sets = 4
+    xs = [(torch.rand(nvec, generator=g, dtype=torch.float64) - 0.5).cuda() for _ in range(sets)]
+    ys = [torch.empty_like(xs[0]) for _ in range(sets)]
+    rhos = [(0.001 + 0.999 * torch.rand(m, generator=g, dtype=torch.float64)).cuda()
+            for _ in range(sets)]
+    reps = max(a.reps, 1)
+    state = {"q": 0}
+
+    def batched():
+        q = state["q"] = (state["q"] + 1) % sets
+        ctx.apply_K_rho(rhos[q], xs[q], ys[q])
+
+    k_ms = _timed(torch, batched, reps * sets)
+    alg = 2.0 * nvec * 8 + 8.0 * m
+    k_gbs = alg / (k_ms * 1e-3) / 1e9
+    k_gdofs = nvec / (k_ms * 1e-3) / 1e9
+    print(f"batched K(rho) on {k} cases: {k_ms * 1e3:.1f} us per launch, {k_gdofs:.2f} GDOF/s, "
+          f"{k_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    # the same products case by case through the single-load kernel
+    single = W.cantilever_points(pr.nx, pr.ny, pr.nz, pr.levels, npoints=3, seed=0, vol_frac=0.1)
+    ctx1 = V.Context.from_problem(single, precision=V.VTS_FP64)
+    nd = ctx1.n_dof
+
+    def per_case():
+        q = state["q"] = (state["q"] + 1) % sets
+        for l in range(k):
+            ctx1.apply_K_rho(rhos[q], xs[q][l * nd:(l + 1) * nd], ys[q][l * nd:(l + 1) * nd])
+
+    s_ms = _timed(torch, per_case, reps * sets)
+    ctx1.close()
+    del single
+    print(f"single-load K(rho), {k} launches: {s_ms * 1e3:.1f} us", file=sys.stderr, flush=True)
+    # the stacked Newton system at the initial point
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ctx.newton_setup()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+    r = (torch.rand(nvec + 1, generator=g, dtype=torch.float64) - 0.5).cuda()
+    z = torch.empty_like(r)
+    sa_ms = _timed(torch, lambda: ctx.apply_S(r, z), reps)
+    vc_ms = _timed(torch, lambda: ctx.precondition(r, z), max(reps // 2, 1))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = ctx.solve_newton(0.0)
+    torch.cuda.synchronize()
+    mr_rate = st["iterations"] / (time.perf_counter() - t)
+    print(f"setup {setup_s:.2f} s, S-apply {sa_ms * 1e3:.0f} us, V-cycle {vc_ms:.2f} ms, "
+          f"MINRES-MG {mr_rate:.1f} it/s", file=sys.stderr, flush=True)
+    ctx.close()
+    for q in range(sets):
+        xs[q] = ys[q] = rhos[q] = None
+    torch.cuda.empty_cache()
+
+    # (2) time-to-KKT of the two-case cantilever
+    pr2 = W.multi_config(1)
+    ttk_out = None
+    if not a.ml_no_solve:
+        ttk_out = multiload_ttk(torch, W, V, pr2)
+
+    # (3) the oracle's K(rho)u on one case of workload (1)
+    from oracle import fe
+    gr = fe.Grid(pr.nx, pr.ny, pr.nz, pr.fixed)
+    Ke = fe.element_stiffness(pr.E, pr.nu, pr.h)
+    rh = W.random_rho(pr.m, seed=1)
+    xv = W.random_vector(pr.n_dof, seed=2)
+    t = time.perf_counter()
+    fe.apply_K(gr, Ke, rh, xv)
+    cpu_s = time.perf_counter() - t
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count()
+
+    # plain copies of 256 MiB: the scale reference of the traffic counters
+    buf = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(buf)
+    for _ in range(5):
+        dst.copy_(buf)
+    torch.cuda.synchronize()
+    del buf, dst
+
+    kern = "k_ml_apply<false>"
+    traffic = measured_traffic(pr.name, kern)
+    line = {
+        "metric": "K(rho)u on k load cases, GDOF/s; stacked MINRES-MG iters/s; time-to-KKT 1e-6",
+        "value": k_gdofs, "unit": "GDOF/s (K(rho) on 3 cases in one launch, FP64)",
+        "n_gpus": 1, "steps": reps * sets, "warmup": 1, "ms_per_step": k_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{pr.name} (the three point loads as three load cases)",
+                   "load_cases": k, "n_dof_per_case": pr.n_dof, "m": pr.m},
+        "roofline": {"bound": "hbm", "achieved": k_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": k_gbs / HBM_PEAK_GBS, "traffic": traffic, "kernel": kern,
+                     "algorithmic_bytes_per_launch": alg},
+        "cpu_baseline": {"value": pr.n_dof / cpu_s / 1e9, "unit": "GDOF/s", "cores": cores,
+                         "kind": "oracle",
+                         "sample": f"one application of the oracle's K(rho)u to one case of "
+                                   f"{pr.name} ({cpu_s:.2f} s)"},
+        "multiload": {
+            "batched_K_us": k_ms * 1e3, "single_load_K_3_launches_us": s_ms * 1e3,
+            "setup_s_initial_point": setup_s, "apply_S_us": sa_ms * 1e3,
+            "vcycle_ms": vc_ms, "minres_mg_iters_per_s": mr_rate,
+            "time_to_kkt": ttk_out,
+        },
+    }
     print(json.dumps(line), flush=True)
     return 0
 
@@ -1149,6 +1345,8 @@ def main():
         return doc_compare(a, torch, W, V)
     if a.scale_kernels:
         return scaling_kernels(a, torch, W, V)
+    if a.multiload:
+        return multiload_run(a, torch, W, V)
     if a.scale:
         return scaling_run(a, torch, W, V)
     if a.paper and a.ip:

@@ -66,17 +66,34 @@ typedef enum {
  * sum rho_lo < V < sum rho_hi, at least one fixed DOF, and fixed DOFs
  * nested across levels (a fixed fine DOF interpolates from fixed coarse
  * DOFs only; holds for clamped faces and fixed corner nodes).  Violations
- * give VTS_EINVAL. */
+ * give VTS_EINVAL.
+ *
+ * Several load cases (nload = k in 2..4): the density minimises the sum of
+ * the compliances 1/2 f_l^T u_l of the cases, K(rho) u_l = f_l.  This is
+ * problem (1.1) for the stacked displacement U = (u_1, ..., u_k) with the
+ * element matrices blockdiag(K_i, ..., K_i), so Sections 2-3 apply as
+ * written: e_i sums the cases' element energies, res_1 and the Newton
+ * system (3.12) take U, and the multigrid of Section 6 works on node blocks
+ * of 3k unknowns (the rank-one element terms of (3.12) couple the cases).
+ * f_host then holds k n_dof entries, case after case; every vector of the
+ * context that has a displacement part (u, res_1, the Newton-system vectors
+ * of vts_apply_S, vts_precondition, VTS_VEC_U, _RHS, _DY, _G1, the
+ * checkpoint) holds k n_dof entries (case after case) before alpha.
+ * Needs precision VTS_FP64.  vts_apply_K and vts_apply_K_rho apply K(rho)
+ * to k vectors at once; the FP32 operators, the allocation-free S-apply,
+ * DOC, the interior point method, server pools and group steps take one
+ * load case only (VTS_EINVAL). */
 typedef struct {
     int32_t nx, ny, nz, levels;
     double E, nu, h;
     const uint8_t* fixed_host;    /* n_dof entries, 1 = fixed */
-    const double* f_host;         /* n_dof entries, load vector */
+    const double* f_host;         /* max(nload, 1) n_dof entries: the load case(s) */
     double V;
     const double* rho_lo_host;    /* m entries or NULL */
     const double* rho_hi_host;    /* m entries or NULL */
     double rho_lo_s, rho_hi_s;
     int32_t precision;            /* vts_precision */
+    int32_t nload;                /* load cases; 0 or 1: one load */
 } vts_problem;
 
 /* Parameters of Algorithms 1 and 2 and of the MINRES rule of Section 6.2.

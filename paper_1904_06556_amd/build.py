@@ -19,8 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvts.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "mg.hip", "operator.hip", "capi.cpp", "host_fe.cpp", "server.cpp",
-           "group.cpp"]
+SOURCES = ["kernels.hip", "mg.hip", "operator.hip", "multiload.hip", "capi.cpp", "host_fe.cpp",
+           "server.cpp", "group.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -65,8 +65,18 @@ vts_status validate(const vts_problem* pr, std::string& err) {
         err = "unknown precision";
         return VTS_EINVAL;
     }
+    if (pr->nload < 0 || pr->nload > kMaxLoads) {
+        err = "nload must be 0..4";
+        return VTS_EINVAL;
+    }
+    if (pr->nload > 1 && pr->precision != VTS_FP64) {
+        err = "several load cases need precision VTS_FP64";
+        return VTS_EINVAL;
+    }
     return VTS_OK;
 }
+
+int load_cases(const vts_problem* pr) { return pr->nload > 1 ? pr->nload : 1; }
 
 template <typename T>
 void fill_level_geom(Level<T>& L, const Dims& d) {
@@ -320,7 +330,7 @@ vts_status evaluate(Ctx& c) {
     c.n_g4 = std::sqrt(r[SL_G4SQ]);
     c.n_g1 = std::sqrt(r[SL_G1SQ]);
     c.g2 = c.V - c.sum_r1;
-    launch_set(c, c.rhs + c.ndof, -c.g2 - c.sum_z);
+    launch_set(c, c.rhs + c.nvec, -c.g2 - c.sum_z);
     if (!std::isfinite(c.n_g1) || !std::isfinite(c.sum_w) || !std::isfinite(c.n_g3)) {
         c.err = "non-finite value in the gradient";
         return VTS_EINVAL;
@@ -343,7 +353,9 @@ void drop_graphs(Ctx& c) {
 
 vts_status build_mg(Ctx& c) {
     int flag = 0;
-    if (c.h64) {
+    if (c.mlh) {
+        flag = ml_mg_build(c);
+    } else if (c.h64) {
         mg_build(c, *c.h64);
         flag = mg_check_factor(c, *c.h64);
     } else {
@@ -371,7 +383,9 @@ vts_status setup(Ctx& c) {
 }
 
 void vcycle_launches(Ctx& c, const double* r, double* z) {
-    if (c.h64)
+    if (c.mlh)
+        ml_vcycle(c, r, z);
+    else if (c.h64)
         mg_vcycle(c, *c.h64, r, z);
     else
         mg_vcycle(c, *c.h32, r, z);
@@ -442,7 +456,7 @@ void mr_init(Ctx& c, MrState& m, double eps, int maxit, bool stop_indef) {
     m.eps = eps;
     m.maxit = maxit < 0 ? c.opt.max_minres : maxit;
     m.stop_indef = stop_indef;
-    m.n = c.ndof + 1;
+    m.n = c.nvec + 1;
     m.x = c.mv[0];
     m.r1 = c.mv[1];
     m.r2 = c.mv[2];
@@ -596,8 +610,8 @@ vts_status newton_step(Ctx& c, vts_newtonstats* out, bool final_call) {
     for (int tries = 0;; ++tries) {
         if ((st = minres(c, c.eps_mr, &ls)) != VTS_OK) return st;
         launch_dnu(c);
-        launch_dot(c, c.g1, c.dy, c.ndof, SL_DOT);
-        launch_copy1(c, c.dy + c.ndof, c.red + SL_AUX);
+        launch_dot(c, c.g1, c.dy, c.nvec, SL_DOT);
+        launch_copy1(c, c.dy + c.nvec, c.red + SL_AUX);
         if ((st = sync_red(c)) != VTS_OK) return st;
         dalpha = c.red_host[SL_AUX];
         slope = c.red_host[SL_DOT] + c.g2 * dalpha + c.red_host[SL_SLOPE_NU];
@@ -610,7 +624,7 @@ vts_status newton_step(Ctx& c, vts_newtonstats* out, bool final_call) {
         return VTS_ENONDESCENT;
     }
     // f^T du for the linear part of the Lagrangian change
-    launch_dot(c, c.f, c.dy, c.ndof, SL_DOT);
+    launch_dot(c, c.f, c.dy, c.nvec, SL_DOT);
     if ((st = sync_red(c)) != VTS_OK) return st;
     const double fdu = c.red_host[SL_DOT];
     double kappa = 1.0;
@@ -718,7 +732,7 @@ vts_status pbm_iterate(Ctx& c, vts_pbmstats* out) {
     vts_status st = newton(c, c.eps_nwt, false, &ns, &nits);
     if (st != VTS_OK) return st;
     launch_outer_eval(c);
-    launch_dot(c, c.f, c.u, c.ndof, SL_DOT);
+    launch_dot(c, c.f, c.u, c.nvec, SL_DOT);
     if ((st = sync_red(c)) != VTS_OK) return st;
     const double* r = c.red_host;
     const double fu = r[SL_DOT];
@@ -786,7 +800,7 @@ vts_status state_solve(Ctx& c, double eps) {
     if (st != VTS_OK) return st;
     vts_linstats ls{0, 0.0};
     if ((st = minres(c, eps, &ls)) != VTS_OK) return st;
-    HIPCHK(hipMemcpyAsync(c.u, c.dy, c.ndof * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+    HIPCHK(hipMemcpyAsync(c.u, c.dy, c.nvec * sizeof(double), hipMemcpyDeviceToDevice, c.s));
     c.eval_valid = false;
     c.setup_valid = false;
     HIPCHK(hipGetLastError());
@@ -945,17 +959,22 @@ struct HostData {
 vts_status prepare_host(const vts_problem* pr, HostData& hd, std::string& err) {
     const Dims d0{pr->nx, pr->ny, pr->nz};
     const int64_t ndof = 3 * nodes_of(d0), m = (int64_t)pr->nx * pr->ny * pr->nz;
+    const int nl = load_cases(pr);
     hd.mask.assign(pr->fixed_host, pr->fixed_host + ndof);
-    hd.f.assign(pr->f_host, pr->f_host + ndof);
+    hd.f.assign(pr->f_host, pr->f_host + nl * ndof);
     int64_t nfixed = 0;
     double nf2 = 0.0;
     for (int64_t q = 0; q < ndof; ++q) {
         hd.mask[q] = hd.mask[q] ? 1 : 0;
         nfixed += hd.mask[q];
-        if (hd.mask[q]) hd.f[q] = 0.0;
-        if (!std::isfinite(hd.f[q])) { err = "load vector is not finite"; return VTS_EINVAL; }
-        nf2 += hd.f[q] * hd.f[q];
     }
+    for (int l = 0; l < nl; ++l)
+        for (int64_t q = 0; q < ndof; ++q) {
+            double& fq = hd.f[l * ndof + q];
+            if (hd.mask[q]) fq = 0.0;
+            if (!std::isfinite(fq)) { err = "load vector is not finite"; return VTS_EINVAL; }
+            nf2 += fq * fq;
+        }
     if (nfixed == 0) { err = "no fixed DOF: K(rho) is singular"; return VTS_EINVAL; }
     if (nf2 == 0.0) { err = "zero load"; return VTS_EINVAL; }
     hd.nfree = ndof - nfixed;
@@ -986,8 +1005,8 @@ vts_status prepare_host(const vts_problem* pr, HostData& hd, std::string& err) {
         dk = Dims{dk.nx / 2, dk.ny / 2, dk.nz / 2};
     }
     int64_t nc = 1;
-    for (uint8_t v : mk) nc += v ? 0 : 1;
-    if (nc > kMaxCoarse) {
+    for (uint8_t v : mk) nc += v ? 0 : nl;
+    if (nc > (nl > 1 ? kMlMaxCoarse : kMaxCoarse)) {
         err = "coarsest level too large for the dense solver (" + std::to_string(nc) + ")";
         return VTS_EINVAL;
     }
@@ -1001,7 +1020,10 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
     c.m = (int64_t)c.nx * c.ny * c.nz;
     c.E = pr->E; c.nu = pr->nu; c.h = pr->h; c.V = pr->V;
     c.prec = pr->precision;
+    c.nl = load_cases(pr);
+    c.nvec = c.nl * c.ndof;
     if (opt) c.opt = *opt; else vts_default_options(&c.opt);
+    if (c.nl > 1) c.opt.use_graphs = 0;
     // the log path is the caller's string: keep a copy, not the pointer
     c.log_path = c.opt.log_path ? c.opt.log_path : "";
     c.opt.log_path = nullptr;
@@ -1037,27 +1059,27 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
     HIPCHK(hipMemcpyAsync(c.Mc, Mc, sizeof(Mc), hipMemcpyHostToDevice, c.s));
     HIPCHK(hipMemcpyAsync(c.Qc, Q, sizeof(Q), hipMemcpyHostToDevice, c.s));
 
-    ALLOC(c.fixed, c.ndof); ALLOC(c.nmask, c.nn); ALLOC(c.f, c.ndof); ALLOC(c.rlo, c.m);
+    ALLOC(c.fixed, c.ndof); ALLOC(c.nmask, c.nn); ALLOC(c.f, c.nvec); ALLOC(c.rlo, c.m);
     ALLOC(c.rhi, c.m);
     HIPCHK(hipMemcpyAsync(c.fixed, mask.data(), c.ndof, hipMemcpyHostToDevice, c.s));
     std::vector<uint8_t> nmask(c.nn);
     for (int64_t q = 0; q < c.nn; ++q)
         nmask[q] = (uint8_t)(mask[3 * q] | (mask[3 * q + 1] << 1) | (mask[3 * q + 2] << 2));
     HIPCHK(hipMemcpyAsync(c.nmask, nmask.data(), c.nn, hipMemcpyHostToDevice, c.s));
-    HIPCHK(hipMemcpyAsync(c.f, f.data(), c.ndof * 8, hipMemcpyHostToDevice, c.s));
+    HIPCHK(hipMemcpyAsync(c.f, f.data(), c.nvec * 8, hipMemcpyHostToDevice, c.s));
     HIPCHK(hipMemcpyAsync(c.rlo, lo.data(), c.m * 8, hipMemcpyHostToDevice, c.s));
     HIPCHK(hipMemcpyAsync(c.rhi, hi.data(), c.m * 8, hipMemcpyHostToDevice, c.s));
-    ALLOC(c.u, c.ndof);
+    ALLOC(c.u, c.nvec);
     ALLOC(c.nlo, c.m); ALLOC(c.nhi, c.m); ALLOC(c.rho, c.m); ALLOC(c.mlo, c.m);
     ALLOC(c.mhi, c.m); ALLOC(c.p, c.m); ALLOC(c.qlo, c.m); ALLOC(c.qhi, c.m);
     ALLOC(c.rhof, c.m);
-    ALLOC(c.e, c.m); ALLOC(c.be, 24 * c.m);
+    ALLOC(c.e, c.m); ALLOC(c.be, 24 * c.m * c.nl);
     ALLOC(c.r1, c.m); ALLOC(c.r2, c.m); ALLOC(c.l2, c.m); ALLOC(c.h2, c.m);
     ALLOC(c.g3, c.m); ALLOC(c.g4, c.m); ALLOC(c.w, c.m); ALLOC(c.zc, c.m);
     ALLOC(c.gch, 24 * c.m);
-    ALLOC(c.g1, c.ndof); ALLOC(c.rhs, c.ndof + 1); ALLOC(c.dy, c.ndof + 1);
+    ALLOC(c.g1, c.nvec); ALLOC(c.rhs, c.nvec + 1); ALLOC(c.dy, c.nvec + 1);
     ALLOC(c.dnl, c.m); ALLOC(c.dnh, c.m); ALLOC(c.c1, c.m); ALLOC(c.c2, c.m); ALLOC(c.wt, c.m);
-    for (int q = 0; q < 8; ++q) ALLOC(c.mv[q], c.ndof + 1);
+    for (int q = 0; q < 8; ++q) ALLOC(c.mv[q], c.nvec + 1);
     ALLOC(c.partials, kRedSlots * kRedBlocks);
     ALLOC(c.spart, apply_S_tile_blocks(c));
     ALLOC(c.red, kRedSlots);
@@ -1068,7 +1090,9 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
         std::memset(c.red_host, 0, kRedSlots * sizeof(double));
     }
     vts_status st;
-    if (c.prec == VTS_FP64) {
+    if (c.nl > 1) {
+        st = ml_create(c, mask);
+    } else if (c.prec == VTS_FP64) {
         c.h64 = new Hierarchy<double>();
         st = build_hierarchy(c, *c.h64, mask);
     } else {
@@ -1081,7 +1105,7 @@ vts_status ctx_create(Ctx& c, const vts_problem* pr, const vts_options* opt, voi
     launch_round_rho(c);
     c.alpha = 1.0;
     c.eps_nwt = c.opt.eps_nwt0;
-    c.eps_mr = c.opt.eps_mr0 > 0 ? c.opt.eps_mr0 : 1e-4 * std::sqrt((double)c.nfree);
+    c.eps_mr = c.opt.eps_mr0 > 0 ? c.opt.eps_mr0 : 1e-4 * std::sqrt((double)c.nl * c.nfree);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c.s));
     return VTS_OK;
@@ -1105,6 +1129,7 @@ void ctx_free(Ctx& c) {
     delete c.h32;
     c.h64 = nullptr;
     c.h32 = nullptr;
+    ml_destroy(c);
 }
 
 thread_local std::string g_create_err;
@@ -1112,6 +1137,24 @@ thread_local std::string g_create_err;
 }  // namespace
 
 namespace vts {
+
+// EINVAL for calls that one load case only supports
+bool several_loads(Ctx& c, const char* what) {
+    if (c.nl <= 1) return false;
+    c.err = std::string(what) + " supports one load case only";
+    return true;
+}
+
+vts_status ml_alloc(Ctx& c, void** ptr, size_t bytes) {
+    uint8_t* q = nullptr;
+    const vts_status st = alloc_t(c, &q, (int64_t)bytes);
+    *ptr = q;
+    return st;
+}
+
+std::vector<uint8_t> ml_coarsen(const std::vector<uint8_t>& fine_mask, int nx, int ny, int nz) {
+    return coarsen_mask(fine_mask, Dims{nx, ny, nz});
+}
 
 bool prof_begin(Ctx& c, int cls) {
     if (c.prof_class != cls) return false;
@@ -1208,7 +1251,7 @@ vts_status vts_reset(vts_ctx* cp) {
     launch_round_rho(c);
     c.alpha = 1.0;
     c.eps_nwt = c.opt.eps_nwt0;
-    c.eps_mr = c.opt.eps_mr0 > 0 ? c.opt.eps_mr0 : 1e-4 * std::sqrt((double)c.nfree);
+    c.eps_mr = c.opt.eps_mr0 > 0 ? c.opt.eps_mr0 : 1e-4 * std::sqrt((double)c.nl * c.nfree);
     c.res_prev = -1.0;
     c.outer = c.newton_total = c.minres_total = 0;
     c.converged = false;
@@ -1228,7 +1271,7 @@ void vts_destroy(vts_ctx* c) {
 size_t vts_footprint_bytes(const vts_problem* pr, const vts_options* opt) {
     (void)opt;
     std::string err;
-    if (validate(pr, err) != VTS_OK) return 0;
+    if (validate(pr, err) != VTS_OK || pr->nload > 1) return 0;
     return make_plan(pr).total();
 }
 
@@ -1264,6 +1307,7 @@ vts_status vts_apply_K(vts_ctx* cp, const double* x, double* y) {
 vts_status vts_apply_K_f32(vts_ctx* cp, const float* x, float* y) {
     if (!cp || !x || !y || x == y) return VTS_EINVAL;
     Ctx& c = *cp;
+    if (several_loads(c, "vts_apply_K_f32")) return VTS_EINVAL;
     launch_apply_K_f32(c, c.rhof, x, y);
     HIPCHK(hipGetLastError());
     return VTS_OK;
@@ -1280,6 +1324,7 @@ vts_status vts_apply_K_rho(vts_ctx* cp, const double* rho, const double* x, doub
 vts_status vts_apply_K_rho_f32(vts_ctx* cp, const float* rho, const float* x, float* y) {
     if (!cp || !rho || !x || !y || x == y) return VTS_EINVAL;
     Ctx& c = *cp;
+    if (several_loads(c, "vts_apply_K_rho_f32")) return VTS_EINVAL;
     launch_apply_K_f32(c, rho, x, y);
     HIPCHK(hipGetLastError());
     return VTS_OK;
@@ -1312,6 +1357,7 @@ vts_status vts_apply_S(vts_ctx* cp, const double* x, double* y) {
 vts_status vts_apply_S_noalloc(vts_ctx* cp, const double* x, double* y) {
     if (!cp || !x || !y || x == y) return VTS_EINVAL;
     Ctx& c = *cp;
+    if (several_loads(c, "vts_apply_S_noalloc")) return VTS_EINVAL;
     if (!c.eval_valid) { c.err = "apply_S before newton_setup"; return VTS_ESTATE; }
     if (!tile_ok(c)) {
         c.err = "allocation-free S-apply needs the tiled operator (cube element)";
@@ -1420,7 +1466,7 @@ vts_status vts_pbm_solve(vts_ctx* cp, vts_result* res) {
         }
     }
     if (res) {
-        launch_dot(c, c.f, c.u, c.ndof, SL_DOT);
+        launch_dot(c, c.f, c.u, c.nvec, SL_DOT);
         launch_outer_eval(c);
         vts_status s3 = sync_red(c);
         if (s3 != VTS_OK && st == VTS_OK) st = s3;
@@ -1453,6 +1499,7 @@ vts_status vts_doc_step(vts_ctx* cp, double q, double tau, double eps_doc, doubl
                         vts_docstats* out) {
     if (!cp || !(q > 0) || !(tau > 0)) return VTS_EINVAL;
     Ctx& c = *cp;
+    if (several_loads(c, "vts_doc_step")) return VTS_EINVAL;
     // the state equation: MINRES with the V-cycle on blockdiag(K(rho), 1)
     c.eval_valid = false;
     c.setup_valid = false;
@@ -1534,17 +1581,20 @@ void vts_ip_default_options(vts_ip_options* o) {
 
 vts_status vts_ip_init(vts_ctx* cp, const vts_ip_options* opt) {
     if (!cp) return VTS_EINVAL;
+    if (several_loads(*cp, "vts_ip_init")) return VTS_EINVAL;
     return ip_init(*cp, opt);
 }
 
 vts_status vts_ip_step(vts_ctx* cp, vts_ipstats* stats) {
     if (!cp) return VTS_EINVAL;
+    if (several_loads(*cp, "vts_ip_step")) return VTS_EINVAL;
     return ip_step(*cp, stats);
 }
 
 vts_status vts_ip_solve(vts_ctx* cp, const vts_ip_options* opt, vts_ipstats* stats) {
     if (!cp) return VTS_EINVAL;
     Ctx& c = *cp;
+    if (several_loads(c, "vts_ip_solve")) return VTS_EINVAL;
     vts_status st = ip_init(c, opt);
     if (st != VTS_OK) return st;
     vts_ipstats s{};
@@ -1567,12 +1617,12 @@ vts_status vts_get_vector(const vts_ctx* cp, int32_t which, double* dst) {
     const double* src = nullptr;
     int64_t n = 0;
     switch (which) {
-        case VTS_VEC_U: src = c.u; n = c.ndof; break;
+        case VTS_VEC_U: src = c.u; n = c.nvec; break;
         case VTS_VEC_RHO: src = c.rho; n = c.m; break;
         case VTS_VEC_ENERGY: src = c.e; n = c.m; break;
-        case VTS_VEC_RHS: src = c.rhs; n = c.ndof + 1; break;
-        case VTS_VEC_DY: src = c.dy; n = c.ndof + 1; break;
-        case VTS_VEC_G1: src = c.g1; n = c.ndof; break;
+        case VTS_VEC_RHS: src = c.rhs; n = c.nvec + 1; break;
+        case VTS_VEC_DY: src = c.dy; n = c.nvec + 1; break;
+        case VTS_VEC_G1: src = c.g1; n = c.nvec; break;
         case VTS_VEC_DNU_LO: src = c.dnl; n = c.m; break;
         case VTS_VEC_DNU_HI: src = c.dnh; n = c.m; break;
         case VTS_VEC_RHO1: src = c.r1; n = c.m; break;
@@ -1595,7 +1645,7 @@ constexpr double kStateVersion = 2.0;
 constexpr int kStateHead = 4, kStateTail = 5;
 
 size_t state_bytes(const Ctx& c) {
-    return (size_t)(kStateHead + c.ndof + 1 + 8 * c.m + kStateTail) * 8;
+    return (size_t)(kStateHead + c.nvec + 1 + 8 * c.m + kStateTail) * 8;
 }
 
 vts_status vts_get_state(const vts_ctx* cp, void* buf, size_t* bytes) {
@@ -1609,10 +1659,10 @@ vts_status vts_get_state(const vts_ctx* cp, void* buf, size_t* bytes) {
     double* b = (double*)buf;
     *b++ = kStateMagic;
     *b++ = kStateVersion;
-    *b++ = (double)c.ndof;
+    *b++ = (double)c.nvec;
     *b++ = (double)c.m;
-    HIPCHK(hipMemcpyAsync(b, c.u, c.ndof * 8, hipMemcpyDeviceToHost, c.s));
-    b += c.ndof;
+    HIPCHK(hipMemcpyAsync(b, c.u, c.nvec * 8, hipMemcpyDeviceToHost, c.s));
+    b += c.nvec;
     *b++ = c.alpha;
     double* arr[8] = {c.nlo, c.nhi, c.rho, c.mlo, c.mhi, c.p, c.qlo, c.qhi};
     for (int q = 0; q < 8; ++q) {
@@ -1635,20 +1685,20 @@ vts_status vts_set_state(vts_ctx* cp, const void* buf, size_t bytes) {
     const size_t need = state_bytes(c);
     if (bytes != need) { c.err = "state size mismatch"; return VTS_EINVAL; }
     const double* b = (const double*)buf;
-    if (b[0] != kStateMagic || b[1] != kStateVersion || b[2] != (double)c.ndof ||
+    if (b[0] != kStateMagic || b[1] != kStateVersion || b[2] != (double)c.nvec ||
         b[3] != (double)c.m) {
-        c.err = "state header does not match this context (magic, version, n_dof, m)";
+        c.err = "state header does not match this context (magic, version, load cases x n_dof, m)";
         return VTS_EINVAL;
     }
-    const double* t = b + kStateHead + c.ndof + 1 + 8 * c.m;
+    const double* t = b + kStateHead + c.nvec + 1 + 8 * c.m;
     for (int q = 2; q < kStateTail; ++q)
         if (!(t[q] >= 0 && t[q] < 2147483647.0 && t[q] == std::floor(t[q]))) {
             c.err = "state counters out of range";
             return VTS_EINVAL;
         }
     b += kStateHead;
-    HIPCHK(hipMemcpyAsync(c.u, b, c.ndof * 8, hipMemcpyHostToDevice, c.s));
-    b += c.ndof;
+    HIPCHK(hipMemcpyAsync(c.u, b, c.nvec * 8, hipMemcpyHostToDevice, c.s));
+    b += c.nvec;
     c.alpha = *b++;
     double* arr[8] = {c.nlo, c.nhi, c.rho, c.mlo, c.mhi, c.p, c.qlo, c.qhi};
     for (int q = 0; q < 8; ++q) {

@@ -10,100 +10,10 @@
 #include <cfloat>
 #include <cmath>
 
+#include "device_util.hpp"
 #include "vts_internal.hpp"
 
 namespace vts {
-
-// ---------------------------------------------------------------------------
-// small device helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t gid() {
-    return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-}
-
-__device__ __forceinline__ int64_t node_id(int i, int j, int k, int NX, int NY) {
-    return (int64_t)i + (int64_t)NX * ((int64_t)j + (int64_t)NY * k);
-}
-
-// Penalty-barrier function of Ben-Tal and Zibulevsky with tau_hat = -1/2
-// (Section 3.1): quadratic for t >= -1/2, logarithmic branch below.
-__device__ __forceinline__ double pen_phi(double t) {
-    return t >= -0.5 ? t + 0.5 * t * t : -0.25 * log(-2.0 * t) - 0.375;
-}
-__device__ __forceinline__ double pen_dphi(double t) {
-    return t >= -0.5 ? 1.0 + t : -0.25 / t;
-}
-__device__ __forceinline__ double pen_d2phi(double t) {
-    return t >= -0.5 ? 1.0 : 0.25 / (t * t);
-}
-// phi(t + dt) - phi(t) without subtracting two values of phi when both points
-// lie on one branch: dt (1 + t + dt/2) (quadratic), -1/4 log1p(dt/t) (log)
-__device__ __forceinline__ double pen_phi_diff(double t, double dt) {
-    const double t1 = t + dt;
-    if (t >= -0.5 && t1 >= -0.5) return dt * (1.0 + t + 0.5 * dt);
-    if (t < -0.5 && t1 < -0.5) return -0.25 * log1p(dt / t);
-    return pen_phi(t1) - pen_phi(t);
-}
-
-// block-wide sum of NQ values per thread; thread 0 writes partials[q*kRedBlocks + block]
-template <int NQ>
-__device__ __forceinline__ void block_sum_store(double (&v)[NQ], double* partials, int slot0,
-                                                uint32_t maxmask = 0) {
-    __shared__ double sh[NQ][kThreads / 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        double x = v[q];
-        const bool mx = (maxmask >> q) & 1u;
-        for (int off = 32; off > 0; off >>= 1) {
-            const double o = __shfl_down(x, off, 64);
-            x = mx ? fmax(x, o) : x + o;
-        }
-        if (lane == 0) sh[q][wv] = x;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const bool mx = (maxmask >> q) & 1u;
-            double x = sh[q][0];
-            for (int k = 1; k < kThreads / 64; ++k) x = mx ? fmax(x, sh[q][k]) : x + sh[q][k];
-            partials[(slot0 + q) * kRedBlocks + blockIdx.x] = x;
-        }
-    }
-}
-
-static inline int red_grid(int64_t n) {
-    int64_t b = (n + kThreads - 1) / kThreads;
-    if (b < 1) b = 1;
-    return (int)(b < kRedBlocks ? b : kRedBlocks);
-}
-static inline int grid1d(int64_t n) {
-    int64_t b = (n + kThreads - 1) / kThreads;
-    return (int)(b < 1 ? 1 : b);
-}
-
-// Sum (or max) of partials[slot*kRedBlocks + b] over b < nb, fixed order.
-__device__ __forceinline__ void finalize_body(const double* __restrict__ partials, int nb,
-                                              int slot0, uint32_t maxmask,
-                                              double* __restrict__ out) {
-    const int q = slot0 + blockIdx.x;
-    const bool mx = (maxmask >> blockIdx.x) & 1u;
-    double x = mx ? -DBL_MAX : 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        const double v = partials[q * kRedBlocks + b];
-        x = mx ? fmax(x, v) : x + v;
-    }
-    __shared__ double sh[kThreads];
-    sh[threadIdx.x] = x;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sh[threadIdx.x] = mx ? fmax(sh[threadIdx.x], sh[threadIdx.x + s])
-                                                  : sh[threadIdx.x] + sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[q] = sh[0];
-}
 
 __global__ void k_finalize(const double* __restrict__ partials, int nb, int slot0,
                            uint32_t maxmask, double* __restrict__ out) {
@@ -162,6 +72,10 @@ k_apply_K(int nx, int ny, int nz, const T* __restrict__ Ke, const T* __restrict_
 }
 
 void launch_apply_K_f64(Ctx& c, const double* rho, const double* x, double* y) {
+    if (c.nl > 1) {
+        ml_apply_K(c, rho, x, y);
+        return;
+    }
     if (tile_ok(c)) {
         // algorithmic bytes: read x and rho, write y (8 B each entry); the
         // Dirichlet data (one mask byte per node) are not counted
@@ -180,25 +94,6 @@ void launch_apply_K_f32(Ctx& c, const float* rho, const float* x, float* y) {
     }
     hipLaunchKernelGGL(k_apply_K<float>, dim3(grid1d(c.nn)), dim3(kThreads), 0, c.s,
                        c.nx, c.ny, c.nz, c.Kef, rho, x, c.fixed, y);
-}
-
-// gather the 24 (masked) DOF values of element (i,j,k)
-__device__ __forceinline__ void gather_elem(const double* __restrict__ x,
-                                            const uint8_t* __restrict__ fixed, int i, int j,
-                                            int k, int NX, int NY, double (&xe)[24]) {
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const int64_t nb = node_id(i + (b & 1), j + ((b >> 1) & 1), k + (b >> 2), NX, NY);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) xe[3 * b + c] = fixed[3 * nb + c] ? 0.0 : x[3 * nb + c];
-    }
-}
-
-__device__ __forceinline__ void elem_ijk(int64_t e, int nx, int ny, int& i, int& j, int& k) {
-    i = (int)(e % nx);
-    const int64_t t = e / nx;
-    j = (int)(t % ny);
-    k = (int)(t / ny);
 }
 
 // e_i = 1/2 u_e^T K_e u_e
@@ -223,6 +118,10 @@ k_energy(int nx, int ny, int nz, const double* __restrict__ Ke, const double* __
 }
 
 void launch_energy(Ctx& c, const double* u, double* e) {
+    if (c.nl > 1) {
+        ml_launch_energy(c, u, e);
+        return;
+    }
     hipLaunchKernelGGL(k_energy, dim3(grid1d(c.m)), dim3(kThreads), 0, c.s, c.nx, c.ny, c.nz,
                        c.Ke, u, c.fixed, e);
 }
@@ -289,6 +188,10 @@ __global__ void __launch_bounds__(kThreads) k_eval(EvalArgs a) {
 }
 
 void launch_eval(Ctx& c) {
+    if (c.nl > 1) {
+        ml_launch_eval(c);
+        return;
+    }
     EvalArgs a{c.nx, c.ny, c.nz, c.alpha, c.Ke, c.u, c.nlo, c.nhi, c.rho, c.mlo, c.mhi, c.p,
                c.qlo, c.qhi, c.rlo, c.rhi, c.fixed, c.e, c.be, c.r1, c.r2, c.l2, c.h2,
                c.g3, c.g4, c.w, c.zc, c.partials};
@@ -346,6 +249,10 @@ k_grad(int nx, int ny, int nz, const double* __restrict__ be, const double* __re
 }
 
 void launch_grad(Ctx& c) {
+    if (c.nl > 1) {
+        ml_launch_grad(c);
+        return;
+    }
     const int g = red_grid(c.nn);
     hipLaunchKernelGGL(k_grad, dim3(g), dim3(kThreads), 0, c.s, c.nx, c.ny, c.nz, c.be, c.r1,
                        c.zc, c.f, c.fixed, c.g1, c.rhs, c.partials);
@@ -435,6 +342,10 @@ __global__ void k_store_neg(const double* __restrict__ red, int slot, double* __
 }
 
 void launch_apply_S(Ctx& c, const double* x, double* y) {
+    if (c.nl > 1) {
+        ml_apply_S(c, x, y);
+        return;
+    }
     if (tile_ok(c)) {
         // algorithmic bytes: x, u, y, rho', w and the DOF mask
         const bool prof = prof_begin(c, VTS_PROF_APPLY_S);
@@ -497,6 +408,10 @@ __global__ void __launch_bounds__(kThreads) k_dnu(DnuArgs a) {
 }
 
 void launch_dnu(Ctx& c) {
+    if (c.nl > 1) {
+        ml_launch_dnu(c);
+        return;
+    }
     DnuArgs a{c.nx, c.ny, c.nz, c.ndof, c.Ke, c.be, c.dy, c.r2, c.l2, c.h2, c.g3, c.g4,
               c.fixed, c.c1, c.c2, c.dnl, c.dnh, c.partials};
     const int g = red_grid(c.m);
@@ -558,8 +473,9 @@ __global__ void k_update(int64_t ndof, int64_t m, double kappa, double* __restri
 }
 
 void launch_update(Ctx& c, double kappa) {
-    const int64_t n = c.ndof > c.m ? c.ndof : c.m;
-    hipLaunchKernelGGL(k_update, dim3(grid1d(n)), dim3(kThreads), 0, c.s, c.ndof, c.m, kappa, c.u,
+    // u holds every load case (nvec entries)
+    const int64_t n = c.nvec > c.m ? c.nvec : c.m;
+    hipLaunchKernelGGL(k_update, dim3(grid1d(n)), dim3(kThreads), 0, c.s, c.nvec, c.m, kappa, c.u,
                        c.dy, c.nlo, c.nhi, c.dnl, c.dnh);
 }
 
@@ -630,9 +546,9 @@ k_kkt(int64_t ndof, int64_t m, double lam, const double* __restrict__ Ku,
 void launch_kkt(Ctx& c, double lam, double* Ku) {
     launch_apply_K_f64(c, c.rho, c.u, Ku);
     launch_energy(c, c.u, c.e);
-    const int64_t n = c.ndof > c.m ? c.ndof : c.m;
+    const int64_t n = c.nvec > c.m ? c.nvec : c.m;
     const int g = red_grid(n);
-    hipLaunchKernelGGL(k_kkt, dim3(g), dim3(kThreads), 0, c.s, c.ndof, c.m, lam, Ku, c.f, c.rho,
+    hipLaunchKernelGGL(k_kkt, dim3(g), dim3(kThreads), 0, c.s, c.nvec, c.m, lam, Ku, c.f, c.rho,
                        c.e, c.rlo, c.rhi, c.partials);
     hipLaunchKernelGGL(k_finalize, dim3(5), dim3(kThreads), 0, c.s, c.partials, g, (int)SL_STAT,
                        0x19u, c.red);
@@ -693,8 +609,8 @@ __global__ void k_init(int64_t ndof, int64_t m, double rho0, double* u, double* 
 }
 
 void launch_init_state(Ctx& c) {
-    const int64_t n = c.ndof > c.m ? c.ndof : c.m;
-    hipLaunchKernelGGL(k_init, dim3(grid1d(n)), dim3(kThreads), 0, c.s, c.ndof, c.m,
+    const int64_t n = c.nvec > c.m ? c.nvec : c.m;
+    hipLaunchKernelGGL(k_init, dim3(grid1d(n)), dim3(kThreads), 0, c.s, c.nvec, c.m,
                        c.V / (double)c.m, c.u, c.nlo, c.nhi, c.rho, c.mlo, c.mhi, c.p, c.qlo,
                        c.qhi);
 }
@@ -828,7 +744,7 @@ void launch_axpy_red(Ctx& c, double* y, int slot, double div, const double* x, i
 // ---------------------------------------------------------------------------
 // K(rho) as the Schur operator with rho' = rho, w = 0 (no rank-one terms, no
 // alpha coupling) and right-hand side [f; 0]
-__global__ void k_doc_setup(int64_t m, int64_t ndof, const double* __restrict__ rho,
+__global__ void k_doc_setup(int64_t m, int64_t nbe, int64_t nvec, const double* __restrict__ rho,
                             const double* __restrict__ f, double* __restrict__ r1,
                             double* __restrict__ w, double* __restrict__ be,
                             double* __restrict__ rhs) {
@@ -837,13 +753,16 @@ __global__ void k_doc_setup(int64_t m, int64_t ndof, const double* __restrict__ 
         r1[t] = rho[t];
         w[t] = 0.0;
     }
-    if (t < 24 * m) be[t] = 0.0;
-    if (t < ndof) rhs[t] = f[t];
-    if (t == 0) rhs[ndof] = 0.0;
+    if (t < nbe) be[t] = 0.0;
+    if (t < nvec) rhs[t] = f[t];
+    if (t == 0) rhs[nvec] = 0.0;
 }
 void launch_doc_setup(Ctx& c) {
-    hipLaunchKernelGGL(k_doc_setup, dim3(grid1d(std::max<int64_t>(24 * c.m, c.ndof + 1))),
-                       dim3(kThreads), 0, c.s, c.m, c.ndof, c.rho, c.f, c.r1, c.w, c.be, c.rhs);
+    // every load case: be of all cases, f and rhs stacked
+    const int64_t nbe = 24 * c.m * c.nl;
+    hipLaunchKernelGGL(k_doc_setup, dim3(grid1d(std::max<int64_t>(nbe, c.nvec + 1))),
+                       dim3(kThreads), 0, c.s, c.m, nbe, c.nvec, c.rho, c.f, c.r1, c.w, c.be,
+                       c.rhs);
 }
 
 __device__ __forceinline__ double doc_candidate(double rho, double e, double lo, double hi,

@@ -307,7 +307,7 @@ vts_status vts_server_fetch(vts_server* S, int64_t id, double* rho_host, double*
 vts_status vts_group_step(vts_ctx** ctxs, int32_t k, vts_pbmstats* stats) {
     if (!ctxs || k < 0) return VTS_EINVAL;
     for (int32_t q = 0; q < k; ++q) {
-        if (!ctxs[q]) return VTS_EINVAL;
+        if (!ctxs[q] || ctxs[q]->nl > 1) return VTS_EINVAL;   // one load case per context
         for (int32_t p = 0; p < q; ++p)
             if (ctxs[p] == ctxs[q]) return VTS_EINVAL;
     }

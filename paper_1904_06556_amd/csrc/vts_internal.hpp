@@ -16,6 +16,8 @@ constexpr int kThreads = 256;          // block size of every 1D launch
 constexpr int kRedBlocks = 1024;       // max blocks of a reduction launch
 constexpr int kRedSlots = 17;          // quantities per reduction buffer
 constexpr int kMaxCoarse = 4096;       // largest dense coarsest system
+constexpr int kMaxLoads = 4;           // load cases of one problem
+constexpr int kMlMaxCoarse = 4096;     // largest dense coarsest system with several cases
 
 // Block of 27 neighbours: offset (dx,dy,dz) in {-1,0,1}^3 -> s = (dx+1) + 3(dy+1) + 9(dz+1).
 constexpr int kStencil = 27;
@@ -188,6 +190,14 @@ struct Ctx {
     // multigrid
     Hierarchy<double>* h64 = nullptr;
     Hierarchy<float>* h32 = nullptr;
+
+    // load cases: u, f, g1 and the u-part of every Newton-system vector hold
+    // nl all-DOF vectors one after another (nvec = nl n_dof entries); with
+    // nl > 1 the multi-load kernels and their multigrid (mlh) serve the
+    // context
+    int nl = 1;
+    int64_t nvec = 0;
+    struct MlHierarchy* mlh = nullptr;
 
     // algorithm state (host)
     double eps_nwt = 1.0, eps_mr = 0.0, res_prev = -1.0;
@@ -399,6 +409,24 @@ constexpr int kScratchPartials = 1 << 16;
 constexpr int kMaxScratchDevices = 64;
 vts_status scratch_partials(int device, double** out, std::string& err);
 bool walsh_form(const double* Ke, double* kh8);    // host_fe.cpp
+
+// several load cases (multiload.hip): evaluation, gradient, batched K,
+// S-apply, Delta nu, energies, update, and the multigrid with node blocks
+// over all cases
+void ml_launch_eval(Ctx& c);
+void ml_launch_grad(Ctx& c);
+void ml_apply_K(Ctx& c, const double* coef, const double* x, double* y);
+void ml_apply_S(Ctx& c, const double* x, double* y);
+void ml_launch_dnu(Ctx& c);
+void ml_launch_energy(Ctx& c, const double* u, double* e);
+void ml_launch_update(Ctx& c, double kappa);
+vts_status ml_create(Ctx& c, const std::vector<uint8_t>& fine_mask);
+void ml_destroy(Ctx& c);
+int ml_mg_build(Ctx& c);
+void ml_vcycle(Ctx& c, const double* r, double* z);
+// capi.cpp: a device buffer of the context, and the coarse DOF mask by injection
+vts_status ml_alloc(Ctx& c, void** ptr, size_t bytes);
+std::vector<uint8_t> ml_coarsen(const std::vector<uint8_t>& fine_mask, int nx, int ny, int nz);
 
 template <typename T> void mg_build(Ctx& c, Hierarchy<T>& H);
 template <typename T> void mg_vcycle(Ctx& c, Hierarchy<T>& H, const double* r, double* z);

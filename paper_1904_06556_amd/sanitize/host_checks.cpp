@@ -97,6 +97,26 @@ int main() {
         vts_ctx* c = nullptr;
         EXPECT(vts_create(&bad.p, &o, nullptr, &c) == VTS_EINVAL);
     }
+    {
+        // several load cases: f holds nload cases; a NaN in the second is
+        // found, mixed precision and more than 4 cases are refused, and the
+        // footprint (server admission) is for one case only
+        Cant two(8, 4, 4, 3);
+        std::vector<double> f2(two.f);
+        f2.insert(f2.end(), two.f.begin(), two.f.end());
+        two.p.f_host = f2.data();
+        two.p.nload = 2;
+        EXPECT(vts_footprint_bytes(&two.p, &o) == 0);
+        vts_ctx* c = nullptr;
+        f2[two.f.size() + 3 * 12 + 2] = NAN;
+        EXPECT(vts_create(&two.p, &o, nullptr, &c) == VTS_EINVAL && c == nullptr);
+        f2[two.f.size() + 3 * 12 + 2] = 0.0;
+        two.p.precision = VTS_MIXED;
+        EXPECT(vts_create(&two.p, &o, nullptr, &c) == VTS_EINVAL);
+        two.p.precision = VTS_FP64;
+        two.p.nload = 5;
+        EXPECT(vts_create(&two.p, &o, nullptr, &c) == VTS_EINVAL);
+    }
     // a valid problem: solved where a device exists, a clean device error otherwise
     int ndev = 0;
     const bool gpu = hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0;

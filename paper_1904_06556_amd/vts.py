@@ -41,7 +41,7 @@ class Problem_t(C.Structure):
                 ("V", C.c_double),
                 ("rho_lo_host", C.POINTER(C.c_double)), ("rho_hi_host", C.POINTER(C.c_double)),
                 ("rho_lo_s", C.c_double), ("rho_hi_s", C.c_double),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("nload", C.c_int32)]
 
 
 class Options_t(C.Structure):
@@ -218,10 +218,14 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-def _problem_struct(nx, ny, nz, levels, fixed, f, V, rho_lo, rho_hi, E, nu, h, precision):
-    """vts_problem over host arrays; returns it with the arrays it points to."""
+def _problem_struct(nx, ny, nz, levels, fixed, f, V, rho_lo, rho_hi, E, nu, h, precision,
+                    nload=1):
+    """vts_problem over host arrays; returns it with the arrays it points to
+    (f: nload load cases of n_dof entries each, one after another)."""
     fixed = np.ascontiguousarray(fixed, dtype=np.uint8)
     f = np.ascontiguousarray(f, dtype=np.float64)
+    if f.size != max(int(nload), 1) * fixed.size:
+        raise ValueError("f must hold nload x n_dof entries")
     pr = Problem_t()
     pr.nx, pr.ny, pr.nz, pr.levels = nx, ny, nz, levels
     pr.E, pr.nu, pr.h, pr.V = E, nu, h, V
@@ -241,6 +245,7 @@ def _problem_struct(nx, ny, nz, levels, fixed, f, V, rho_lo, rho_hi, E, nu, h, p
     else:
         pr.rho_hi_s = float(rho_hi)
     pr.precision = precision
+    pr.nload = nload
     return pr, keep
 
 
@@ -249,10 +254,10 @@ class Context:
 
     def __init__(self, nx, ny, nz, levels, fixed, f, V, rho_lo=1e-3, rho_hi=1.0, E=1.0,
                  nu=0.3, h=1.0, precision=VTS_FP64, options: Optional[Options_t] = None,
-                 stream=None):
+                 stream=None, nload=1):
         L = lib()
         pr, self._keep = _problem_struct(nx, ny, nz, levels, fixed, f, V, rho_lo, rho_hi, E, nu,
-                                         h, precision)
+                                         h, precision, nload)
         self._pr = pr
         self._opt = options if options is not None else default_options()
         self.stream = stream
@@ -264,11 +269,21 @@ class Context:
         nd, m, nf, lv = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
         L.vts_sizes(self.h, C.byref(nd), C.byref(m), C.byref(nf), C.byref(lv))
         self.n_dof, self.m, self.n_free, self.levels = nd.value, m.value, nf.value, lv.value
+        # load cases: displacement-sized vectors hold nload n_dof entries
+        self.nload = max(int(nload), 1)
+        self.n_vec = self.nload * self.n_dof
 
     @classmethod
     def from_problem(cls, pr, precision=None, options=None, stream=None):
+        """A problem with load cases (extra["load_cases"], k x n_dof) gives a
+        context with nload = k; otherwise its load f."""
+        cases = pr.extra.get("load_cases")
         if precision is None:
             precision = VTS_MIXED if pr.extra.get("precision") == "mixed" else VTS_FP64
+        if cases is not None and len(cases) > 1:
+            f = np.ascontiguousarray(np.asarray(cases, dtype=np.float64).ravel())
+            return cls(pr.nx, pr.ny, pr.nz, pr.levels, pr.fixed, f, pr.V, pr.rho_lo, pr.rho_hi,
+                       pr.E, pr.nu, pr.h, precision, options, stream, nload=len(cases))
         return cls(pr.nx, pr.ny, pr.nz, pr.levels, pr.fixed, pr.f, pr.V, pr.rho_lo, pr.rho_hi,
                    pr.E, pr.nu, pr.h, precision, options, stream)
 
@@ -312,8 +327,8 @@ class Context:
 
     def apply_K(self, x, y):
         import torch
-        self._check(lib().vts_apply_K(self.h, _ptr(x, torch.float64, self.n_dof),
-                                      _ptr(y, torch.float64, self.n_dof)))
+        self._check(lib().vts_apply_K(self.h, _ptr(x, torch.float64, self.n_vec),
+                                      _ptr(y, torch.float64, self.n_vec)))
 
     def apply_K_f32(self, x, y):
         import torch
@@ -323,8 +338,8 @@ class Context:
     def apply_K_rho(self, rho, x, y):
         import torch
         self._check(lib().vts_apply_K_rho(self.h, _ptr(rho, torch.float64, self.m),
-                                          _ptr(x, torch.float64, self.n_dof),
-                                          _ptr(y, torch.float64, self.n_dof)))
+                                          _ptr(x, torch.float64, self.n_vec),
+                                          _ptr(y, torch.float64, self.n_vec)))
 
     def apply_K_rho_f32(self, rho, x, y):
         import torch
@@ -334,7 +349,7 @@ class Context:
 
     def element_energy(self, u, e):
         import torch
-        self._check(lib().vts_element_energy(self.h, _ptr(u, torch.float64, self.n_dof),
+        self._check(lib().vts_element_energy(self.h, _ptr(u, torch.float64, self.n_vec),
                                              _ptr(e, torch.float64, self.m)))
 
     def newton_setup(self):
@@ -342,8 +357,8 @@ class Context:
 
     def apply_S(self, x, y):
         import torch
-        self._check(lib().vts_apply_S(self.h, _ptr(x, torch.float64, self.n_dof + 1),
-                                      _ptr(y, torch.float64, self.n_dof + 1)))
+        self._check(lib().vts_apply_S(self.h, _ptr(x, torch.float64, self.n_vec + 1),
+                                      _ptr(y, torch.float64, self.n_vec + 1)))
 
     def apply_S_noalloc(self, x, y):
         import torch
@@ -352,8 +367,8 @@ class Context:
 
     def precondition(self, r, z):
         import torch
-        self._check(lib().vts_precondition(self.h, _ptr(r, torch.float64, self.n_dof + 1),
-                                           _ptr(z, torch.float64, self.n_dof + 1)))
+        self._check(lib().vts_precondition(self.h, _ptr(r, torch.float64, self.n_vec + 1),
+                                           _ptr(z, torch.float64, self.n_vec + 1)))
 
     # --- solvers ---------------------------------------------------------
     def solve_newton(self, eps_mr):
@@ -435,8 +450,8 @@ class Context:
     # --- state -----------------------------------------------------------
     def get_vector(self, which, out):
         import torch
-        n = {0: self.n_dof, 1: self.m, 2: self.m, 3: self.n_dof + 1, 4: self.n_dof + 1,
-             5: self.n_dof, 6: self.m, 7: self.m, 8: self.m, 9: self.m}[VEC.get(which, which)
+        n = {0: self.n_vec, 1: self.m, 2: self.m, 3: self.n_vec + 1, 4: self.n_vec + 1,
+             5: self.n_vec, 6: self.m, 7: self.m, 8: self.m, 9: self.m}[VEC.get(which, which)
                                                                       if isinstance(which, str) else which]
         w = VEC[which] if isinstance(which, str) else which
         self._check(lib().vts_get_vector(self.h, w, _ptr(out, torch.float64, n)))
@@ -444,8 +459,8 @@ class Context:
     def vector(self, which):
         import torch
         w = VEC[which] if isinstance(which, str) else which
-        n = {0: self.n_dof, 1: self.m, 2: self.m, 3: self.n_dof + 1, 4: self.n_dof + 1,
-             5: self.n_dof, 6: self.m, 7: self.m, 8: self.m, 9: self.m}[w]
+        n = {0: self.n_vec, 1: self.m, 2: self.m, 3: self.n_vec + 1, 4: self.n_vec + 1,
+             5: self.n_vec, 6: self.m, 7: self.m, 8: self.m, 9: self.m}[w]
         out = torch.empty(n, dtype=torch.float64, device="cuda")
         self.get_vector(w, out)
         torch.cuda.synchronize()
@@ -465,7 +480,7 @@ class Context:
     def state_dict(self):
         """Unpacks get_state() by the layout documented in vts.h."""
         b = self.get_state()
-        nd, m = self.n_dof, self.m
+        nd, m = self.n_vec, self.m
         o = STATE_HEAD
         out = {"u": b[o:o + nd], "alpha": b[o + nd]}
         o += nd + 1
@@ -480,7 +495,8 @@ class Context:
     @staticmethod
     def pack_state(d, n_dof, m):
         """Packs a state dict into the checkpoint layout; the counters
-        (outer, newton, minres) default to 0."""
+        (outer, newton, minres) default to 0.  n_dof is the length of u
+        (n_vec, load cases times n_dof, for several load cases)."""
         parts = [[STATE_MAGIC, STATE_VERSION, n_dof, m], np.asarray(d["u"], float), [d["alpha"]]]
         for name in ("nu_lo", "nu_hi", "rho", "mu_lo", "mu_hi", "p", "q_lo", "q_hi"):
             parts.append(np.asarray(d[name], float))

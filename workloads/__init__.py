@@ -33,7 +33,7 @@ __all__ = [
     "Problem", "cantilever_edge", "bar_rollers", "cantilever_points", "bridge_top",
     "paper_cantilever", "paper_bridge", "mg_levels", "config",
     "random_rho", "random_vector", "serving_requests", "CONFIGS",
-    "load_cases", "with_load_cases", "cantilever_two_loads", "multi_config",
+    "load_cases", "with_load_cases", "cantilever_two_loads", "multi_config", "point_cases",
 ]
 
 
@@ -150,12 +150,17 @@ def cantilever_points(nx, ny, nz, levels, npoints=3, seed=0, V=None,
     pr = Problem(name or f"cant-points-{nx}x{ny}x{nz}-l{levels}", nx, ny, nz,
                  levels, fixed, f, float(V), rho_lo, rho_hi)
     pr.extra["load_nodes_jk"] = picked
-    # the same point loads as separate load cases (the multi-load reading)
-    cases = np.zeros((npoints, fixed.size))
-    for c, (j, k) in enumerate(picked):
-        cases[c, 3 * (nx + (nx + 1) * (j + (ny + 1) * k)) + 2] = -1.0
-    pr.extra["load_cases"] = cases
     return pr
+
+
+def point_cases(pr: Problem) -> np.ndarray:
+    """The point loads of a `cantilever_points` problem as separate load
+    cases, (npoints, n_dof)."""
+    nx, ny = pr.nx, pr.ny
+    cases = np.zeros((len(pr.extra["load_nodes_jk"]), pr.n_dof))
+    for c, (j, k) in enumerate(pr.extra["load_nodes_jk"]):
+        cases[c, 3 * (nx + (nx + 1) * (j + (ny + 1) * k)) + 2] = -1.0
+    return cases
 
 
 def load_cases(pr: Problem) -> np.ndarray:
@@ -206,8 +211,8 @@ def multi_config(idx: int) -> Problem:
     if idx == 1:
         return cantilever_two_loads(64, 32, 32, 5, vol_frac=0.2, name="cant2load-64x32x32")
     if idx == 2:
-        return cantilever_points(192, 96, 96, 6, npoints=3, seed=0, vol_frac=0.1,
-                                 name="cant3case-192x96x96")
+        pr = cantilever_points(192, 96, 96, 6, npoints=3, seed=0, vol_frac=0.1)
+        return with_load_cases(pr, point_cases(pr), name="cant3case-192x96x96")
     raise ValueError(idx)
 
 
