@@ -583,6 +583,28 @@ def _timed(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def cpu_baseline_one_case_K(pr):
+    """The FP64 oracle's K(rho)u (element gather, dense element products,
+    scatter) applied once to one load case of `pr` on the host cores."""
+    import workloads as W
+    from oracle import fe
+    gr = fe.Grid(pr.nx, pr.ny, pr.nz, pr.fixed)
+    Ke = fe.element_stiffness(pr.E, pr.nu, pr.h)
+    rh = W.random_rho(pr.m, seed=1)
+    xv = W.random_vector(pr.n_dof, seed=2)
+    t = time.perf_counter()
+    fe.apply_K(gr, Ke, rh, xv)
+    cpu_s = time.perf_counter() - t
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count()
+    return {"value": pr.n_dof / cpu_s / 1e9, "unit": "GDOF/s (K(rho)u)", "cores": cores,
+            "kind": "oracle",
+            "sample": f"one application of the oracle's K(rho)u to one case of {pr.name} "
+                      f"({cpu_s:.2f} s)"}
+
+
 def multiload_ttk(torch, W, V, pr2):
     """Time-to-KKT (FP64) of a multi-load problem from the initial point (the
     second of two solves), and the KKT residual of the returned state on the
@@ -625,19 +647,21 @@ def multiload_ttk(torch, W, V, pr2):
 
 def multiload_run(a, torch, W, V):
     """Several load cases (the stacked problem, summed compliance), FP64.
-    (1) The three point loads of the 192x96x96 cantilever as three cases:
-    K(rho) on the three vectors in one launch over rotating (x, y) sets, with
-    its roofline against the compulsory bytes (read x and rho, write y);
-    the same three products by the single-load kernel, one launch per case;
-    at the initial Newton point the multigrid setup, the stacked S-apply,
-    one V-cycle and MINRES-MG iterations per second.  (2) Time-to-KKT of
-    the two-case 64x32x32 cantilever, KKT from the returned state on the
-    device.  (3) The CPU oracle's K(rho)u on one case of workload (1)."""
+    (1) The three point loads of the 192x96x96 cantilever as three cases, at
+    the initial Newton point: MINRES-MG iterations per second on the stacked
+    system (the line's value), the finest colour pass of its V-cycle (node
+    blocks of 9 unknowns; HIP events around every launch, algorithmic bytes)
+    as the roofline kernel, the multigrid setup, the stacked S-apply, one
+    V-cycle, and K(rho) on the three cases (one element-kernel launch per
+    case) over rotating (x, rho, y) sets.  (2) Time-to-KKT of the two-case
+    64x32x32 cantilever, KKT from the returned state on the device.  (3) The
+    CPU oracle's K(rho)u on one case of workload (1)."""
     import numpy as np
     pr = W.multi_config(2)
-    opts = V.default_options(max_minres=40)
-    ctx = V.Context.from_problem(pr, precision=V.VTS_FP64, options=opts)
-    k, nvec, m = ctx.nload, ctx.n_vec, ctx.m
+    its = 40
+    ctx = V.Context.from_problem(pr, precision=V.VTS_FP64,
+                                 options=V.default_options(max_minres=its))
+    k, nvec, m, nd = ctx.nload, ctx.n_vec, ctx.m, ctx.n_dof
     g = torch.Generator(device="cpu").manual_seed(1)
     sets = 4
     xs = [(torch.rand(nvec, generator=g, dtype=torch.float64) - 0.5).cuda() for _ in range(sets)]
@@ -652,25 +676,14 @@ def multiload_run(a, torch, W, V):
         ctx.apply_K_rho(rhos[q], xs[q], ys[q])
 
     k_ms = _timed(torch, batched, reps * sets)
-    alg = 2.0 * nvec * 8 + 8.0 * m
-    k_gbs = alg / (k_ms * 1e-3) / 1e9
+    k_launch_bytes = 16.0 * nd + 8.0 * m
+    k_gbs = k * k_launch_bytes / (k_ms * 1e-3) / 1e9
     k_gdofs = nvec / (k_ms * 1e-3) / 1e9
-    print(f"batched K(rho) on {k} cases: {k_ms * 1e3:.1f} us per launch, {k_gdofs:.2f} GDOF/s, "
-          f"{k_gbs:.0f} GB/s", file=sys.stderr, flush=True)
-    # the same products case by case through the single-load kernel
-    single = W.cantilever_points(pr.nx, pr.ny, pr.nz, pr.levels, npoints=3, seed=0, vol_frac=0.1)
-    ctx1 = V.Context.from_problem(single, precision=V.VTS_FP64)
-    nd = ctx1.n_dof
-
-    def per_case():
-        q = state["q"] = (state["q"] + 1) % sets
-        for l in range(k):
-            ctx1.apply_K_rho(rhos[q], xs[q][l * nd:(l + 1) * nd], ys[q][l * nd:(l + 1) * nd])
-
-    s_ms = _timed(torch, per_case, reps * sets)
-    ctx1.close()
-    del single
-    print(f"single-load K(rho), {k} launches: {s_ms * 1e3:.1f} us", file=sys.stderr, flush=True)
+    print(f"K(rho) on {k} cases: {k_ms * 1e3:.1f} us per call ({k} launches), {k_gdofs:.1f} "
+          f"GDOF/s, {k_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    for q in range(sets):
+        xs[q] = ys[q] = rhos[q] = None
+    torch.cuda.empty_cache()
     # the stacked Newton system at the initial point
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -680,17 +693,18 @@ def multiload_run(a, torch, W, V):
     r = (torch.rand(nvec + 1, generator=g, dtype=torch.float64) - 0.5).cuda()
     z = torch.empty_like(r)
     sa_ms = _timed(torch, lambda: ctx.apply_S(r, z), reps)
-    vc_ms = _timed(torch, lambda: ctx.precondition(r, z), max(reps // 2, 1))
+    vc_ms = _timed(torch, lambda: ctx.precondition(r, z), reps)
+    gs = profiled(ctx, "gs_fine", lambda: [ctx.precondition(r, z) for _ in range(reps)])
     torch.cuda.synchronize()
     t = time.perf_counter()
     st = ctx.solve_newton(0.0)
     torch.cuda.synchronize()
-    mr_rate = st["iterations"] / (time.perf_counter() - t)
-    print(f"setup {setup_s:.2f} s, S-apply {sa_ms * 1e3:.0f} us, V-cycle {vc_ms:.2f} ms, "
-          f"MINRES-MG {mr_rate:.1f} it/s", file=sys.stderr, flush=True)
+    mr_s = time.perf_counter() - t
+    mr_rate = st["iterations"] / mr_s
+    print(f"setup {setup_s:.2f} s, S-apply {sa_ms * 1e3:.0f} us, V-cycle {vc_ms:.2f} ms, finest "
+          f"colour pass {gs['avg_launch_ms'] * 1e3:.1f} us ({gs['gbs']:.0f} GB/s), MINRES-MG "
+          f"{mr_rate:.1f} it/s", file=sys.stderr, flush=True)
     ctx.close()
-    for q in range(sets):
-        xs[q] = ys[q] = rhos[q] = None
     torch.cuda.empty_cache()
 
     # (2) time-to-KKT of the two-case cantilever
@@ -700,18 +714,7 @@ def multiload_run(a, torch, W, V):
         ttk_out = multiload_ttk(torch, W, V, pr2)
 
     # (3) the oracle's K(rho)u on one case of workload (1)
-    from oracle import fe
-    gr = fe.Grid(pr.nx, pr.ny, pr.nz, pr.fixed)
-    Ke = fe.element_stiffness(pr.E, pr.nu, pr.h)
-    rh = W.random_rho(pr.m, seed=1)
-    xv = W.random_vector(pr.n_dof, seed=2)
-    t = time.perf_counter()
-    fe.apply_K(gr, Ke, rh, xv)
-    cpu_s = time.perf_counter() - t
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except Exception:
-        cores = os.cpu_count()
+    cpu = cpu_baseline_one_case_K(pr)
 
     # plain copies of 256 MiB: the scale reference of the traffic counters
     buf = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -721,25 +724,26 @@ def multiload_run(a, torch, W, V):
     torch.cuda.synchronize()
     del buf, dst
 
-    kern = "k_ml_apply<false>"
-    traffic = measured_traffic(pr.name, kern)
+    kern = f"k_ml_gs<{3 * k}, true>"
     line = {
-        "metric": "K(rho)u on k load cases, GDOF/s; stacked MINRES-MG iters/s; time-to-KKT 1e-6",
-        "value": k_gdofs, "unit": "GDOF/s (K(rho) on 3 cases in one launch, FP64)",
-        "n_gpus": 1, "steps": reps * sets, "warmup": 1, "ms_per_step": k_ms,
+        "metric": "MINRES-MG iterations/s on the stacked Newton system of k load cases",
+        "value": mr_rate, "unit": "iterations/s (FP64, 3 load cases, 192x96x96)",
+        "n_gpus": 1, "steps": st["iterations"], "warmup": 1, "ms_per_step": 1e3 * mr_s / max(st["iterations"], 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{pr.name} (the three point loads as three load cases)",
-                   "load_cases": k, "n_dof_per_case": pr.n_dof, "m": pr.m},
-        "roofline": {"bound": "hbm", "achieved": k_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": k_gbs / HBM_PEAK_GBS, "traffic": traffic, "kernel": kern,
-                     "algorithmic_bytes_per_launch": alg},
-        "cpu_baseline": {"value": pr.n_dof / cpu_s / 1e9, "unit": "GDOF/s", "cores": cores,
-                         "kind": "oracle",
-                         "sample": f"one application of the oracle's K(rho)u to one case of "
-                                   f"{pr.name} ({cpu_s:.2f} s)"},
+                   "load_cases": k, "n_dof_per_case": nd, "m": m},
+        "roofline": {"bound": "hbm", "achieved": gs["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gs["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(pr.name, kern),
+                     "kernel": kern, "algorithmic_bytes_per_launch": gs["bytes_per_launch"],
+                     "avg_launch_us": gs["avg_launch_ms"] * 1e3, "launches": gs["launches"]},
+        "cpu_baseline": cpu,
         "multiload": {
-            "batched_K_us": k_ms * 1e3, "single_load_K_3_launches_us": s_ms * 1e3,
+            "K_3_cases_us": k_ms * 1e3, "K_gdofs": k_gdofs,
+            "K_roofline": {"kernel": "k_apply_K_plane<double>", "achieved": k_gbs,
+                           "frac": k_gbs / HBM_PEAK_GBS,
+                           "traffic": measured_traffic("cant3pt-192x96x96",
+                                                       "k_apply_K_plane<double>")},
             "setup_s_initial_point": setup_s, "apply_S_us": sa_ms * 1e3,
             "vcycle_ms": vc_ms, "minres_mg_iters_per_s": mr_rate,
             "time_to_kkt": ttk_out,

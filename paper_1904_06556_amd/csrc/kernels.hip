@@ -76,6 +76,11 @@ void launch_apply_K_f64(Ctx& c, const double* rho, const double* x, double* y) {
         ml_apply_K(c, rho, x, y);
         return;
     }
+    launch_apply_K_case(c, rho, x, y);
+}
+
+// K(rho) x on one all-DOF vector (one load case)
+void launch_apply_K_case(Ctx& c, const double* rho, const double* x, double* y) {
     if (tile_ok(c)) {
         // algorithmic bytes: read x and rho, write y (8 B each entry); the
         // Dirichlet data (one mask byte per node) are not counted

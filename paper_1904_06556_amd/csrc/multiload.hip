@@ -12,12 +12,16 @@
 // be[(24 l + j) m + e].  The multigrid (Section 6) takes node blocks of
 // NB = 3k unknowns (a node over all cases): block row R = 3 l + c of node n
 // is entry l (3 nn) + 3 n + c of the level's stacked vector.  Its stencils
-// are assembled on every level, A[((q NB + R) NB + S) nn + n] with q the
-// neighbour offset (dx+1) + 3 (dy+1) + 9 (dz+1), node index fastest.  The
+// are assembled on every level, A[((q NB + R) NB + S) nn + p] with q the
+// neighbour offset (dx+1) + 3 (dy+1) + 9 (dz+1) and p the node's position in
+// colour-major order (the nodes of parity colour 0, then 1, ...), so that a
+// colour pass reads each row of its nodes as one contiguous segment.  The
 // finest stencil comes from (rho', w, b); coarse ones by Galerkin products
 // with the trilinear prolongation per case; block Gauss-Seidel in the eight
 // parity colours, alpha last (first) in the forward (backward) sweep; the
-// coarsest level by a dense Cholesky inverse.  Everything is FP64.
+// coarsest level by a dense Cholesky inverse.  Everything is FP64.  K(rho)
+// on the k cases is the single-load operator once per case: a fused
+// k-case element kernel would need k times the registers of that kernel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -188,15 +192,13 @@ k_ml_grad(int nx, int ny, int nz, int nl, int64_t ndof, const double* __restrict
     block_sum_store<1>(acc, partials, SL_G1SQ);
 }
 
-// Batched K(coef) on the k cases (one read of coef per element serves every
-// case), with RANK1 plus the rank-one terms sum_e wt_e b_{e,l}:
-//   y_l = mask(K(coef) x_l + sum_e wt_e b_{e,l}).
-template <bool RANK1>
+// The rank-one part of the stacked S-apply, added to y (masked):
+//   y_l += sum_e wt_e b_{e,l} at each node (one thread per node, every case).
+template <int NL>
 __global__ void __launch_bounds__(kThreads)
-k_ml_apply(int nx, int ny, int nz, int nl, int64_t ndof, const double* __restrict__ Ke,
-           const double* __restrict__ coef, const double* __restrict__ x,
-           const uint8_t* __restrict__ fixed, const double* __restrict__ be,
-           const double* __restrict__ wt, double* __restrict__ y) {
+k_ml_rank1(int nx, int ny, int nz, int64_t ndof, const double* __restrict__ be,
+           const double* __restrict__ wt, const uint8_t* __restrict__ fixed,
+           double* __restrict__ y) {
     const int NX = nx + 1, NY = ny + 1;
     const int64_t nn = (int64_t)NX * NY * (nz + 1);
     const int64_t m = (int64_t)nx * ny * nz;
@@ -205,9 +207,9 @@ k_ml_apply(int nx, int ny, int nz, int nl, int64_t ndof, const double* __restric
     const int i = (int)(n % NX);
     const int64_t t = n / NX;
     const int j = (int)(t % NY), k = (int)(t / NY);
-    double acc[kMaxLoads][3];
+    double acc[NL][3];
 #pragma unroll
-    for (int l = 0; l < kMaxLoads; ++l) acc[l][0] = acc[l][1] = acc[l][2] = 0.0;
+    for (int l = 0; l < NL; ++l) acc[l][0] = acc[l][1] = acc[l][2] = 0.0;
     for (int ez = -1; ez <= 0; ++ez) {
         const int kk = k + ez;
         if (kk < 0 || kk >= nz) continue;
@@ -219,43 +221,21 @@ k_ml_apply(int nx, int ny, int nz, int nl, int64_t ndof, const double* __restric
                 if (ii < 0 || ii >= nx) continue;
                 const int64_t e = ii + (int64_t)nx * (jj + (int64_t)ny * kk);
                 const int la = -ex - 2 * ey - 4 * ez;
-                const double* K0 = Ke + (3 * la) * 24;
-                const double r = coef[e];
-                const double q = RANK1 ? wt[e] : 0.0;
+                const double q = wt[e];
 #pragma unroll
-                for (int l = 0; l < kMaxLoads; ++l) {
-                    if (l >= nl) break;
-                    const double* xl = x + l * ndof;
-                    double s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-                    for (int b = 0; b < 8; ++b) {
-                        const int64_t nb =
-                            node_id(ii + (b & 1), jj + ((b >> 1) & 1), kk + (b >> 2), NX, NY);
-                        const double x0 = fixed[3 * nb] ? 0.0 : xl[3 * nb];
-                        const double x1 = fixed[3 * nb + 1] ? 0.0 : xl[3 * nb + 1];
-                        const double x2 = fixed[3 * nb + 2] ? 0.0 : xl[3 * nb + 2];
-                        s0 += K0[3 * b] * x0 + K0[3 * b + 1] * x1 + K0[3 * b + 2] * x2;
-                        s1 += K0[24 + 3 * b] * x0 + K0[24 + 3 * b + 1] * x1 + K0[24 + 3 * b + 2] * x2;
-                        s2 += K0[48 + 3 * b] * x0 + K0[48 + 3 * b + 1] * x1 + K0[48 + 3 * b + 2] * x2;
-                    }
-                    acc[l][0] += r * s0;
-                    acc[l][1] += r * s1;
-                    acc[l][2] += r * s2;
-                    if (RANK1) {
-                        const double* bl = be + ((int64_t)l * 24 + 3 * la) * m + e;
-                        acc[l][0] += q * bl[0];
-                        acc[l][1] += q * bl[m];
-                        acc[l][2] += q * bl[2 * m];
-                    }
+                for (int l = 0; l < NL; ++l) {
+                    const double* bl = be + ((int64_t)l * 24 + 3 * la) * m + e;
+                    acc[l][0] += q * bl[0];
+                    acc[l][1] += q * bl[m];
+                    acc[l][2] += q * bl[2 * m];
                 }
             }
         }
     }
 #pragma unroll
-    for (int l = 0; l < kMaxLoads; ++l) {
-        if (l >= nl) break;
-        for (int c = 0; c < 3; ++c) y[l * ndof + 3 * n + c] = fixed[3 * n + c] ? 0.0 : acc[l][c];
-    }
+    for (int l = 0; l < NL; ++l)
+        for (int c = 0; c < 3; ++c)
+            if (!fixed[3 * n + c]) y[l * ndof + 3 * n + c] += acc[l][c];
 }
 
 // S pass 1: wt_e = w_e (sum_l b_{e,l}^T x_{l,e} - beta), partial sums of wt
@@ -376,6 +356,22 @@ __device__ __forceinline__ void node_ijk(int64_t n, int NX, int NY, int& i, int&
     k = (int)(t / NY);
 }
 
+// nodes of parity colour c = (i&1) + 2 (j&1) + 4 (k&1) on a grid of NX x NY x NZ nodes
+__device__ __forceinline__ int64_t colour_count(int c, int NX, int NY, int NZ) {
+    return (int64_t)((NX - (c & 1) + 1) / 2) * ((NY - ((c >> 1) & 1) + 1) / 2) *
+           ((NZ - (c >> 2) + 1) / 2);
+}
+
+// colour-major position of node (i, j, k): the nodes of the lower colours,
+// then (i, j, k)'s index within its colour (x fastest)
+__device__ __forceinline__ int64_t cm_index(int i, int j, int k, int NX, int NY, int NZ) {
+    const int c = (i & 1) | ((j & 1) << 1) | ((k & 1) << 2);
+    int64_t off = 0;
+    for (int q = 0; q < c; ++q) off += colour_count(q, NX, NY, NZ);
+    const int mx = (NX - (c & 1) + 1) / 2, my = (NY - ((c >> 1) & 1) + 1) / 2;
+    return off + (i >> 1) + (int64_t)mx * ((j >> 1) + (int64_t)my * (k >> 1));
+}
+
 // finest stencil: one thread per (node, neighbour offset q, block row R)
 template <int NB>
 __global__ void __launch_bounds__(kThreads)
@@ -429,8 +425,9 @@ k_ml_stencil(int nx, int ny, int nz, const double* __restrict__ Ke,
         for (int S = 0; S < NB; ++S)
             if (fixed[3 * n2 + S % 3]) acc[S] = 0.0;
     }
+    const int64_t pn = cm_index(i, j, k, NX, NY, NZ);
 #pragma unroll
-    for (int S = 0; S < NB; ++S) A[(((int64_t)q * NB + R) * NB + S) * nn + n] = acc[S];
+    for (int S = 0; S < NB; ++S) A[(((int64_t)q * NB + R) * NB + S) * nn + pn] = acc[S];
 }
 
 // finest alpha column: -sum_e w_e b_{e,l} at the node (masked)
@@ -466,7 +463,7 @@ k_ml_acol_fine(int nx, int ny, int nz, int NB, const double* __restrict__ w,
             }
         }
     }
-    ac[(int64_t)R * nn + n] = s;
+    ac[(int64_t)R * nn + cm_index(i, j, k, NX, NY, nz + 1)] = s;
 }
 
 // Galerkin coarse stencil P^T A P: one thread per (coarse node I, offset q,
@@ -522,8 +519,8 @@ k_ml_galerkin(int cnx, int cny, int cnz, const double* __restrict__ Af,
                                 if (fi2 < 0 || fi2 >= FX || ox < -1 || ox > 1) continue;
                                 const double wgt = wy * (ax ? 0.5 : 1.0) * (bx ? 0.5 : 1.0);
                                 const int qf = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
-                                const int64_t nf = node_id(fi, fj, fk, FX, FY);
-                                const double* row = Af + (((int64_t)qf * NB + R) * NB) * nnf + nf;
+                                const int64_t pf = cm_index(fi, fj, fk, FX, FY, FZ);
+                                const double* row = Af + (((int64_t)qf * NB + R) * NB) * nnf + pf;
 #pragma unroll
                                 for (int S = 0; S < NB; ++S) acc[S] += wgt * row[(int64_t)S * nnf];
                             }
@@ -537,8 +534,9 @@ k_ml_galerkin(int cnx, int cny, int cnz, const double* __restrict__ Af,
         for (int S = 0; S < NB; ++S)
             if (cfixed[3 * J + S % 3]) acc[S] = 0.0;
     }
+    const int64_t pI = cm_index(ci, cj, ck, CX, CY, CZ);
 #pragma unroll
-    for (int S = 0; S < NB; ++S) Ac[(((int64_t)q * NB + R) * NB + S) * nnc + I] = acc[S];
+    for (int S = 0; S < NB; ++S) Ac[(((int64_t)q * NB + R) * NB + S) * nnc + pI] = acc[S];
 }
 
 // coarse alpha column P^T c (masked)
@@ -567,12 +565,12 @@ k_ml_acol_coarse(int cnx, int cny, int cnz, int NB, const double* __restrict__ a
                     const int fi = 2 * ci + ax;
                     if (fi < 0 || fi >= FX) continue;
                     const double wgt = (az ? 0.5 : 1.0) * (ay ? 0.5 : 1.0) * (ax ? 0.5 : 1.0);
-                    s += wgt * acf[(int64_t)R * nnf + node_id(fi, fj, fk, FX, FY)];
+                    s += wgt * acf[(int64_t)R * nnf + cm_index(fi, fj, fk, FX, FY, FZ)];
                 }
             }
         }
     }
-    acc_[(int64_t)R * nnc + I] = s;
+    acc_[(int64_t)R * nnc + cm_index(ci, cj, ck, CX, CY, CZ)] = s;
 }
 
 // inverse of each node's diagonal block (identity on fixed components), by
@@ -580,16 +578,22 @@ k_ml_acol_coarse(int cnx, int cny, int cnz, int NB, const double* __restrict__ a
 // definite); flag = 1 on a non-positive pivot
 template <int NB>
 __global__ void __launch_bounds__(kThreads)
-k_ml_blockinv(int64_t nn, const double* __restrict__ A, const uint8_t* __restrict__ fixed,
-              double* __restrict__ Dinv, int* __restrict__ flag) {
+k_ml_blockinv(int nx, int ny, int nz, const double* __restrict__ A,
+              const uint8_t* __restrict__ fixed, double* __restrict__ Dinv,
+              int* __restrict__ flag) {
+    const int NX = nx + 1, NY = ny + 1, NZ = nz + 1;
+    const int64_t nn = (int64_t)NX * NY * NZ;
     const int64_t n = gid();
     if (n >= nn) return;
+    int i, j, k;
+    node_ijk(n, NX, NY, i, j, k);
+    const int64_t pn = cm_index(i, j, k, NX, NY, NZ);
     double D[NB][NB], X[NB][NB];
     for (int R = 0; R < NB; ++R) {
         const bool fr = fixed[3 * n + R % 3];
         for (int S = 0; S < NB; ++S) {
             const bool fs = fixed[3 * n + S % 3];
-            double v = A[(((int64_t)13 * NB + R) * NB + S) * nn + n];
+            double v = A[(((int64_t)13 * NB + R) * NB + S) * nn + pn];
             if (fr || fs) v = (R == S) ? 1.0 : 0.0;
             D[R][S] = v;
             X[R][S] = (R == S) ? 1.0 : 0.0;
@@ -615,7 +619,7 @@ k_ml_blockinv(int64_t nn, const double* __restrict__ A, const uint8_t* __restric
     }
     if (bad) *flag = 1;
     for (int R = 0; R < NB; ++R)
-        for (int S = 0; S < NB; ++S) Dinv[((int64_t)R * NB + S) * nn + n] = X[R][S];
+        for (int S = 0; S < NB; ++S) Dinv[((int64_t)R * NB + S) * nn + pn] = X[R][S];
 }
 
 // dense coarsest matrix: row p (free DOF rows[p]) from the stencil, alpha last
@@ -639,6 +643,7 @@ k_ml_dense(int nx, int ny, int nz, const double* __restrict__ A, const double* _
     const int R = 3 * l + (int)(rem % 3);
     int i, j, k;
     node_ijk(n, NX, NY, i, j, k);
+    const int64_t pn = cm_index(i, j, k, NX, NY, NZ);
     for (int q = 0; q < 27; ++q) {
         const int i2 = i + q % 3 - 1, j2 = j + (q / 3) % 3 - 1, k2 = k + q / 9 - 1;
         if (i2 < 0 || i2 >= NX || j2 < 0 || j2 >= NY || k2 < 0 || k2 >= NZ) continue;
@@ -646,10 +651,10 @@ k_ml_dense(int nx, int ny, int nz, const double* __restrict__ A, const double* _
         for (int S = 0; S < NB; ++S) {
             const int col = cmap[vidx(S, n2, nn)];
             if (col < 0) continue;
-            A0[(int64_t)p * nc + col] = A[(((int64_t)q * NB + R) * NB + S) * nn + n];
+            A0[(int64_t)p * nc + col] = A[(((int64_t)q * NB + R) * NB + S) * nn + pn];
         }
     }
-    const double a = ac[(int64_t)R * nn + n];
+    const double a = ac[(int64_t)R * nn + pn];
     A0[(int64_t)p * nc + nc - 1] = a;
     A0[(int64_t)(nc - 1) * nc + p] = a;
 }
@@ -719,95 +724,105 @@ k_ml_dense_apply(const double* __restrict__ Ainv, const int* __restrict__ rows, 
     z[rows[p]] = s;
 }
 
-// one colour of block Gauss-Seidel: nodes of parity colour `col`
-template <int NB>
-__global__ void __launch_bounds__(kThreads)
+// One colour of block Gauss-Seidel on the nodes of parity colour `col`.  A
+// workgroup takes kMlGsNodes consecutive nodes of the colour (consecutive in
+// the colour-major arrays) and NB block rows: thread (R, slot) forms row R of
+// its node's residual r - A z - ac z_alpha, so the threads of one row read
+// one contiguous segment per coefficient; the rows meet in LDS for the block
+// solve dz = Dinv res, and thread (R, slot) adds row R of dz.  TOP marks the
+// finest level's instantiation (the same code; a kernel of its own for the
+// profiler).
+constexpr int kMlGsNodes = 16;
+
+template <int NB, bool TOP>
+__global__ void __launch_bounds__(kMlGsNodes * 12)
 k_ml_gs(int nx, int ny, int nz, int col, const double* __restrict__ A,
         const double* __restrict__ ac, const double* __restrict__ Dinv,
         const double* __restrict__ r, double* __restrict__ z) {
+    __shared__ double sres[NB][kMlGsNodes];
     const int NX = nx + 1, NY = ny + 1, NZ = nz + 1;
     const int64_t nn = (int64_t)NX * NY * NZ;
     const int cx = col & 1, cy = (col >> 1) & 1, cz = col >> 2;
     const int mx = (NX - cx + 1) / 2, my = (NY - cy + 1) / 2, mz = (NZ - cz + 1) / 2;
-    const int64_t t = gid();
-    if (t >= (int64_t)mx * my * mz) return;
-    const int i = 2 * (int)(t % mx) + cx;
-    const int64_t t2 = t / mx;
-    const int j = 2 * (int)(t2 % my) + cy, k = 2 * (int)(t2 / my) + cz;
-    const int64_t n = node_id(i, j, k, NX, NY);
-    const double za = z[(int64_t)NB * nn];
-    double res[NB];
-#pragma unroll
-    for (int R = 0; R < NB; ++R) res[R] = r[vidx(R, n, nn)] - ac[(int64_t)R * nn + n] * za;
-    for (int q = 0; q < 27; ++q) {
-        const int i2 = i + q % 3 - 1, j2 = j + (q / 3) % 3 - 1, k2 = k + q / 9 - 1;
-        if (i2 < 0 || i2 >= NX || j2 < 0 || j2 >= NY || k2 < 0 || k2 >= NZ) continue;
-        const int64_t n2 = node_id(i2, j2, k2, NX, NY);
-        double zs[NB];
-#pragma unroll
-        for (int S = 0; S < NB; ++S) zs[S] = z[vidx(S, n2, nn)];
-#pragma unroll
-        for (int R = 0; R < NB; ++R) {
-            const double* row = A + (((int64_t)q * NB + R) * NB) * nn + n;
+    const int slot = (int)(threadIdx.x % kMlGsNodes);
+    const int R = (int)(threadIdx.x / kMlGsNodes);
+    const int64_t g = (int64_t)blockIdx.x * kMlGsNodes + slot;
+    const bool act = g < (int64_t)mx * my * mz;
+    int64_t off = 0;
+    for (int q = 0; q < col; ++q) off += colour_count(q, NX, NY, NZ);
+    const int64_t pn = off + g;
+    int i = 0, j = 0, k = 0;
+    int64_t n = 0;
+    double res = 0.0;
+    if (act) {
+        i = 2 * (int)(g % mx) + cx;
+        const int64_t g2 = g / mx;
+        j = 2 * (int)(g2 % my) + cy;
+        k = 2 * (int)(g2 / my) + cz;
+        n = node_id(i, j, k, NX, NY);
+        res = r[vidx(R, n, nn)] - ac[(int64_t)R * nn + pn] * z[(int64_t)NB * nn];
+        for (int q = 0; q < 27; ++q) {
+            const int i2 = i + q % 3 - 1, j2 = j + (q / 3) % 3 - 1, k2 = k + q / 9 - 1;
+            if (i2 < 0 || i2 >= NX || j2 < 0 || j2 >= NY || k2 < 0 || k2 >= NZ) continue;
+            const int64_t n2 = node_id(i2, j2, k2, NX, NY);
+            const double* row = A + (((int64_t)q * NB + R) * NB) * nn + pn;
             double s = 0.0;
 #pragma unroll
-            for (int S = 0; S < NB; ++S) s += row[(int64_t)S * nn] * zs[S];
-            res[R] -= s;
+            for (int S = 0; S < NB; ++S) s += row[(int64_t)S * nn] * z[vidx(S, n2, nn)];
+            res -= s;
         }
     }
-#pragma unroll
-    for (int R = 0; R < NB; ++R) {
+    sres[R][slot] = res;
+    __syncthreads();
+    if (act) {
         double d = 0.0;
 #pragma unroll
-        for (int S = 0; S < NB; ++S) d += Dinv[((int64_t)R * NB + S) * nn + n] * res[S];
+        for (int S = 0; S < NB; ++S) d += Dinv[((int64_t)R * NB + S) * nn + pn] * sres[S][slot];
         z[vidx(R, n, nn)] += d;
     }
 }
 
-// t = r - A z - ac z_alpha on every node
+// t = r - A z - ac z_alpha, one thread per (node, block row), node fastest
 template <int NB>
 __global__ void __launch_bounds__(kThreads)
 k_ml_resid(int nx, int ny, int nz, const double* __restrict__ A, const double* __restrict__ ac,
            const double* __restrict__ r, const double* __restrict__ z, double* __restrict__ t_) {
     const int NX = nx + 1, NY = ny + 1, NZ = nz + 1;
     const int64_t nn = (int64_t)NX * NY * NZ;
-    const int64_t n = gid();
-    if (n >= nn) return;
+    const int64_t t = gid();
+    if (t >= nn * NB) return;
+    const int64_t n = t % nn;
+    const int R = (int)(t / nn);
     int i, j, k;
     node_ijk(n, NX, NY, i, j, k);
-    const double za = z[(int64_t)NB * nn];
-    double res[NB];
-#pragma unroll
-    for (int R = 0; R < NB; ++R) res[R] = r[vidx(R, n, nn)] - ac[(int64_t)R * nn + n] * za;
+    const int64_t pn = cm_index(i, j, k, NX, NY, NZ);
+    double res = r[vidx(R, n, nn)] - ac[(int64_t)R * nn + pn] * z[(int64_t)NB * nn];
     for (int q = 0; q < 27; ++q) {
         const int i2 = i + q % 3 - 1, j2 = j + (q / 3) % 3 - 1, k2 = k + q / 9 - 1;
         if (i2 < 0 || i2 >= NX || j2 < 0 || j2 >= NY || k2 < 0 || k2 >= NZ) continue;
         const int64_t n2 = node_id(i2, j2, k2, NX, NY);
-        double zs[NB];
+        const double* row = A + (((int64_t)q * NB + R) * NB) * nn + pn;
+        double s = 0.0;
 #pragma unroll
-        for (int S = 0; S < NB; ++S) zs[S] = z[vidx(S, n2, nn)];
-#pragma unroll
-        for (int R = 0; R < NB; ++R) {
-            const double* row = A + (((int64_t)q * NB + R) * NB) * nn + n;
-            double s = 0.0;
-#pragma unroll
-            for (int S = 0; S < NB; ++S) s += row[(int64_t)S * nn] * zs[S];
-            res[R] -= s;
-        }
+        for (int S = 0; S < NB; ++S) s += row[(int64_t)S * nn] * z[vidx(S, n2, nn)];
+        res -= s;
     }
-#pragma unroll
-    for (int R = 0; R < NB; ++R) t_[vidx(R, n, nn)] = res[R];
+    t_[vidx(R, n, nn)] = res;
 }
 
 // partial sums of ac^T z (the alpha row without its diagonal)
 __global__ void __launch_bounds__(kThreads)
-k_ml_acol_dot(int64_t nn, int NB, const double* __restrict__ ac, const double* __restrict__ z,
-              double* partials) {
+k_ml_acol_dot(int nx, int ny, int nz, int NB, const double* __restrict__ ac,
+              const double* __restrict__ z, double* partials) {
+    const int NX = nx + 1, NY = ny + 1, NZ = nz + 1;
+    const int64_t nn = (int64_t)NX * NY * NZ;
     double acc[1] = {0.0};
     for (int64_t t = gid(); t < nn * NB; t += (int64_t)gridDim.x * blockDim.x) {
         const int R = (int)(t / nn);
         const int64_t n = t % nn;
-        acc[0] += ac[t] * z[vidx(R, n, nn)];
+        int i, j, k;
+        node_ijk(n, NX, NY, i, j, k);
+        acc[0] += ac[(int64_t)R * nn + cm_index(i, j, k, NX, NY, NZ)] * z[vidx(R, n, nn)];
     }
     block_sum_store<1>(acc, partials, 0);
 }
@@ -919,8 +934,8 @@ void build_levels(Ctx& c, MlHierarchy& H) {
     }
     for (int k = 1; k < H.L; ++k) {
         MlLevel& Lk = H.lv[k];
-        hipLaunchKernelGGL(k_ml_blockinv<NB>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s, Lk.nn,
-                           Lk.A, Lk.fixed, Lk.Dinv, H.flag);
+        hipLaunchKernelGGL(k_ml_blockinv<NB>, dim3(grid_of(Lk.nn)), dim3(kThreads), 0, c.s, Lk.nx,
+                           Lk.ny, Lk.nz, Lk.A, Lk.fixed, Lk.Dinv, H.flag);
     }
     MlLevel& C0 = H.lv[0];
     const int64_t n0 = (int64_t)H.nc * H.nc;
@@ -936,8 +951,8 @@ void alpha_row(Ctx& c, MlHierarchy& H, const MlLevel& Lv, const double* r, doubl
                int mode) {
     const int64_t n = Lv.nn * H.NB;
     const int g = red_grid(n);
-    hipLaunchKernelGGL(k_ml_acol_dot, dim3(g), dim3(kThreads), 0, c.s, Lv.nn, H.NB, Lv.ac, z,
-                       H.part);
+    hipLaunchKernelGGL(k_ml_acol_dot, dim3(g), dim3(kThreads), 0, c.s, Lv.nx, Lv.ny, Lv.nz, H.NB,
+                       Lv.ac, z, H.part);
     hipLaunchKernelGGL(k_ml_fin, dim3(1), dim3(kThreads), 0, c.s, H.part, g, 0, 0u, H.red);
     hipLaunchKernelGGL(k_ml_alpha, dim3(1), dim3(64), 0, c.s, (int64_t)H.NB * Lv.nn, c.sum_w,
                        H.red, r, z, t, mode);
@@ -954,16 +969,31 @@ void vcycle_level(Ctx& c, MlHierarchy& H, int k, const double* r, double* z) {
         return;
     }
     const int NX = Lv.nx + 1, NY = Lv.ny + 1, NZ = Lv.nz + 1;
-    auto colour_grid = [&](int col) {
+    auto colour_nodes = [&](int col) {
         const int cx = col & 1, cy = (col >> 1) & 1, cz = col >> 2;
-        const int64_t cnt = (int64_t)((NX - cx + 1) / 2) * ((NY - cy + 1) / 2) * ((NZ - cz + 1) / 2);
-        return grid_of(cnt);
+        return (int64_t)((NX - cx + 1) / 2) * ((NY - cy + 1) / 2) * ((NZ - cz + 1) / 2);
     };
-    for (int col = 0; col < 8; ++col)
-        hipLaunchKernelGGL(k_ml_gs<NB>, dim3(colour_grid(col)), dim3(kThreads), 0, c.s, Lv.nx,
-                           Lv.ny, Lv.nz, col, Lv.A, Lv.ac, Lv.Dinv, r, z);
+    // the finest level's colour passes are one kernel class of the profiler:
+    // algorithmic bytes = the colour's stencil rows, inverse blocks, r, alpha
+    // column and z (read and written), and the z of every other node
+    const bool top = k == H.L - 1;
+    auto gs = [&](int col) {
+        const int64_t cnt = colour_nodes(col);
+        const bool prof = top && prof_begin(c, VTS_PROF_GS_FINE);
+        const dim3 grid((unsigned)((cnt + kMlGsNodes - 1) / kMlGsNodes)), block(kMlGsNodes * NB);
+        if (top)
+            hipLaunchKernelGGL((k_ml_gs<NB, true>), grid, block, 0, c.s, Lv.nx, Lv.ny, Lv.nz, col,
+                               Lv.A, Lv.ac, Lv.Dinv, r, z);
+        else
+            hipLaunchKernelGGL((k_ml_gs<NB, false>), grid, block, 0, c.s, Lv.nx, Lv.ny, Lv.nz, col,
+                               Lv.A, Lv.ac, Lv.Dinv, r, z);
+        if (prof)
+            prof_end(c, 8.0 * ((double)cnt * (28.0 * NB * NB + 4.0 * NB) +
+                               (double)NB * (double)(Lv.nn - cnt)), 1);
+    };
+    for (int col = 0; col < 8; ++col) gs(col);
     alpha_row(c, H, Lv, r, z, nullptr, 0);
-    hipLaunchKernelGGL(k_ml_resid<NB>, dim3(grid_of(Lv.nn)), dim3(kThreads), 0, c.s, Lv.nx,
+    hipLaunchKernelGGL(k_ml_resid<NB>, dim3(grid_of(Lv.nn * NB)), dim3(kThreads), 0, c.s, Lv.nx,
                        Lv.ny, Lv.nz, Lv.A, Lv.ac, r, z, Lv.t);
     alpha_row(c, H, Lv, r, z, Lv.t, 1);
     const MlLevel& C = H.lv[k - 1];
@@ -973,9 +1003,7 @@ void vcycle_level(Ctx& c, MlHierarchy& H, int k, const double* r, double* z) {
     hipLaunchKernelGGL(k_ml_prolong<NB>, dim3(grid_of(Lv.nn)), dim3(kThreads), 0, c.s, C.nx,
                        C.ny, C.nz, C.z, Lv.fixed, z);
     alpha_row(c, H, Lv, r, z, nullptr, 0);
-    for (int col = 7; col >= 0; --col)
-        hipLaunchKernelGGL(k_ml_gs<NB>, dim3(colour_grid(col)), dim3(kThreads), 0, c.s, Lv.nx,
-                           Lv.ny, Lv.nz, col, Lv.A, Lv.ac, Lv.Dinv, r, z);
+    for (int col = 7; col >= 0; --col) gs(col);
 }
 
 }  // namespace
@@ -1008,18 +1036,34 @@ void ml_launch_grad(Ctx& c) {
     fin(c, g, SL_G1SQ, 1, 0u);
 }
 
+// K(coef) on the k cases: the single-load operator (the plane-marching
+// element kernel) once per case
 void ml_apply_K(Ctx& c, const double* coef, const double* x, double* y) {
-    hipLaunchKernelGGL(k_ml_apply<false>, dim3(grid_of(c.nn)), dim3(kThreads), 0, c.s, c.nx, c.ny,
-                       c.nz, c.nl, c.ndof, c.Ke, coef, x, c.fixed, (const double*)nullptr,
-                       (const double*)nullptr, y);
+    for (int l = 0; l < c.nl; ++l) launch_apply_K_case(c, coef, x + l * c.ndof, y + l * c.ndof);
 }
 
+// S [x; beta]: t_e (coupling the cases) and its sum, K(rho') x_l per case,
+// then the rank-one terms added, and the alpha entry -sum wt
 void ml_apply_S(Ctx& c, const double* x, double* y) {
     const int g = red_grid(c.m);
     hipLaunchKernelGGL(k_ml_tdot, dim3(g), dim3(kThreads), 0, c.s, c.nx, c.ny, c.nz, c.nl, c.ndof,
                        c.be, c.w, x, c.fixed, c.wt, c.partials);
-    hipLaunchKernelGGL(k_ml_apply<true>, dim3(grid_of(c.nn)), dim3(kThreads), 0, c.s, c.nx, c.ny,
-                       c.nz, c.nl, c.ndof, c.Ke, c.r1, x, c.fixed, c.be, c.wt, y);
+    ml_apply_K(c, c.r1, x, y);
+    const dim3 gn(grid_of(c.nn));
+    switch (c.nl) {
+        case 2:
+            hipLaunchKernelGGL(k_ml_rank1<2>, gn, dim3(kThreads), 0, c.s, c.nx, c.ny, c.nz, c.ndof,
+                               c.be, c.wt, c.fixed, y);
+            break;
+        case 3:
+            hipLaunchKernelGGL(k_ml_rank1<3>, gn, dim3(kThreads), 0, c.s, c.nx, c.ny, c.nz, c.ndof,
+                               c.be, c.wt, c.fixed, y);
+            break;
+        default:
+            hipLaunchKernelGGL(k_ml_rank1<4>, gn, dim3(kThreads), 0, c.s, c.nx, c.ny, c.nz, c.ndof,
+                               c.be, c.wt, c.fixed, y);
+            break;
+    }
     fin(c, g, SL_WT, 1, 0u);
     hipLaunchKernelGGL(k_ml_store_neg, dim3(1), dim3(64), 0, c.s, c.red, (int)SL_WT, y + c.nvec);
 }

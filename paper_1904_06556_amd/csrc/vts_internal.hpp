@@ -351,6 +351,7 @@ void galerkin_child_matrices(const double* Ke, const double* Q, double* Mc);
 
 // launchers (kernels.hip); all asynchronous on ctx.s
 void launch_apply_K_f64(Ctx& c, const double* rho, const double* x, double* y);
+void launch_apply_K_case(Ctx& c, const double* rho, const double* x, double* y);  // one case
 void launch_apply_K_f32(Ctx& c, const float* rho, const float* x, float* y);
 void launch_energy(Ctx& c, const double* u, double* e);
 void launch_eval(Ctx& c);                    // e, be, coefficients, sums -> red[0..]

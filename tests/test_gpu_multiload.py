@@ -4,7 +4,8 @@ gradient and the reduced right-hand side, the batched K(rho) on k vectors,
 the S-apply of the stacked system (3.12), one V-cycle with 3k x 3k node
 blocks (FP64, 1e-10), one Newton step, and whole solves (KKT <= 1e-6 from
 the returned (rho, U, alpha) on the host, compliance against the oracle's
-run).  Cases k = 2 and 3 (node blocks of 6 and 9) on 1- to 3-level
+run), and a checkpoint round trip.  Cases k = 2, 3 and 4 (node blocks of 6, 9
+and 12) on 1- to 3-level
 hierarchies, the benchmark's two-case 64x32x32 cantilever for the
 operators, and the proportional-cases property (f, c f) == one load
 sqrt(1 + c^2) f on the GPU itself."""
@@ -52,8 +53,19 @@ def three_loads(nx, ny, nz, levels):
     return W.with_load_cases(pr, [*W.load_cases(pr), third], name=f"cant3load-{nx}x{ny}x{nz}")
 
 
+def four_loads(nx, ny, nz, levels):
+    """The three cases above plus a seeded fourth on the top face (z)."""
+    pr = three_loads(nx, ny, nz, levels)
+    rng = np.random.default_rng(8)
+    fourth = np.zeros(pr.n_dof)
+    top = np.nonzero(np.arange(pr.n_nodes) // ((nx + 1) * (ny + 1)) == nz)[0]
+    fourth[3 * top + 2] = rng.uniform(-1.0, 0.0, top.size)
+    return W.with_load_cases(pr, [*W.load_cases(pr), fourth], name=f"cant4load-{nx}x{ny}x{nz}")
+
+
 CASES = {
     "k2-8x4x4-l3": lambda: W.cantilever_two_loads(8, 4, 4, 3),
+    "k4-8x4x4-l2": lambda: four_loads(8, 4, 4, 2),
     "k2-8x4x4-l1": lambda: W.cantilever_two_loads(8, 4, 4, 1),
     "k3-8x4x4-l2": lambda: three_loads(8, 4, 4, 2),
     "k2-16x8x8-l3": lambda: W.multi_config(0),
@@ -285,3 +297,22 @@ def test_multiload_argument_errors():
         ctx.apply_S(x, torch.empty_like(x))
     assert ei.value.status == V.VTS_ESTATE
     ctx.close()
+
+
+def test_multiload_checkpoint_resumes_bitwise():
+    """vts_get_state / vts_set_state carry every case of u: a context resumed
+    from a checkpoint takes the same Newton step as the original."""
+    pr = W.cantilever_two_loads(8, 4, 4, 3)
+    say("multi-load checkpoint", pr.name)
+    a = V.Context.from_problem(pr, precision=V.VTS_FP64)
+    a.newton_step()
+    a.newton_step()
+    buf = a.get_state()
+    assert buf.size == 4 + a.n_vec + 1 + 8 * a.m + 5
+    b = V.Context.from_problem(pr, precision=V.VTS_FP64)
+    b.set_state(buf)
+    sa, sb = a.newton_step(), b.newton_step()
+    assert sa == sb
+    assert np.array_equal(a.get_state(), b.get_state())
+    a.close()
+    b.close()
