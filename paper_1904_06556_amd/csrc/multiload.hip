@@ -732,7 +732,7 @@ k_ml_dense_apply(const double* __restrict__ Ainv, const int* __restrict__ rows, 
 // solve dz = Dinv res, and thread (R, slot) adds row R of dz.  TOP marks the
 // finest level's instantiation (the same code; a kernel of its own for the
 // profiler).
-constexpr int kMlGsNodes = 16;
+constexpr int kMlGsNodes = 32;
 
 template <int NB, bool TOP>
 __global__ void __launch_bounds__(kMlGsNodes * 12)
@@ -783,6 +783,9 @@ k_ml_gs(int nx, int ny, int nz, int col, const double* __restrict__ A,
 }
 
 // t = r - A z - ac z_alpha, one thread per (node, block row), node fastest
+// in the natural order (z read and t written in runs; the coefficients of
+// consecutive nodes come from the two colour-major ranges of the row's two
+// x parities)
 template <int NB>
 __global__ void __launch_bounds__(kThreads)
 k_ml_resid(int nx, int ny, int nz, const double* __restrict__ A, const double* __restrict__ ac,
