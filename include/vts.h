@@ -235,7 +235,9 @@ vts_status vts_reset(vts_ctx* ctx);
 
 /* Device bytes vts_create would allocate for this problem (for admission):
  * an upper bound of vts_allocated_bytes, counted in 256-byte granules.
- * Returns 0 for an invalid problem. */
+ * Returns 0 for an invalid problem and for a problem with several load
+ * cases (those are not admitted to server pools; vts_allocated_bytes gives
+ * a created context's size). */
 size_t vts_footprint_bytes(const vts_problem* pr, const vts_options* opt);
 
 /* Device bytes this context holds (256-byte granules). */
