@@ -72,6 +72,10 @@ class Options:
     kkt_tol: float = 1e-6                     # > 0: success iff the KKT residual is below it
 
 
+# outer-loop resumptions after a final KKT check that misses kkt_tol (R31)
+KKT_RESUMES = 3
+
+
 def p_floor(o: "Options", alpha: float) -> float:
     """Floor of the penalty parameters p after an outer iteration."""
     if o.p_min_relative and alpha != 0.0:
@@ -538,8 +542,31 @@ class Solver:
         if st is None:
             st = self.initial()
         eps_nwt = o.eps_nwt0
+        eps_stat = o.eps_stat
+        k, resumes = 0, 0
+        while True:
+            st, eps_nwt, k = self._outer_loop(st, eps_nwt, eps_stat, k)
+            self._final(st)
+            st = self.state
+            if self.status == "kkt" and resumes < KKT_RESUMES and k < o.max_outer:
+                # the returned state misses the KKT target (the final Newton
+                # call moved the stationarity term past it): the outer loop
+                # goes on from that state with half the stationarity target
+                resumes += 1
+                eps_stat = 0.5 * eps_stat
+                self.status = "ok"
+                continue
+            return st
+
+    def _outer_loop(self, st, eps_nwt, eps_stat, k0):
+        """Outer iterations of Algorithm 1 from index k0 until its stopping
+        test (gap ratio, and this library's stationarity term below
+        eps_stat) holds; returns (state, eps_nwt, iterations so far)."""
+        P, o = self.P, self.opts
         stat_best, stat_since = 0.0, -1
-        for k in range(o.max_outer):
+        k = k0
+        while k < o.max_outer:
+            k += 1
             st, ev = self.newton(st, eps_nwt)
             if self.status == "stalled":
                 # a call before the final one that stalls is taken as the
@@ -552,13 +579,13 @@ class Solver:
             self.log.outer.append(dict(gap=delta, dual=d, ratio=ratio, eps_nwt=eps_nwt,
                                        sum_rho=float(st.rho.sum())))
             rho_n, mul_n, muh_n = update_multipliers(st, ev, o.beta)
-            stat = stationarity(P, rho_n, ev.e, st.alpha) if o.eps_stat else 0.0
+            stat = stationarity(P, rho_n, ev.e, st.alpha) if eps_stat else 0.0
             self.log.outer[-1]["stat"] = stat
             if self.progress is not None:
-                self.progress(k, self.log.outer[-1])
-            stat_ok = stat < (o.eps_stat or 1.0)
+                self.progress(k - 1, self.log.outer[-1])
+            stat_ok = stat < (eps_stat or 1.0)
             if ratio < o.eps_pbm and not stat_ok and o.stall_steps > 0 and \
-                    stat < 10.0 * (o.eps_stat or 1.0):
+                    stat < 10.0 * (eps_stat or 1.0):
                 # the stationarity test is an addition to Algorithm 1's gap test:
                 # once the gap test holds and the term, within 10x of its target,
                 # stops decreasing (no new value below 0.9 x its best for
@@ -576,6 +603,14 @@ class Solver:
             st.q_lo = np.maximum(o.gamma * st.q_lo, q_floor(o, st.alpha))
             st.q_hi = np.maximum(o.gamma * st.q_hi, q_floor(o, st.alpha))
             eps_nwt = max(min(100.0 * ratio, eps_nwt), o.eps_nwt_min)
+        self._last_ev = ev
+        return st, eps_nwt, k
+
+    def _final(self, st):
+        """The final Newton call of Algorithm 1, the last rho update and the
+        result checks; sets self.state and self.status."""
+        P, o = self.P, self.opts
+        ev = self._last_ev
         eps_final = o.eps_nwt_final if o.eps_nwt_final is not None else 10.0 * o.eps_pbm
         self.kkt = None
         if self.status == "ok":
@@ -592,4 +627,3 @@ class Solver:
         else:
             st.rho, _, _ = update_multipliers(st, ev, o.beta, rho_only=True)
         self.state = st
-        return st

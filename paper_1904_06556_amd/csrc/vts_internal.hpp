@@ -18,6 +18,7 @@ constexpr int kRedSlots = 17;          // quantities per reduction buffer
 constexpr int kMaxCoarse = 4096;       // largest dense coarsest system
 constexpr int kMaxLoads = 4;           // load cases of one problem
 constexpr int kMlMaxCoarse = 4096;     // largest dense coarsest system with several cases
+constexpr int kKktResumes = 3;         // outer-loop resumptions after a missed KKT target
 
 // Block of 27 neighbours: offset (dx,dy,dz) in {-1,0,1}^3 -> s = (dx+1) + 3(dy+1) + 9(dz+1).
 constexpr int kStencil = 27;
@@ -204,6 +205,8 @@ struct Ctx {
     int outer = 0, newton_total = 0, minres_total = 0;
     int status = VTS_OK;
     bool converged = false;
+    double eps_stat = 0;            // the outer loop's stationarity target (halved on a resumption)
+    int kkt_resumes = 0;            // resumptions after a final KKT check above kkt_tol
     double stat_best = 0;           // smallest stationarity term since the gap test first held
     int stat_since = -1;            // outer iterations since it last fell below 0.9 x best
                                     // (-1: the gap test has not held yet)
