@@ -141,8 +141,12 @@ typedef struct {
                                      the returned (rho, u, alpha) is at most this, whatever the
                                      final Newton call's own test gave; a final Newton that
                                      stalled (VTS_ENOTCONV, VTS_ENONDESCENT) then goes on to the
-                                     rho update and state solve.  <= 0: the accept_stall rule
-                                     decides.  Default 1e-6 */
+                                     rho update and state solve.  A check above kkt_tol (the
+                                     final Newton call can move the stationarity term past it)
+                                     resumes the outer loop from the returned state with half
+                                     the stationarity target, at most 3 times and within
+                                     max_outer (a "resume" line in the log).  <= 0: the
+                                     accept_stall rule decides.  Default 1e-6 */
     double eps_state;             /* > 0: after the last update of rho, vts_pbm_solve solves the
                                      state equation K(rho) u = f for the returned rho (MINRES
                                      with one V-cycle of blockdiag(K(rho), 1), stopping at this
