@@ -178,6 +178,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run paper_1904_06556_amd.build.build()")
+        # torch provides the device memory and streams the library works on:
+        # load it first, so that libvts runs on the HIP runtime torch's
+        # tensors and streams belong to
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
